@@ -1,0 +1,545 @@
+"""CPU FP64 oracle for SpAMM with error control inside SP2 purification.
+
+TEST INFRASTRUCTURE ONLY: the plain, slow, obviously-correct reference the
+GPU library is checked against.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import it; the product path
+(``paper_2005_10680_amd``) never does, and the two share no code.
+
+Heavy loops live in ``oracle.c`` (plain C, one IEEE operation per source
+operation); this module does the orchestration in numpy.  Every function
+names the part of the paper it follows.
+
+Parity status of each function (what pins it, see tests/test_oracle_*.py):
+  norms          exact rounding pinned to math.fsum of exact square splits
+  cse_tree       pinned to the worked example, eqs. (3)-(6), to the closed
+                 form at nb = 2, to brute force and to bound orderings
+  kept / spamm   pinned to brute force and to the dense product at tau = 0
+  truncate       pinned to direct recomputation of ||E||_F and maximality
+  sp2            pinned to diagonal F (exact step function) and to dense
+                 eigendecomposition on small systems
+  adjoint        pinned to finite differences and to the Frechet derivative
+                 of the step function (eigh-based) on small systems
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
+                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, d = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.o_block_sq.argtypes = [P, i64, P, P]
+        L.o_norms.argtypes = [i64, i32, P, P, P]
+        L.o_exact_sum_nonneg.argtypes = [P, i64]
+        L.o_exact_sum_nonneg.restype = d
+        L.o_cse_tree.argtypes = [i32, P, P, P, P, P, i32, i32, d, d, P]
+        L.o_cse_tree.restype = i32
+        L.o_cse_tree_leafvals.argtypes = [i32, P, P, P, P]
+        L.o_cse_tree_leafvals.restype = i32
+        L.o_cse_flat_sum.argtypes = [i32, P, P, P, P, P, i32, P, P]
+        L.o_kept_counts.argtypes = [i32, P, P, P, P, d, i32, P]
+        L.o_kept_lists.argtypes = [i32, P, P, P, P, d, i64, P, P, P, P]
+        L.o_block_products.argtypes = [i32, i32, P, P, P, P, i64, P, P, P, P, P]
+        L.o_traces.argtypes = [i64, i32, i64, P, P, P, P]
+        L.o_gerschgorin.argtypes = [i64, i32, i64, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+# Block-sparse container (the oracle's own; independent of the GPU library)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class BSM:
+    """Block-sparse matrix: blocks (brow[k], bcol[k]) with vals[k, col, row]."""
+    n: int
+    b: int
+    brow: np.ndarray
+    bcol: np.ndarray
+    vals: np.ndarray
+    _map: np.ndarray | None = field(default=None, repr=False)
+
+    @property
+    def nb(self):
+        return (self.n + self.b - 1) // self.b
+
+    @property
+    def nblk(self):
+        return int(self.brow.shape[0])
+
+    @staticmethod
+    def of(M) -> "BSM":
+        """From any object with n, b, brow, bcol, vals (e.g. synth.BlockMatrix)."""
+        return BSM(int(M.n), int(M.b), np.ascontiguousarray(M.brow, dtype=np.int32),
+                   np.ascontiguousarray(M.bcol, dtype=np.int32),
+                   np.ascontiguousarray(M.vals, dtype=np.float64))
+
+    def block_map(self) -> np.ndarray:
+        """map[r*nb + c] = index of block (r, c) or -1 (an absent quadrant)."""
+        if self._map is None:
+            m = np.full(self.nb * self.nb, -1, dtype=np.int32)
+            m[self.brow.astype(np.int64) * self.nb + self.bcol] = np.arange(self.nblk, dtype=np.int32)
+            self._map = m
+        return self._map
+
+    def to_dense(self) -> np.ndarray:
+        nb, b = self.nb, self.b
+        D = np.zeros((nb * b, nb * b))
+        for k in range(self.nblk):
+            r, c = int(self.brow[k]), int(self.bcol[k])
+            D[r * b:(r + 1) * b, c * b:(c + 1) * b] = self.vals[k].T
+        return D[: self.n, : self.n]
+
+    def keys(self) -> np.ndarray:
+        return self.brow.astype(np.int64) * self.nb + self.bcol
+
+    def subset(self, keep: np.ndarray) -> "BSM":
+        return BSM(self.n, self.b, self.brow[keep].copy(), self.bcol[keep].copy(),
+                   np.ascontiguousarray(self.vals[keep]))
+
+    def sorted(self) -> "BSM":
+        o = np.argsort(self.keys(), kind="stable")
+        return self.subset(o)
+
+
+def from_dense(D: np.ndarray, b: int) -> BSM:
+    n = D.shape[0]
+    nb = (n + b - 1) // b
+    P = np.zeros((nb * b, nb * b))
+    P[:n, :n] = D
+    T = P.reshape(nb, b, nb, b).transpose(0, 2, 3, 1)
+    present = np.any(T != 0.0, axis=(2, 3))
+    rr, cc = np.nonzero(present)
+    return BSM(n, b, rr.astype(np.int32), cc.astype(np.int32), np.ascontiguousarray(T[rr, cc]))
+
+
+# ---------------------------------------------------------------------------
+# Norms (skip test of Algorithm 2, leaf values of Algorithm 3)
+# ---------------------------------------------------------------------------
+
+def norms(X: BSM):
+    """(sq, nu): sq = RN(exact sum of squares) per block, nu = sqrt_RN(sq)."""
+    sq = np.empty(X.nblk)
+    nu = np.empty(X.nblk)
+    if X.nblk:
+        lib().o_norms(X.nblk, X.b, _p(X.vals), _p(sq), _p(nu))
+    return sq, nu
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3 (CSE) and the selection rule that follows it
+# ---------------------------------------------------------------------------
+
+def cse_tree(A: BSM, B: BSM, taus, nuA=None, nuB=None, mode=0, tau0=0.0, c_low=0.0) -> np.ndarray:
+    """Error bound of SpAMM(A, B, tau_k) for every candidate (Algorithm 3)."""
+    taus = np.ascontiguousarray(taus, dtype=np.float64)
+    if nuA is None:
+        nuA = norms(A)[1]
+    if nuB is None:
+        nuB = norms(B)[1]
+    nuA = np.ascontiguousarray(nuA, dtype=np.float64)
+    nuB = np.ascontiguousarray(nuB, dtype=np.float64)
+    out = np.zeros(taus.shape[0])
+    rc = lib().o_cse_tree(A.nb, _p(A.block_map()), _p(nuA), _p(B.block_map()), _p(nuB), _p(taus),
+                          taus.shape[0], mode, tau0, c_low, _p(out))
+    assert rc == 0
+    return out
+
+
+def cse_tree_leafvals(A: BSM, B: BSM, leafvals: np.ndarray) -> float:
+    """Algorithm 3's combination rule on explicit leaf errors
+    leafvals[i, k, j] (0 where the product is kept)."""
+    lv = np.ascontiguousarray(leafvals, dtype=np.float64)
+    assert lv.shape == (A.nb, A.nb, A.nb)
+    out = np.zeros(1)
+    rc = lib().o_cse_tree_leafvals(A.nb, _p(A.block_map()), _p(B.block_map()), _p(lv), _p(out))
+    assert rc == 0
+    return float(out[0])
+
+
+def cse_flat_sum(A: BSM, B: BSM, taus, nuA=None, nuB=None):
+    taus = np.ascontiguousarray(taus, dtype=np.float64)
+    nuA = norms(A)[1] if nuA is None else np.ascontiguousarray(nuA)
+    nuB = norms(B)[1] if nuB is None else np.ascontiguousarray(nuB)
+    flat = np.zeros(taus.shape[0])
+    ssum = np.zeros(taus.shape[0])
+    lib().o_cse_flat_sum(A.nb, _p(A.block_map()), _p(nuA), _p(B.block_map()), _p(nuB), _p(taus),
+                         taus.shape[0], _p(flat), _p(ssum))
+    return flat, ssum
+
+
+def select(bound: np.ndarray, taus: np.ndarray, budget: float):
+    """Pick the candidate whose bound is the largest one below the budget.
+    Bounds do not increase along the (decreasing) candidate list, so this is
+    the first m with bound_m < budget; none -> (N, 0.0): exact product."""
+    for m in range(len(bound)):
+        if bound[m] < budget:
+            return m, float(taus[m])
+    return len(bound), 0.0
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 (SpAMM) at the leaf level
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Kept:
+    oi: np.ndarray     # output block rows
+    oj: np.ndarray     # output block cols
+    kptr: np.ndarray   # int64 [nout+1]
+    klist: np.ndarray  # int32 kept inner block indices, ascending per output
+
+    @property
+    def npairs(self):
+        return int(self.kptr[-1])
+
+
+def kept(A: BSM, B: BSM, tau: float, sym: bool, nuA=None, nuB=None) -> Kept:
+    """Kept triples {(i,k,j): RN(nu(A_ik) nu(B_kj)) >= tau}; outputs in
+    row-major order, restricted to i <= j when sym."""
+    nuA = norms(A)[1] if nuA is None else np.ascontiguousarray(nuA)
+    nuB = norms(B)[1] if nuB is None else np.ascontiguousarray(nuB)
+    nb = A.nb
+    counts = np.zeros(nb * nb, dtype=np.int32)
+    L = lib()
+    L.o_kept_counts(nb, _p(A.block_map()), _p(nuA), _p(B.block_map()), _p(nuB), float(tau), int(sym),
+                    _p(counts))
+    nz = np.nonzero(counts)[0]
+    oi = (nz // nb).astype(np.int32)
+    oj = (nz % nb).astype(np.int32)
+    kptr = np.zeros(nz.shape[0] + 1, dtype=np.int64)
+    np.cumsum(counts[nz], out=kptr[1:])
+    klist = np.zeros(int(kptr[-1]), dtype=np.int32)
+    if nz.shape[0]:
+        L.o_kept_lists(nb, _p(A.block_map()), _p(nuA), _p(B.block_map()), _p(nuB), float(tau),
+                       nz.shape[0], _p(oi), _p(oj), _p(kptr), _p(klist))
+    return Kept(oi, oj, kptr, klist)
+
+
+def block_products(A: BSM, B: BSM, K: Kept, sel=None) -> np.ndarray:
+    """Values of the output blocks of K (or of the outputs listed in sel):
+    C_ij = sum over kept k ascending of the textbook product A_ik B_kj."""
+    if sel is None:
+        oi, oj, kptr, klist = K.oi, K.oj, K.kptr, K.klist
+    else:
+        sel = np.asarray(sel, dtype=np.int64)
+        oi, oj = K.oi[sel], K.oj[sel]
+        lens = K.kptr[sel + 1] - K.kptr[sel]
+        kptr = np.zeros(sel.shape[0] + 1, dtype=np.int64)
+        np.cumsum(lens, out=kptr[1:])
+        klist = np.concatenate([K.klist[K.kptr[s]:K.kptr[s + 1]] for s in sel]) if sel.shape[0] else \
+            np.zeros(0, dtype=np.int32)
+        klist = np.ascontiguousarray(klist, dtype=np.int32)
+        oi = np.ascontiguousarray(oi); oj = np.ascontiguousarray(oj)
+    b = A.b
+    out = np.zeros((oi.shape[0], b, b))
+    if oi.shape[0]:
+        lib().o_block_products(b, A.nb, _p(A.block_map()), _p(A.vals), _p(B.block_map()), _p(B.vals),
+                               oi.shape[0], _p(oi), _p(oj), _p(kptr), _p(klist), _p(out))
+    return out
+
+
+def spamm(A: BSM, B: BSM, tau: float, sym: bool = False, nuA=None, nuB=None):
+    """C~ = SpAMM(A, B, tau) (Algorithm 2) on the pattern of the kept
+    outputs.  sym: A = B = X symmetric, compute i <= j and mirror
+    C~_ji = C~_ij^T.  Returns (C~, Kept)."""
+    K = kept(A, B, tau, sym, nuA, nuB)
+    V = block_products(A, B, K)
+    if sym:
+        off = K.oi != K.oj
+        brow = np.concatenate([K.oi, K.oj[off]])
+        bcol = np.concatenate([K.oj, K.oi[off]])
+        vals = np.concatenate([V, V[off].transpose(0, 2, 1)])
+    else:
+        brow, bcol, vals = K.oi, K.oj, V
+    C = BSM(A.n, A.b, brow.astype(np.int32), bcol.astype(np.int32), np.ascontiguousarray(vals)).sorted()
+    return C, K
+
+
+# ---------------------------------------------------------------------------
+# Truncation, ||E||_F < delta (Algorithm 1/5 truncation lines)
+# ---------------------------------------------------------------------------
+
+KEY_BITS = 40  # quantum Q = 2^(e_T - KEY_BITS), T = RN(delta^2) in [2^e_T, 2^(e_T+1))
+KSAT = 1 << 41
+
+
+@dataclass
+class TruncInfo:
+    removed_keys: np.ndarray   # upper-block keys r*nb+c (r <= c) of removed units
+    removed_fro2: float        # sum of w*sq over removed units (double)
+    kt: int                    # integer budget K_T
+    ksum: int                  # integer sum of removed keys
+
+
+def trunc_quanta(delta: float):
+    """(T, Q, K_T) of the truncation rule for budget delta."""
+    T = delta * delta
+    if not (T > 0.0 and math.isfinite(T)):
+        return T, 0.0, 0
+    e_T = math.frexp(T)[1] - 1
+    Q = math.ldexp(1.0, max(e_T - KEY_BITS, -1000))
+    tq = int(math.floor(T / Q))
+    kt = tq - ((tq + (1 << 29) - 1) >> 29)
+    return T, Q, kt
+
+
+def trunc_keys(sq_upper: np.ndarray, w: np.ndarray, Q: float) -> np.ndarray:
+    """k_u = ceil(w*sq/Q), saturated at 2^41 (exact integers)."""
+    v = w * sq_upper
+    with np.errstate(over="ignore", invalid="ignore"):
+        s = v / Q
+    k = np.where(s < float(KSAT), np.ceil(np.where(s < float(KSAT), s, 0.0)), float(KSAT))
+    return k.astype(np.uint64)
+
+
+def truncate(X: BSM, delta: float, sq=None):
+    """Remove whole symmetric units (diagonal blocks; off-diagonal pairs) in
+    ascending order of their quantised squared norm, ties by coordinates,
+    as long as the removed squared Frobenius norm provably stays below
+    delta^2.  Returns (X~, TruncInfo)."""
+    if sq is None:
+        sq = norms(X)[0]
+    nb = X.nb
+    up = X.brow <= X.bcol
+    ukeys = X.keys()[up]
+    sq_up = sq[up]
+    w = np.where(X.brow[up] == X.bcol[up], 1.0, 2.0)
+    T, Q, kt = trunc_quanta(delta)
+    if kt <= 0:
+        return X, TruncInfo(np.zeros(0, dtype=np.int64), 0.0, kt, 0)
+    k = trunc_keys(sq_up, w, Q)
+    order = np.lexsort((ukeys, k))
+    csum = np.cumsum(k[order], dtype=np.uint64)  # exact: < 2^22 units * 2^41
+    q = int(np.searchsorted(csum, np.uint64(kt), side="left"))  # first index with csum >= kt
+    removed = ukeys[order[:q]]
+    ksum = int(csum[q - 1]) if q else 0
+    fro2 = float(np.sum((w * sq_up)[order[:q]])) if q else 0.0
+    rem_r, rem_c = removed // nb, removed % nb
+    drop = np.zeros(nb * nb, dtype=bool)
+    drop[removed] = True
+    drop[rem_c * nb + rem_r] = True
+    keep = ~drop[X.keys()]
+    return X.subset(keep), TruncInfo(np.sort(removed), fro2, kt, ksum)
+
+
+# ---------------------------------------------------------------------------
+# Purification pieces: starting matrix, traces, SP2 (Algorithms 1, 4, 5)
+# ---------------------------------------------------------------------------
+
+def gerschgorin(F: BSM):
+    out = np.zeros(2)
+    lib().o_gerschgorin(F.nblk, F.b, F.n, _p(F.brow), _p(F.bcol), _p(F.vals), _p(out))
+    return float(out[0]), float(out[1])
+
+
+def x0(F: BSM, lmin: float, lmax: float) -> BSM:
+    """X_0 = (lmax I - F) / (lmax - lmin): the linear map of F sending its
+    spectrum into [0, 1], occupied states near 1 (the starting matrix of the
+    purification algorithms).  Entry-wise, with W = RN(lmax - lmin):
+    diagonal x = RN(RN(lmax - f) / W), off-diagonal x = RN(-f / W); padding
+    past n is +0.  Every diagonal block is present."""
+    nb, b, n = F.nb, F.b, F.n
+    W = lmax - lmin
+    M = F.block_map()
+    dmiss = [d for d in range(nb) if M[d * nb + d] < 0]
+    brow = np.concatenate([F.brow, np.array(dmiss, dtype=np.int32)])
+    bcol = np.concatenate([F.bcol, np.array(dmiss, dtype=np.int32)])
+    vals = np.concatenate([F.vals, np.zeros((len(dmiss), b, b))])
+    ar = np.arange(b)
+    gi = brow[:, None, None].astype(np.int64) * b + ar[None, None, :]   # row of vals[k, col, row]
+    gj = bcol[:, None, None].astype(np.int64) * b + ar[None, :, None]   # col
+    on_diag = gi == gj
+    out = np.where(on_diag, (lmax - vals) / W, (-vals) / W)
+    out = np.where((gi < n) & (gj < n), out, 0.0)
+    return BSM(n, b, brow, bcol, np.ascontiguousarray(out)).sorted()
+
+
+def traces(X: BSM):
+    """(t1, t2, e) = RN(tr X), RN(||X||_F^2), RN(tr X - ||X||_F^2), exact sums."""
+    out = np.zeros(3)
+    lib().o_traces(X.nblk, X.b, X.n, _p(X.brow), _p(X.bcol), _p(X.vals), _p(out))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def combine(X: BSM, C: BSM, branch: int) -> BSM:
+    """X^ = C (branch 0, f(x) = x^2) or RN(RN(2x) - c) (branch 1, f(x) = 2x - x^2)
+    on the union pattern."""
+    if branch == 0:
+        return C
+    nb = X.nb
+    keys = np.union1d(X.keys(), C.keys())
+    b = X.b
+    vals = np.zeros((keys.shape[0], b, b))
+    xm = {int(k): i for i, k in enumerate(X.keys())}
+    cm = {int(k): i for i, k in enumerate(C.keys())}
+    for t, kk in enumerate(keys):
+        kk = int(kk)
+        xv = 2.0 * X.vals[xm[kk]] if kk in xm else np.zeros((b, b))
+        if kk in cm:
+            xv = xv - C.vals[cm[kk]]
+        vals[t] = xv
+    return BSM(X.n, b, (keys // nb).astype(np.int32), (keys % nb).astype(np.int32), vals)
+
+
+@dataclass
+class SP2Params:
+    n_occ: int
+    eps: float = 1e-6
+    taus: np.ndarray | None = None
+    homo: float = float("nan")    # highest occupied eigenvalue of F (or an upper bound)
+    lumo: float = float("nan")    # lowest unoccupied eigenvalue of F (or a lower bound)
+    n_max: int = 60
+    variant: str = "hybrid"       # "hybrid" (Alg. 5), "spamm" (Alg. 4), "truncmul" (Alg. 1)
+    delta_const: float = float("nan")  # explicit per-step delta when no gap is given
+    e_tol: float = 0.0
+
+
+@dataclass
+class SP2State:
+    """Everything step i needs besides X~_{i-1}."""
+    i: int
+    xh: float
+    xl: float
+    e_hist: list
+
+
+def step_delta(p: SP2Params, gap: float) -> float:
+    """delta_i = eps * g_i / (4 n_max), g_i the mapped gap of X_i (reading of
+    the refs the paper cites for the tolerance schedule), or the constant."""
+    if math.isfinite(p.delta_const):
+        return p.delta_const
+    return p.eps * gap / (4.0 * p.n_max)
+
+
+def choose_branch(t1: float, t2: float, n_occ: int) -> int:
+    """SP2 polynomial for this step: 0 -> x^2, 1 -> 2x - x^2, whichever
+    trace lands closer to the occupation (ties -> x^2)."""
+    return 0 if abs(t2 - n_occ) <= abs((2.0 * t1 - t2) - n_occ) else 1
+
+
+def map_gap(x: float, branch: int) -> float:
+    return x * x if branch == 0 else 2.0 * x - x * x
+
+
+def should_stop(e_hist: list, e_tol: float) -> bool:
+    """Stop when |e| <= e_tol, or once two further steps failed to reduce |e|
+    after it fell below 1e-3 (rounding/truncation noise floor)."""
+    if not e_hist:
+        return False
+    if abs(e_hist[-1]) <= e_tol:
+        return True
+    if len(e_hist) >= 3 and abs(e_hist[-3]) < 1e-3 and abs(e_hist[-1]) >= abs(e_hist[-3]):
+        return True
+    return False
+
+
+@dataclass
+class StepLog:
+    i: int
+    branch: int
+    delta: float
+    bound: np.ndarray
+    idx: int
+    tau: float
+    npairs: int
+    nout: int
+    trunc: TruncInfo | None
+    t1: float
+    t2: float
+    e: float
+
+
+def sp2_step(X: BSM, st: SP2State, p: SP2Params):
+    """One iteration of Algorithm 5 (hybrid) / 4 (spamm) / 1 (truncmul) on
+    X~_{i-1} = X.  Returns (X~_i, Xhat_i, StepLog, new state) or
+    (None, None, log, state) when the stop rule fires before the step."""
+    t1, t2, e = traces(X)
+    e_hist = st.e_hist + [e]
+    if should_stop(e_hist, p.e_tol) or st.i > p.n_max:
+        return None, None, StepLog(st.i, -1, 0.0, np.zeros(0), -1, 0.0, 0, 0, None, t1, t2, e), \
+            SP2State(st.i, st.xh, st.xl, e_hist)
+    br = choose_branch(t1, t2, p.n_occ)
+    xh, xl = map_gap(st.xh, br), map_gap(st.xl, br)
+    delta = step_delta(p, xh - xl)
+    taus = np.asarray(p.taus, dtype=np.float64)
+    nu = norms(X)[1]
+    if p.variant == "truncmul":
+        bound, idx, tau = np.zeros(len(taus)), len(taus), 0.0
+    else:
+        budget = delta / 2.0 if p.variant == "hybrid" else delta
+        bound = cse_tree(X, X, taus, nu, nu)
+        idx, tau = select(bound, taus, budget)
+    C, K = spamm(X, X, tau, sym=True, nuA=nu, nuB=nu)
+    Xh = combine(X, C, br)
+    if p.variant == "spamm":
+        Xt, ti = Xh.sorted(), None
+    else:
+        tb = delta / 2.0 if p.variant == "hybrid" else delta
+        Xt, ti = truncate(Xh.sorted(), tb)
+    log = StepLog(st.i, br, delta, bound, idx, tau, K.npairs, int(K.oi.shape[0]), ti, t1, t2, e)
+    return Xt, Xh, log, SP2State(st.i + 1, xh, xl, e_hist)
+
+
+def sp2_start(F: BSM, p: SP2Params):
+    """X~_0 from F: Gerschgorin map (reading of 'a linear transformation'),
+    then the first truncation with delta_0."""
+    lmin, lmax = gerschgorin(F)
+    X0 = x0(F, lmin, lmax)
+    W = lmax - lmin
+    xh = (lmax - p.homo) / W
+    xl = (lmax - p.lumo) / W
+    d0 = step_delta(p, xh - xl)
+    if p.variant == "spamm":
+        Xt, ti = X0, None
+    else:
+        Xt, ti = truncate(X0, d0)
+    return Xt, X0, SP2State(1, xh, xl, []), (lmin, lmax, d0, ti)
+
+
+def sp2(F: BSM, p: SP2Params, keep_tape: bool = False):
+    """Full purification.  Returns (D~, logs, info)."""
+    X, X0, st, info = sp2_start(F, p)
+    logs = []
+    tape = [X] if keep_tape else None
+    while True:
+        Xn, _, log, st = sp2_step(X, st, p)
+        logs.append(log)
+        if Xn is None:
+            break
+        X = Xn
+        if keep_tape:
+            tape.append(X)
+    return X, logs, {"lmin": info[0], "lmax": info[1], "delta0": info[2], "tape": tape,
+                     "converged": logs[-1].branch == -1 and st.i <= p.n_max}

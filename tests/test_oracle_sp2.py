@@ -1,0 +1,106 @@
+"""Pins of the oracle's purification (Algorithms 1, 4 and 5 with SP2
+polynomials):
+
+* diagonal F -> the exact step function, tr(D) = N_occ exactly;
+* chain and 3D systems -> ||D~ - D||_F < eps against dense eigh;
+* zero tolerances reproduce plain dense SP2;
+* per step: ||X^_i - f_i(X~_{i-1})||_F < delta_i/2 and ||E_i||_F < delta_i/2
+  (the two conditions of Algorithm 5), delta_i for Algorithms 1 and 4."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def eigh_density(F, n_occ):
+    w, U = np.linalg.eigh(F.to_dense())
+    return U[:, :n_occ] @ U[:, :n_occ].T, w
+
+
+def test_diagonal_f_exact_step():
+    n, b = 96, 8
+    rng = np.random.default_rng(0)
+    f = rng.uniform(-2.0, 2.0, n)
+    f[np.abs(f) < 0.3] += 0.6                                 # keep away from mu = 0
+    n_occ = int(np.sum(f < 0.0))
+    F = oracle.from_dense(np.diag(f), b)
+    fs = np.sort(f)
+    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=synth.tau_paper(), homo=fs[n_occ - 1], lumo=fs[n_occ])
+    D, logs, info = oracle.sp2(F, p)
+    Dd = D.to_dense()
+    want = np.diag((f < 0.0).astype(np.float64))
+    assert np.array_equal(Dd, want)
+    assert np.trace(Dd) == n_occ
+
+
+def test_chain_vs_eigh():
+    Fm = synth.chain1d(1024, 1, 32)
+    F = oracle.BSM.of(Fm)
+    Dref, w = eigh_density(F, 512)
+    p = oracle.SP2Params(n_occ=512, eps=1e-6, taus=synth.tau_paper(), homo=w[511], lumo=w[512])
+    D, logs, info = oracle.sp2(F, p)
+    assert np.linalg.norm(D.to_dense() - Dref) < 1e-6
+    assert 5 <= len(logs) <= 40
+
+
+def test_sys3d_vs_eigh_and_step_conditions():
+    n, b = 768, 32
+    F = oracle.BSM.of(synth.sys3d(n, 7, b))
+    n_occ = n // 2
+    Dref, w = eigh_density(F, n_occ)
+    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=synth.tau_log(32), homo=w[n_occ - 1], lumo=w[n_occ])
+    X, X0, st, _ = oracle.sp2_start(F, p)
+    checked = 0
+    while True:
+        Xn, Xh, log, st = oracle.sp2_step(X, st, p)
+        if Xn is None:
+            break
+        Xd = X.to_dense()
+        f = Xd @ Xd if log.branch == 0 else 2 * Xd - Xd @ Xd
+        assert np.linalg.norm(Xh.to_dense() - f) < log.delta / 2       # SpAMM error
+        assert np.linalg.norm(Xn.to_dense() - Xh.to_dense()) < log.delta / 2  # truncation
+        X = Xn
+        checked += 1
+    assert checked >= 10
+    assert np.linalg.norm(X.to_dense() - Dref) < 1e-6
+
+
+def test_zero_tolerance_is_dense_sp2():
+    Fm = synth.chain1d(256, 3, 32)
+    F = oracle.BSM.of(Fm)
+    _, w = eigh_density(F, 128)
+    p = oracle.SP2Params(n_occ=128, eps=1e-6, taus=synth.tau_paper(), homo=w[127], lumo=w[128],
+                         delta_const=0.0, n_max=25)
+    D, logs, info = oracle.sp2(F, p)
+    assert all(l.tau == 0.0 for l in logs if l.branch >= 0)
+    # plain dense SP2 with the same branch sequence
+    lmin, lmax = info["lmin"], info["lmax"]
+    X = (lmax * np.eye(F.n) - F.to_dense()) / (lmax - lmin)
+    for l in logs:
+        if l.branch < 0:
+            break
+        X = X @ X if l.branch == 0 else 2 * X - X @ X
+    assert np.linalg.norm(D.to_dense() - X) <= 1e-12 * np.linalg.norm(X)
+
+
+@pytest.mark.parametrize("variant", ["spamm", "truncmul"])
+def test_other_variants_step_conditions(variant):
+    n, b = 512, 32
+    F = oracle.BSM.of(synth.sys3d(n, 8, b))
+    n_occ = n // 2
+    Dref, w = eigh_density(F, n_occ)
+    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=synth.tau_log(32), homo=w[n_occ - 1],
+                         lumo=w[n_occ], variant=variant)
+    X, X0, st, _ = oracle.sp2_start(F, p)
+    while True:
+        Xn, Xh, log, st = oracle.sp2_step(X, st, p)
+        if Xn is None:
+            break
+        Xd = X.to_dense()
+        f = Xd @ Xd if log.branch == 0 else 2 * Xd - Xd @ Xd
+        assert np.linalg.norm(Xn.to_dense() - f) < log.delta            # whole step error
+        if variant == "truncmul":
+            assert log.tau == 0.0
+        X = Xn
+    assert np.linalg.norm(X.to_dense() - Dref) < 1e-6
