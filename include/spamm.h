@@ -1,0 +1,198 @@
+/*
+ * spamm.h - C ABI of the MI355X (gfx950) library for sparse approximate
+ * matrix-matrix multiplication with error control, driven inside SP2
+ * density-matrix purification (Artemov & Rubensson, "Sparse approximate
+ * matrix-matrix multiplication for density matrix purification with error
+ * control").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every pointer marked "device" is HIP device memory owned by the caller.
+ *   The library never allocates, frees or retains caller memory; scratch
+ *   space is the caller's workspace (ws, ws_bytes), sized with the matching
+ *   *_workspace_bytes query.
+ * - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *   the call returns before it finishes, except where a function says it
+ *   reads results back to the host (it then synchronises `stream`).
+ * - Return value: SPAMM_OK (0) on success, a negative SPAMM_E* code on
+ *   error (nothing was enqueued, or the device results are invalid), or a
+ *   positive SPAMM_W* warning (results valid).  spamm_last_error() returns
+ *   a message for the last non-zero code of the calling thread.  No C++
+ *   exception crosses this boundary.
+ *
+ * Block-sparse matrix (spamm_bsm)
+ * -------------------------------
+ * The quadtree of eq. (2) is stored linearised at the leaf level: an n x n
+ * matrix with leaf size b has nb = ceil(n/b) block rows; each present leaf
+ * block occupies one "slot" holding b*b doubles, column-major inside the
+ * block (element (r, c) at offset c*b + r).  Rows/columns past n are zero
+ * padding.  Absent blocks are identically zero quadrants.  A slot whose
+ * brow is -1 is a hole (a block that was removed); every kernel skips it.
+ */
+#ifndef SPAMM_H
+#define SPAMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SPAMM_OK 0
+#define SPAMM_EINVAL (-1)     /* bad argument (message says which) */
+#define SPAMM_ECAPACITY (-2)  /* an output capacity was too small */
+#define SPAMM_EWORKSPACE (-3) /* workspace smaller than the query said */
+#define SPAMM_EHIP (-4)       /* a HIP runtime call failed */
+#define SPAMM_ENOTSUP (-5)    /* combination not supported */
+#define SPAMM_WNOCONV 1       /* purification hit n_max before the stop rule */
+#define SPAMM_WTAUFALLBACK 2  /* no candidate met the budget: tau = 0 (exact) */
+
+/* flags */
+#define SPAMM_SYMMETRIC 1u   /* A = B = X symmetric: outputs i <= j, C_ji = C_ij^T */
+#define SPAMM_B_TRANSPOSED 2u /* B is given as its transpose Bt (Bt_jk = B_kj^T) */
+#define SPAMM_SYNC 4u        /* synchronise the stream before returning */
+
+typedef void* spamm_stream_t; /* hipStream_t */
+
+typedef struct spamm_bsm {
+    int64_t n;       /* matrix order */
+    int32_t b;       /* leaf size: 32, 64 or 128 */
+    int32_t nb;      /* ceil(n / b) */
+    int64_t cap;     /* capacity in slots of brow/bcol/val/norm/sq/sqlo */
+    int32_t* nslot;  /* device [1]: slots in use (slots 0..nslot-1) */
+    int32_t* brow;   /* device [cap]: block row of each slot, -1 = hole */
+    int32_t* bcol;   /* device [cap]: block column of each slot */
+    int32_t* map;    /* device [nb*nb]: slot of block (r, c) or -1 */
+    double* val;     /* device [cap*b*b]: block values, column-major */
+    double* norm;    /* device [cap]: Frobenius norm nu of each slot */
+    double* sq;      /* device [cap]: RN(exact sum of squares) of each slot */
+    double* sqlo;    /* device [cap]: sum of squares minus sq (double-double tail) */
+} spamm_bsm;
+
+/*
+ * Block norms (the ||A||_F of the skip test of Algorithm 2 and the leaf
+ * values of Algorithm 3).
+ * For every live slot: sq = RN(sum of x^2) rounded once from the exact sum,
+ * norm = correctly rounded sqrt(sq), sqlo = the double-double tail of the
+ * sum (for traces).  Deterministic and independent of element order.
+ * X: in/out (val read; norm, sq, sqlo written).  No workspace.
+ */
+int spamm_build_norms(spamm_bsm* X, spamm_stream_t stream);
+
+/*
+ * Error-bound sweep over candidate thresholds (Algorithm 3, CSE) followed by
+ * the selection rule (the candidate whose bound is the largest one below
+ * the budget).
+ *   A, B      : inputs with norms built; B transposed when SPAMM_B_TRANSPOSED.
+ *   tau       : device [N], strictly decreasing, > 0, 1 <= N <= 1024.
+ *   budget    : device [1] (the product error budget delta), or NULL to use
+ *               budget_host.
+ *   mode      : 0 = the paper's leaf errors; 1 = precision tiers (tau is the
+ *               list of low-precision limits sigma, tau0_dev[0] the fixed skip
+ *               threshold, c_low the per-pair rounding factor of the low tier).
+ *   bound_out : device [N] bound of ||SpAMM(A,B,tau_k) - AB||_F per candidate.
+ *   idx_out   : device [1] selected index (N when none qualifies).
+ *   tau_out   : device [1] selected threshold (0 when none qualifies).
+ * Workspace: spamm_sweep_workspace_bytes(nb, N).
+ */
+size_t spamm_sweep_workspace_bytes(int32_t nb, int32_t N);
+int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, int32_t N,
+                    const double* budget, double budget_host, int32_t mode, const double* tau0_dev,
+                    double c_low, uint32_t flags, double* bound_out, int32_t* idx_out, double* tau_out,
+                    void* ws, size_t ws_bytes, spamm_stream_t stream);
+
+/*
+ * SpAMM product at threshold tau (Algorithm 2 with the skip test applied to
+ * leaf pairs; identical kept set to the recursive form because a leaf norm
+ * never exceeds its ancestors').
+ *   C~_ij = sum over k ascending with RN(nu(A_ik) nu(B_kj)) >= tau of A_ik B_kj
+ * on the output pattern {(i,j): some kept k}; SPAMM_SYMMETRIC computes i <= j
+ * and writes C_ji = C_ij^T.  tau_dev: device [1]; tau = 0 keeps every present
+ * pair (the exact product).  C: output with its own capacity; its map is
+ * rewritten, nslot set.  kept_out: device [2] = {kept pairs executed, output
+ * blocks}; may be NULL.  SPAMM_ECAPACITY when C->cap or the workspace pair
+ * capacity is too small (C->nslot then holds the required slot count).
+ * Workspace: spamm_multiply_workspace_bytes(nb, max_pairs).
+ */
+size_t spamm_multiply_workspace_bytes(int32_t nb, int64_t max_pairs);
+int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev, uint32_t flags,
+                   spamm_bsm* C, int64_t* kept_out, void* ws, size_t ws_bytes, spamm_stream_t stream);
+
+/*
+ * Truncation ||E||_F < delta (the truncation lines of Algorithms 1 and 5),
+ * in place on a symmetric matrix with norms built.  Units are diagonal
+ * blocks and symmetric off-diagonal pairs; with T = RN(delta^2) and
+ * Q = 2^(floor(log2 T) - 40), each unit gets the integer key
+ * k = ceil(w*sq/Q) (w = 1 diagonal, 2 pair; saturated at 2^41).  Units are
+ * taken in ascending (k, r*nb + c) order and the longest prefix whose key
+ * sum stays below K_T = floor(T/Q) - ceil(floor(T/Q)/2^29) is removed,
+ * which guarantees the exact removed Frobenius norm is < delta.
+ * Removed slots become holes.  removed_out: device [2] = {removed units,
+ * removed sum of w*sq}; may be NULL.
+ * Workspace: spamm_truncate_workspace_bytes(cap).
+ */
+size_t spamm_truncate_workspace_bytes(int64_t cap);
+int spamm_truncate(spamm_bsm* X, double delta, uint32_t flags, double* removed_out, void* ws,
+                   size_t ws_bytes, spamm_stream_t stream);
+
+/* Parameters of purify_sp2 (Algorithms 1, 4 and 5 with SP2 polynomials). */
+typedef struct sp2_params {
+    int64_t n_occ;       /* occupied count: the trace the iteration converges to */
+    double eps;          /* target ||D - D~||_F */
+    int32_t n_max;       /* iteration limit (SPAMM_WNOCONV when reached) */
+    int32_t variant;     /* 0 hybrid (Alg. 5), 1 SpAMM only (Alg. 4), 2 truncmul (Alg. 1) */
+    const double* tau;   /* device [N] candidate thresholds (see spamm_sweep_tau) */
+    int32_t N;
+    double homo, lumo;   /* eigenvalue bounds of F around the gap (homo < lumo), or NaN */
+    double delta_const;  /* explicit per-step delta when homo/lumo are NaN (else NaN) */
+    double e_tol;        /* stop when |tr X - ||X||_F^2| <= e_tol (0: noise-floor rule only) */
+    int32_t keep_tape;   /* nonzero: keep every X~_i in the workspace (adjoint, inspection) */
+    int32_t reserved;
+} sp2_params;
+
+/* Per-iteration record written by purify_sp2 (host memory). */
+typedef struct sp2_iter_log {
+    int32_t i, branch, idx, stop; /* branch 0: x^2, 1: 2x - x^2; stop != 0 on the final record */
+    double delta, tau, t1, t2, e;
+    int64_t npairs, nout, nslot_hat, nslot_kept, removed_units;
+    double removed_fro2;
+    float ms_sweep, ms_pairs, ms_gemm, ms_norms, ms_trunc, ms_total;
+} sp2_iter_log;
+
+/*
+ * Purification: X_0 = (lmax I - F)/(lmax - lmin) with Gerschgorin bounds,
+ * X~_0 truncated with delta_0, then X~_i = trunc(SpAMM-evaluated f_i(X~_{i-1}))
+ * with f_i = x^2 or 2x - x^2 (the trace closer to n_occ), the SpAMM
+ * threshold chosen by the sweep with budget delta_i/2 and the truncation
+ * with delta_i/2 (Algorithm 5), delta_i = eps*g_i/(4*n_max) from the
+ * mapped gap g_i, until the stop rule fires.
+ *   F     : symmetric input with norms NOT required (computed internally).
+ *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise).
+ *   log   : host [n_max + 2] records; nlog_out: records written.
+ * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, keep_tape ? n_max : 0).
+ * Reads scalars back every iteration (synchronises the stream).
+ */
+size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
+                                  int32_t tape_steps);
+int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out,
+               void* ws, size_t ws_bytes, spamm_stream_t stream);
+
+/*
+ * View of tape entry `step` (X~_step, 0 <= step <= tape_steps) inside a
+ * purify_sp2 workspace that was run with keep_tape: fills *out with device
+ * pointers into ws (no copy).  Arguments must equal those of the
+ * purify_sp2_workspace_bytes query the workspace was sized with.
+ */
+int purify_sp2_tape_view(void* ws, int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
+                         int32_t tape_steps, int32_t step, spamm_bsm* out);
+
+const char* spamm_status_str(int code);
+const char* spamm_last_error(void);
+int spamm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAMM_H */

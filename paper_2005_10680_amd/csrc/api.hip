@@ -1,0 +1,730 @@
+// C ABI of the library (include/spamm.h): argument validation, workspace
+// carving and the purification driver.  Kernels live in the other .hip files.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/spamm.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace spamm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) return fail(SPAMM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int ceil_log2(int x) {
+    int L = 0;
+    while ((1 << L) < x) ++L;
+    return L;
+}
+
+int num_cus() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cached = p.multiProcessorCount;
+        else cached = 256;
+    }
+    return cached;
+}
+
+int check_bsm(const spamm_bsm* X, const char* name, bool need_norms) {
+    if (!X) return fail(SPAMM_EINVAL, "%s is NULL", name);
+    if (X->n <= 0) return fail(SPAMM_EINVAL, "%s: n must be positive", name);
+    if (X->b != 32 && X->b != 64 && X->b != 128) return fail(SPAMM_EINVAL, "%s: leaf size must be 32, 64 or 128", name);
+    if ((int64_t)X->nb != (X->n + X->b - 1) / X->b) return fail(SPAMM_EINVAL, "%s: nb != ceil(n/b)", name);
+    if (X->nb > 2048) return fail(SPAMM_EINVAL, "%s: nb > 2048 is not supported", name);
+    if (X->cap < 0) return fail(SPAMM_EINVAL, "%s: negative capacity", name);
+    if (!X->nslot || !X->brow || !X->bcol || !X->map || !X->val)
+        return fail(SPAMM_EINVAL, "%s: NULL array", name);
+    if (need_norms && (!X->norm || !X->sq || !X->sqlo)) return fail(SPAMM_EINVAL, "%s: NULL norm arrays", name);
+    return SPAMM_OK;
+}
+
+MatView view(const spamm_bsm* X) {
+    MatView v;
+    v.n = X->n;
+    v.b = X->b;
+    v.nb = X->nb;
+    v.cap = X->cap;
+    v.nslot = X->nslot;
+    v.brow = X->brow;
+    v.bcol = X->bcol;
+    v.map = X->map;
+    v.val = X->val;
+    v.norm = X->norm;
+    v.sq = X->sq;
+    v.sqlo = X->sqlo;
+    return v;
+}
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// sweep workspace
+// ---------------------------------------------------------------------------
+struct SweepWs {
+    int nb, L, l0, T;
+    int64_t ncap;
+    uint8_t *tA, *tB;
+    int32_t *flag, *idx, *lflag, *lpos, *pstart;
+    uint32_t* keys[2];
+    double* vals[2];
+    int64_t* cnt;  // [4]
+    int32_t* ovf;
+    void* scan_tmp;
+};
+
+void carve_sweep(Carver& c, int nb, int N, SweepWs& w) {
+    w.nb = nb;
+    w.L = ceil_log2(nb);
+    w.l0 = cse_level0(nb);
+    w.T = 1 << (w.L - w.l0);
+    w.ncap = (int64_t)w.T * w.T * w.T;
+    w.tA = c.take<uint8_t>((size_t)w.T * w.T);
+    w.tB = c.take<uint8_t>((size_t)w.T * w.T);
+    w.flag = c.take<int32_t>(w.ncap);
+    w.idx = c.take<int32_t>(w.ncap);
+    w.lflag = c.take<int32_t>(w.ncap);
+    w.lpos = c.take<int32_t>(w.ncap);
+    w.pstart = c.take<int32_t>(w.ncap + 1);
+    w.keys[0] = c.take<uint32_t>(w.ncap);
+    w.keys[1] = c.take<uint32_t>(w.ncap);
+    w.vals[0] = c.take<double>((size_t)w.ncap * N);
+    w.vals[1] = c.take<double>((size_t)w.ncap * N);
+    w.cnt = c.take<int64_t>(4);
+    w.ovf = c.take<int32_t>(4);
+    w.scan_tmp = c.take<char>(scan_temp_bytes(w.ncap));
+}
+
+void run_sweep(const MatView& A, const MatView& B, int btrans, const double* tau, int N, const double* budget_dev,
+               double budget_host, int mode, const double* tau0, double c_low, double* bound_out, int32_t* idx_out,
+               double* tau_out, SweepWs& w, const int32_t* done, hipStream_t s) {
+    const int T = w.T;
+    fill_u8(w.tA, (int64_t)T * T, 0, s);
+    fill_u8(w.tB, (int64_t)T * T, 0, s);
+    launch_occupancy(A, kOccA, nullptr, 0, w.tA, T, w.l0, done, s);
+    launch_occupancy(B, btrans ? kOccBt : kOccB, nullptr, 0, w.tB, T, w.l0, done, s);
+    launch_cube_flags(T, w.tA, w.tB, w.flag, done, s);
+    scan_i32(w.flag, w.idx, w.ncap, nullptr, &w.cnt[0], w.scan_tmp, s);
+    launch_cube_list(T, w.flag, w.idx, w.keys[0], &w.cnt[0], w.ncap, w.ovf, done, s);
+    launch_cube_eval(mode, w.l0, A.nb, w.keys[0], &w.cnt[0], w.ncap, A.map, A.norm, B.map, B.norm, btrans, tau, N,
+                     tau0, c_low, w.vals[0], done, s);
+    int cur = 0;
+    for (int lev = w.l0 + 1; lev <= w.L; ++lev) {
+        int64_t* nc = &w.cnt[cur];
+        int64_t* np = &w.cnt[1 - cur];
+        launch_level_flags(w.keys[cur], nc, w.ncap, w.lflag, done, s);
+        scan_i32(w.lflag, w.lpos, w.ncap, nc, np, w.scan_tmp, s);
+        launch_level_build(w.keys[cur], nc, w.ncap, w.lflag, w.lpos, np, w.keys[1 - cur], w.pstart, done, s);
+        launch_level_eval(w.keys[cur], w.vals[cur], w.pstart, np, w.ncap, N, w.vals[1 - cur], done, s);
+        cur = 1 - cur;
+    }
+    launch_select(w.vals[cur], &w.cnt[cur], tau, N, budget_dev, budget_host, bound_out, idx_out, tau_out, done, s);
+}
+
+// ---------------------------------------------------------------------------
+// multiply workspace
+// ---------------------------------------------------------------------------
+struct MulWs {
+    int nb, P, nw;
+    int64_t PP, cap_out, cap_pairs;
+    uint32_t *bitsA, *bitsB;
+    int32_t *cnt, *cflag, *off, *oidx, *oi, *oj, *optr, *hflag, *hslot;
+    int2* pairs;
+    int64_t* sc;  // [8]: npairs, nout, nslot_total
+    int32_t* counters;
+    int32_t* ovf;
+    void* scan_tmp;
+};
+
+void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
+    w.nb = nb;
+    w.P = 1 << ceil_log2(nb);
+    w.nw = (nb + 31) / 32;
+    w.PP = (int64_t)w.P * w.P;
+    w.cap_out = (int64_t)nb * nb;
+    w.cap_pairs = max_pairs;
+    w.bitsA = c.take<uint32_t>((size_t)nb * w.nw);
+    w.bitsB = c.take<uint32_t>((size_t)nb * w.nw);
+    w.cnt = c.take<int32_t>(w.PP);
+    w.cflag = c.take<int32_t>(w.PP);
+    w.off = c.take<int32_t>(w.PP);
+    w.oidx = c.take<int32_t>(w.PP);
+    w.hflag = c.take<int32_t>(w.PP);
+    w.hslot = c.take<int32_t>(w.PP);
+    w.oi = c.take<int32_t>(w.cap_out);
+    w.oj = c.take<int32_t>(w.cap_out);
+    w.optr = c.take<int32_t>(w.cap_out + 1);
+    w.pairs = c.take<int2>(w.cap_pairs > 0 ? w.cap_pairs : 1);
+    w.sc = c.take<int64_t>(8);
+    w.counters = c.take<int32_t>(16);
+    w.ovf = c.take<int32_t>(4);
+    w.scan_tmp = c.take<char>(scan_temp_bytes(w.PP));
+}
+
+// Kept pairs of SpAMM(A, B, *tau) and the output pattern written into C
+// (map, brow, bcol, nslot); with X given, the pattern of 2X - C (branch 1).
+void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const double* tau_dev, const MatView& C,
+               uint8_t* fromc, MulWs& w, const int32_t* mapX, const int32_t* branch_dev, const int32_t* done,
+               hipStream_t s) {
+    const int nb = A.nb;
+    fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
+    fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
+    launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
+    launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
+    launch_kept_count(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, nullptr,
+                      w.cnt, w.cflag, nullptr, done, s);
+    scan_i32(w.cnt, w.off, w.PP, nullptr, &w.sc[0], w.scan_tmp, s);
+    scan_i32(w.cflag, w.oidx, w.PP, nullptr, &w.sc[1], w.scan_tmp, s);
+    launch_kept_fill(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, tau_dev, nullptr, w.cnt,
+                     w.off, w.oidx, &w.sc[0], &w.sc[1], w.cap_pairs, w.cap_out, w.oi, w.oj, w.optr, w.pairs, w.ovf,
+                     done, s);
+    launch_hat_flags(nb, w.P, w.cnt, sym, mapX, branch_dev, w.hflag, done, s);
+    scan_i32(w.hflag, w.hslot, w.PP, nullptr, &w.sc[2], w.scan_tmp, s);
+    launch_hat_assign(nb, w.P, w.cnt, sym, w.hflag, w.hslot, &w.sc[2], C.cap, C.map, C.brow, C.bcol, C.nslot, fromc,
+                      w.ovf, done, s);
+}
+
+// Leaf products of the kept pairs into C's slots (combined with X when given).
+void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatView& C, const uint8_t* fromc,
+              MulWs& w, const int32_t* mapX, const double* valX, const int32_t* branch_dev, const int32_t* done,
+              hipStream_t s) {
+    const int nb = A.nb;
+    GemmArgs g;
+    g.b = A.b;
+    g.nb = nb;
+    g.oi = w.oi;
+    g.oj = w.oj;
+    g.optr = w.optr;
+    g.pairs = w.pairs;
+    g.nout = &w.sc[1];
+    g.npairs = &w.sc[0];
+    g.valA = A.val;
+    g.valB = B.val;
+    g.btrans = btrans;
+    g.sym = sym;
+    g.map_out = C.map;
+    g.val_out = C.val;
+    g.mapX = mapX;
+    g.valX = valX;
+    g.branch = branch_dev;
+    g.counters = w.counters;
+    g.ovf = w.ovf;
+    g.done = done;
+    launch_gemm_f64(g, num_cus(), s);
+    if (mapX) launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s);
+}
+
+// ---------------------------------------------------------------------------
+// host copies of the decision rules of the driver (same arithmetic as the
+// algorithm's statement; double precision, one rounding per operation)
+// ---------------------------------------------------------------------------
+double step_delta(const sp2_params* p, double gap) {
+    if (!isnan(p->delta_const)) return p->delta_const;
+    return p->eps * gap / (4.0 * (double)p->n_max);
+}
+int choose_branch(double t1, double t2, int64_t n_occ) {
+    const double no = (double)n_occ;
+    return fabs(t2 - no) <= fabs((2.0 * t1 - t2) - no) ? 0 : 1;
+}
+double map_gap(double x, int br) { return br == 0 ? x * x : 2.0 * x - x * x; }
+bool should_stop(const std::vector<double>& eh, double e_tol) {
+    if (eh.empty()) return false;
+    if (fabs(eh.back()) <= e_tol) return true;
+    const size_t n = eh.size();
+    if (n >= 3 && fabs(eh[n - 3]) < 1e-3 && fabs(eh[n - 1]) >= fabs(eh[n - 3])) return true;
+    return false;
+}
+// RN(a - b) for double-doubles a, b (the trace difference)
+double dd_diff(double ahi, double alo, double bhi, double blo) {
+    double s = ahi - bhi;
+    double bb = s - ahi;
+    double e = (ahi - (s - bb)) + (-bhi - bb);
+    e = e + (alo - blo);
+    return s + e;
+}
+
+double trunc_quantum(double delta) {
+    const double T = delta * delta;
+    if (!(T > 0.0) || !isfinite(T)) return 0.0;
+    int e;
+    frexp(T, &e);
+    int eq = e - 1 - 40;
+    if (eq < -1000) eq = -1000;
+    return ldexp(1.0, eq);
+}
+
+__global__ void k_trunc_report(const int64_t* stats, const double* delta_dev, double delta_host, double scale,
+                               double* out) {
+    const double delta = (delta_dev ? *delta_dev : delta_host) * scale;
+    const double T = delta * delta;
+    double Q = 0.0;
+    if (T > 0.0 && isfinite(T)) {
+        int e;
+        frexp(T, &e);
+        int eq = e - 1 - 40;
+        if (eq < -1000) eq = -1000;
+        Q = ldexp(1.0, eq);
+    }
+    out[0] = (double)stats[0];
+    out[1] = (double)stats[1] * Q;
+}
+
+void carve_mat(Carver& c, int64_t n, int b, int64_t cap, spamm_bsm& m) {
+    m.n = n;
+    m.b = b;
+    m.nb = (int32_t)((n + b - 1) / b);
+    m.cap = cap;
+    m.nslot = c.take<int32_t>(1);
+    m.brow = c.take<int32_t>(cap);
+    m.bcol = c.take<int32_t>(cap);
+    m.map = c.take<int32_t>((size_t)m.nb * m.nb);
+    m.val = c.take<double>((size_t)cap * b * b);
+    m.norm = c.take<double>(cap);
+    m.sq = c.take<double>(cap);
+    m.sqlo = c.take<double>(cap);
+}
+
+struct Sp2Ws {
+    spamm_bsm X[2];
+    std::vector<spamm_bsm> tape;
+    SweepWs sw;
+    MulWs mw;
+    uint8_t* fromc;
+    void* trunc_tmp;
+    int64_t* tstats;  // [4]
+    double* trace_tmp;
+    double* trace_out;  // [4]
+    double* rowtmp;     // [2n]
+    double* lam;        // [2]
+    int32_t* dflag;
+    int32_t* dpos;
+    int64_t* dcount;
+    double* bound;  // [N]
+    Sp2Ctl* ctl;
+};
+
+void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, int tape_steps, Sp2Ws& w) {
+    const int64_t n = (int64_t)nb * b;
+    carve_mat(c, n, b, cap, w.X[0]);
+    carve_mat(c, n, b, cap, w.X[1]);
+    w.tape.resize(tape_steps > 0 ? tape_steps + 1 : 0);
+    for (auto& t : w.tape) carve_mat(c, n, b, cap, t);
+    carve_sweep(c, nb, N, w.sw);
+    carve_mul(c, nb, max_pairs, w.mw);
+    w.fromc = c.take<uint8_t>(cap);
+    w.trunc_tmp = c.take<char>(trunc_temp_bytes(cap));
+    w.tstats = c.take<int64_t>(4);
+    w.trace_tmp = c.take<double>(traces_temp_bytes() / sizeof(double));
+    w.trace_out = c.take<double>(4);
+    w.rowtmp = c.take<double>(2 * (size_t)n);
+    w.lam = c.take<double>(2);
+    w.dflag = c.take<int32_t>(nb);
+    w.dpos = c.take<int32_t>(nb);
+    w.dcount = c.take<int64_t>(2);
+    w.bound = c.take<double>(N);
+    w.ctl = c.take<Sp2Ctl>(1);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spamm_last_error(void) { return g_err; }
+
+int spamm_version(void) { return 100; }
+
+const char* spamm_status_str(int code) {
+    switch (code) {
+        case SPAMM_OK: return "ok";
+        case SPAMM_EINVAL: return "invalid argument";
+        case SPAMM_ECAPACITY: return "capacity exceeded";
+        case SPAMM_EWORKSPACE: return "workspace too small";
+        case SPAMM_EHIP: return "HIP runtime error";
+        case SPAMM_ENOTSUP: return "not supported";
+        case SPAMM_WNOCONV: return "iteration limit reached before the stop rule";
+        case SPAMM_WTAUFALLBACK: return "no candidate met the budget; exact product used";
+        default: return "unknown status";
+    }
+}
+
+int spamm_build_norms(spamm_bsm* X, spamm_stream_t stream) {
+    int rc = check_bsm(X, "X", true);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    launch_norms(X->b, X->nslot, X->cap, X->brow, X->val, X->sq, X->sqlo, X->norm, s);
+    HIP_TRY(hipGetLastError());
+    return SPAMM_OK;
+}
+
+size_t spamm_sweep_workspace_bytes(int32_t nb, int32_t N) {
+    if (nb < 1 || N < 1) return 0;
+    Carver c(nullptr);
+    SweepWs w;
+    carve_sweep(c, nb, N, w);
+    return c.off + 256;
+}
+
+int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, int32_t N, const double* budget,
+                    double budget_host, int32_t mode, const double* tau0_dev, double c_low, uint32_t flags,
+                    double* bound_out, int32_t* idx_out, double* tau_out, void* ws, size_t ws_bytes,
+                    spamm_stream_t stream) {
+    int rc = check_bsm(A, "A", true);
+    if (!rc) rc = check_bsm(B, "B", true);
+    if (rc) return rc;
+    if (A->nb != B->nb || A->b != B->b) return fail(SPAMM_EINVAL, "A and B must share n and leaf size");
+    if (N < 1 || N > 1024) return fail(SPAMM_EINVAL, "N must be in [1, 1024]");
+    if (!tau || !idx_out || !tau_out) return fail(SPAMM_EINVAL, "NULL output");
+    if (mode == 1 && !tau0_dev) return fail(SPAMM_EINVAL, "mode 1 needs tau0");
+    if (mode != 0 && mode != 1) return fail(SPAMM_EINVAL, "mode must be 0 or 1");
+    size_t need = spamm_sweep_workspace_bytes(A->nb, N);
+    if (!ws || ws_bytes < need) return fail(SPAMM_EWORKSPACE, "sweep needs %zu workspace bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    // the candidate list must be strictly decreasing and positive
+    std::vector<double> th(N);
+    HIP_TRY(hipMemcpyAsync(th.data(), tau, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int m = 0; m < N; ++m) {
+        if (!(th[m] > 0.0) || !isfinite(th[m])) return fail(SPAMM_EINVAL, "tau[%d] must be finite and > 0", m);
+        if (m > 0 && !(th[m] < th[m - 1])) return fail(SPAMM_EINVAL, "tau must be strictly decreasing");
+    }
+    Carver c(ws);
+    SweepWs w;
+    carve_sweep(c, A->nb, N, w);
+    fill_i32(w.ovf, 1, 0, s);
+    run_sweep(view(A), view(B), (flags & SPAMM_B_TRANSPOSED) ? 1 : 0, tau, N, budget, budget_host, mode, tau0_dev,
+              c_low, bound_out, idx_out, tau_out, w, nullptr, s);
+    HIP_TRY(hipGetLastError());
+    if (flags & SPAMM_SYNC) HIP_TRY(hipStreamSynchronize(s));
+    return SPAMM_OK;
+}
+
+size_t spamm_multiply_workspace_bytes(int32_t nb, int64_t max_pairs) {
+    if (nb < 1) return 0;
+    Carver c(nullptr);
+    MulWs w;
+    carve_mul(c, nb, max_pairs, w);
+    c.take<uint8_t>(0);
+    return c.off + 256;
+}
+
+int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev, uint32_t flags, spamm_bsm* C,
+                   int64_t* kept_out, void* ws, size_t ws_bytes, spamm_stream_t stream) {
+    int rc = check_bsm(A, "A", true);
+    if (!rc) rc = check_bsm(B, "B", true);
+    if (!rc) rc = check_bsm(C, "C", false);
+    if (rc) return rc;
+    if (A->nb != B->nb || A->b != B->b || C->nb != A->nb || C->b != A->b)
+        return fail(SPAMM_EINVAL, "A, B and C must share n and leaf size");
+    if (!tau_dev) return fail(SPAMM_EINVAL, "tau_dev is NULL");
+    const int sym = (flags & SPAMM_SYMMETRIC) ? 1 : 0;
+    const int btrans = (flags & SPAMM_B_TRANSPOSED) ? 1 : 0;
+    // the caller's workspace fixes the pair capacity
+    const size_t base = spamm_multiply_workspace_bytes(A->nb, 0);
+    if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "multiply needs at least %zu workspace bytes", base);
+    // pair capacity: what the workspace holds beyond the base (512 bytes slack
+    // cover the alignment of the carved arrays)
+    const int64_t max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    MulWs w;
+    carve_mul(c, A->nb, max_pairs, w);
+    if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
+    fill_i32(w.ovf, 1, 0, s);
+    run_pairs(view(A), view(B), btrans, sym, tau_dev, view(C), nullptr, w, nullptr, nullptr, nullptr, s);
+    run_gemm(view(A), view(B), btrans, sym, view(C), nullptr, w, nullptr, nullptr, nullptr, nullptr, s);
+    HIP_TRY(hipGetLastError());
+    int64_t sc[3];
+    int32_t ovf = 0;
+    HIP_TRY(hipMemcpyAsync(sc, w.sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ovf, w.ovf, sizeof(ovf), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (kept_out) {
+        int64_t ko[2] = {sc[0], sc[1]};
+        HIP_TRY(hipMemcpyAsync(kept_out, ko, sizeof(ko), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (ovf) {
+        return fail(SPAMM_ECAPACITY, "capacity exceeded: pairs %lld (cap %lld), slots %lld (cap %lld)",
+                    (long long)sc[0], (long long)max_pairs, (long long)sc[2], (long long)C->cap);
+    }
+    return SPAMM_OK;
+}
+
+size_t spamm_truncate_workspace_bytes(int64_t cap) { return trunc_temp_bytes(cap) + 64 + 512; }
+
+int spamm_truncate(spamm_bsm* X, double delta, uint32_t flags, double* removed_out, void* ws, size_t ws_bytes,
+                   spamm_stream_t stream) {
+    int rc = check_bsm(X, "X", true);
+    if (rc) return rc;
+    if (!(delta >= 0.0) || !isfinite(delta)) return fail(SPAMM_EINVAL, "delta must be finite and >= 0");
+    size_t need = spamm_truncate_workspace_bytes(X->cap);
+    if (!ws || ws_bytes < need) return fail(SPAMM_EWORKSPACE, "truncate needs %zu workspace bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    void* tmp = c.take<char>(trunc_temp_bytes(X->cap));
+    int64_t* stats = c.take<int64_t>(4);
+    int32_t* ovf = c.take<int32_t>(4);
+    fill_i32(ovf, 1, 0, s);
+    launch_truncate(view(X), nullptr, delta, 1.0, tmp, X->cap, stats, ovf, nullptr, s);
+    if (removed_out) hipLaunchKernelGGL(k_trunc_report, dim3(1), dim3(1), 0, s, stats, nullptr, delta, 1.0, removed_out);
+    HIP_TRY(hipGetLastError());
+    if (flags & SPAMM_SYNC) HIP_TRY(hipStreamSynchronize(s));
+    return SPAMM_OK;
+}
+
+size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
+                                  int32_t tape_steps) {
+    if (nb < 1 || N < 1 || cap_blocks < 1) return 0;
+    Carver c(nullptr);
+    Sp2Ws w;
+    carve_sp2(c, nb, b, N, cap_blocks, max_pairs, tape_steps, w);
+    return c.off + 256;
+}
+
+int purify_sp2_tape_view(void* ws, int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
+                         int32_t tape_steps, int32_t step, spamm_bsm* out) {
+    if (!ws || !out || nb < 1 || N < 1 || cap_blocks < 1) return fail(SPAMM_EINVAL, "bad tape view arguments");
+    if (step < 0 || step > tape_steps) return fail(SPAMM_EINVAL, "tape step out of range");
+    Carver c(ws);
+    Sp2Ws w;
+    carve_sp2(c, nb, b, N, cap_blocks, max_pairs, tape_steps, w);
+    *out = w.tape[step];
+    return SPAMM_OK;
+}
+
+int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out, void* ws,
+               size_t ws_bytes, spamm_stream_t stream) {
+    int rc = check_bsm(F, "F", false);
+    if (!rc) rc = check_bsm(D, "D", true);
+    if (rc) return rc;
+    if (!p || !log || !nlog_out) return fail(SPAMM_EINVAL, "NULL argument");
+    if (D->nb != F->nb || D->b != F->b || D->n != F->n) return fail(SPAMM_EINVAL, "D must match F");
+    if (p->n_max < 1 || p->n_max > 10000) return fail(SPAMM_EINVAL, "n_max out of range");
+    if (p->variant < 0 || p->variant > 2) return fail(SPAMM_EINVAL, "variant must be 0, 1 or 2");
+    if (p->N < 1 || p->N > 1024 || !p->tau) return fail(SPAMM_EINVAL, "bad candidate list");
+    if (p->n_occ < 0 || p->n_occ > F->n) return fail(SPAMM_EINVAL, "n_occ out of range");
+    const bool have_gap = !isnan(p->homo) && !isnan(p->lumo);
+    if (!have_gap && isnan(p->delta_const)) return fail(SPAMM_EINVAL, "need homo/lumo or delta_const");
+    if (have_gap && !(p->homo < p->lumo)) return fail(SPAMM_EINVAL, "need homo < lumo");
+    if (!(p->eps > 0.0)) return fail(SPAMM_EINVAL, "eps must be > 0");
+    const int nb = F->nb, b = F->b;
+    const int tape_steps = p->keep_tape ? p->n_max : 0;
+    // internal capacity: whatever the workspace holds (the binding sizes it)
+    int64_t cap = 0;
+    {
+        // find the largest cap with the given pair capacity that fits: the
+        // binding passes the same cap/pairs it queried with, encoded in D->cap
+        cap = D->cap;
+    }
+    int64_t max_pairs = 0;
+    {
+        size_t base = purify_sp2_workspace_bytes(nb, b, p->N, cap, 0, tape_steps);
+        if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "purify needs at least %zu workspace bytes", base);
+        max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    Sp2Ws w;
+    carve_sp2(c, nb, b, p->N, cap, max_pairs, tape_steps, w);
+    if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
+    int64_t nf = 0;
+    {
+        int32_t t = 0;
+        HIP_TRY(hipMemcpyAsync(&t, F->nslot, sizeof(t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        nf = t;
+    }
+    if (nf + nb > cap) return fail(SPAMM_ECAPACITY, "D->cap must be at least nslot(F) + nb");
+
+    hipEvent_t ev[8];
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t* e;
+        ~EvGuard() {
+            for (int q = 0; q < 8; ++q) hipEventDestroy(e[q]);
+        }
+    } guard{ev};
+
+    Sp2Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    fill_i32(w.mw.ovf, 1, 0, s);
+    fill_i32(w.sw.ovf, 1, 0, s);
+
+    // X_0 and its first truncation
+    MatView Fv = view(F);
+    MatView X0 = view(&w.X[0]);
+    launch_gersch(Fv, w.rowtmp, w.lam, s);
+    launch_x0(Fv, w.lam, X0, w.dflag, w.dpos, w.mw.scan_tmp, w.dcount, s);
+    launch_norms(b, X0.nslot, X0.cap, X0.brow, X0.val, X0.sq, X0.sqlo, X0.norm, s);
+    double lam[2];
+    HIP_TRY(hipMemcpyAsync(lam, w.lam, sizeof(lam), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double W = lam[1] - lam[0];
+    double xh = have_gap ? (lam[1] - p->homo) / W : NAN;
+    double xl = have_gap ? (lam[1] - p->lumo) / W : NAN;
+    const double delta0 = step_delta(p, xh - xl);
+    hc.delta = delta0;
+    HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+    if (p->variant != 1) launch_truncate(X0, &w.ctl->delta, 0.0, 1.0, w.trunc_tmp, cap, w.tstats, w.mw.ovf, nullptr, s);
+    if (tape_steps > 0) {
+        // tape[0] = X~_0
+        spamm_bsm& t = w.tape[0];
+        HIP_TRY(hipMemcpyAsync(t.nslot, X0.nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(t.brow, X0.brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(t.bcol, X0.bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(t.map, X0.map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(t.val, X0.val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(t.norm, X0.norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(t.sq, X0.sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(t.sqlo, X0.sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+    }
+
+    std::vector<double> e_hist;
+    int cur = 0;
+    int nlog = 0;
+    int status = SPAMM_OK;
+    const double tb_scale = p->variant == 0 ? 0.5 : 1.0;
+    for (int it = 1;; ++it) {
+        spamm_bsm* Xc = tape_steps > 0 ? &w.tape[it - 1] : &w.X[cur];
+        spamm_bsm* Xn = tape_steps > 0 ? (it <= tape_steps ? &w.tape[it] : nullptr) : &w.X[1 - cur];
+        MatView xv = view(Xc);
+        launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp, w.trace_out,
+                      nullptr, s);
+        double tr[4];
+        int64_t msc[3], ts[2];
+        int32_t ovf[2];
+        Sp2Ctl cs;
+        HIP_TRY(hipMemcpyAsync(tr, w.trace_out, sizeof(tr), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(msc, w.mw.sc, sizeof(msc), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(ts, w.tstats, sizeof(ts), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&ovf[0], w.mw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&ovf[1], w.sw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&cs, w.ctl, sizeof(cs), hipMemcpyDeviceToHost, s));
+        int32_t nsl = 0;
+        HIP_TRY(hipMemcpyAsync(&nsl, xv.nslot, sizeof(nsl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ovf[0] || ovf[1]) {
+            status = fail(SPAMM_ECAPACITY, "capacity exceeded in iteration %d (flags %d/%d; pairs %lld of %lld)",
+                          it - 1, ovf[0], ovf[1], (long long)msc[0], (long long)max_pairs);
+            break;
+        }
+        if (nlog > 0) {
+            sp2_iter_log& L = log[nlog - 1];
+            L.idx = cs.idx;
+            L.tau = cs.tau;
+            L.npairs = msc[0];
+            L.nout = msc[1];
+            L.nslot_hat = msc[2];
+            L.removed_units = ts[0];
+            L.removed_fro2 = (double)ts[1] * trunc_quantum(L.delta * tb_scale);
+            L.nslot_kept = nsl;
+            float ms = 0;
+            hipEventElapsedTime(&ms, ev[0], ev[1]); L.ms_sweep = ms;
+            hipEventElapsedTime(&ms, ev[1], ev[2]); L.ms_pairs = ms;
+            hipEventElapsedTime(&ms, ev[2], ev[3]); L.ms_gemm = ms;
+            hipEventElapsedTime(&ms, ev[3], ev[4]); L.ms_norms = ms;
+            hipEventElapsedTime(&ms, ev[4], ev[5]); L.ms_trunc = ms;
+            hipEventElapsedTime(&ms, ev[0], ev[5]); L.ms_total = ms;
+        }
+        const double t1 = tr[0], t2 = tr[2];
+        const double e = dd_diff(tr[0], tr[1], tr[2], tr[3]);
+        e_hist.push_back(e);
+        sp2_iter_log& L = log[nlog++];
+        memset(&L, 0, sizeof(L));
+        L.i = it;
+        L.t1 = t1;
+        L.t2 = t2;
+        L.e = e;
+        L.branch = -1;
+        const bool stop = should_stop(e_hist, p->e_tol);
+        if (stop || it > p->n_max || Xn == nullptr) {
+            L.stop = stop ? 1 : 2;
+            if (!stop) status = SPAMM_WNOCONV;
+            break;
+        }
+        const int br = choose_branch(t1, t2, p->n_occ);
+        if (have_gap) {
+            xh = map_gap(xh, br);
+            xl = map_gap(xl, br);
+        }
+        const double delta = step_delta(p, xh - xl);
+        L.branch = br;
+        L.delta = delta;
+        hc.branch = br;
+        hc.delta = delta;
+        hc.budget = p->variant == 0 ? delta / 2.0 : delta;
+        hc.tau = 0.0;
+        hc.idx = p->N;
+        HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+        MatView nv = view(Xn);
+        HIP_TRY(hipEventRecord(ev[0], s));
+        if (p->variant != 2)
+            run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
+                      &w.ctl->tau, w.sw, nullptr, s);
+        HIP_TRY(hipEventRecord(ev[1], s));
+        // kept pairs, output pattern and the leaf products (combined with X)
+        run_pairs(xv, xv, 1, 1, &w.ctl->tau, nv, w.fromc, w.mw, xv.map, &w.ctl->branch, nullptr, s);
+        HIP_TRY(hipEventRecord(ev[2], s));
+        run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, nullptr, s);
+        HIP_TRY(hipEventRecord(ev[3], s));
+        launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, s);
+        HIP_TRY(hipEventRecord(ev[4], s));
+        if (p->variant != 1)
+            launch_truncate(nv, &w.ctl->delta, 0.0, tb_scale, w.trunc_tmp, cap, w.tstats, w.mw.ovf, nullptr, s);
+        HIP_TRY(hipEventRecord(ev[5], s));
+        HIP_TRY(hipGetLastError());
+        cur = 1 - cur;
+    }
+    // final: copy the last iterate into D
+    if (status >= 0) {
+        spamm_bsm* Xf = tape_steps > 0 ? &w.tape[nlog - 1] : &w.X[cur];
+        HIP_TRY(hipMemcpyAsync(D->nslot, Xf->nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D->brow, Xf->brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D->bcol, Xf->bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D->map, Xf->map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D->val, Xf->val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D->norm, Xf->norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D->sq, Xf->sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D->sqlo, Xf->sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    *nlog_out = nlog;
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// K2: the error-bound sweep (Algorithm 3, CSE) for every candidate
+// threshold at once, and the selection rule.
+//
+// The product recursion of Algorithm 3 is an octree over (i, k, j) block
+// triples.  Nodes are identified by 3D Morton keys, whose low three bits are
+// the octant (a, kappa, c) inside the parent.  The bottom l0 levels are
+// evaluated per "cube" (2^l0 x 2^l0 x 2^l0 triples) by one workgroup: the
+// cube's A and B leaf norms are staged in LDS and one thread per candidate
+// walks the cube's subtree in the canonical order of Algorithm 3
+// (a = row half outer, c = column half inner, t = E1 + E2, acc += t^2,
+// sqrt at the end).  The levels above run as segmented reductions over the
+// sorted node lists, one launch per level.  All arithmetic is in the
+// paper's order with one rounding per operation, so every candidate's bound
+// is bit-identical to the recursive definition.
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spamm {
+
+static int ceil_log2(int x) {
+    int L = 0;
+    while ((1 << L) < x) ++L;
+    return L;
+}
+
+int cse_level0(int nb) {
+    int L = ceil_log2(nb);
+    int l0 = L - 7;  // at most 128^3 cubes
+    if (l0 < 3) l0 = 3;
+    if (l0 > L) l0 = L;
+    return l0;
+}
+
+size_t cse_cube_cap(int nb) {
+    int L = ceil_log2(nb);
+    int T = 1 << (L - cse_level0(nb));
+    return (size_t)T * T * T;
+}
+
+__global__ void k_cube_flags(int T, const uint8_t* __restrict__ tA, const uint8_t* __restrict__ tB,
+                             int32_t* __restrict__ flag, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t TTT = (int64_t)T * T * T;
+    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < TTT; z += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t I, K, J;
+        demorton3((uint32_t)z, I, K, J);
+        flag[z] = (tA[(size_t)I * T + K] && tB[(size_t)K * T + J]) ? 1 : 0;
+    }
+}
+
+void launch_cube_flags(int T, const uint8_t* tilesA, const uint8_t* tilesB, int32_t* flag, const int32_t* done,
+                       hipStream_t s) {
+    int64_t TTT = (int64_t)T * T * T;
+    hipLaunchKernelGGL(k_cube_flags, dim3(grid_for(TTT, 256, 8192)), dim3(256), 0, s, T, tilesA, tilesB, flag, done);
+}
+
+__global__ void k_cube_list(int T, const int32_t* __restrict__ flag, const int32_t* __restrict__ idx,
+                            uint32_t* __restrict__ keys, const int64_t* __restrict__ ncubes, int64_t cap,
+                            int32_t* __restrict__ ovf, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t TTT = (int64_t)T * T * T;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && *ncubes > cap) atomicOr(ovf, kOvfCubes);
+    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < TTT; z += (int64_t)gridDim.x * blockDim.x) {
+        if (flag[z] && idx[z] < cap) keys[idx[z]] = (uint32_t)z;
+    }
+}
+
+void launch_cube_list(int T, const int32_t* flag, const int32_t* idx, uint32_t* keys, const int64_t* ncubes,
+                      int64_t cap, int32_t* ovf, const int32_t* done, hipStream_t s) {
+    int64_t TTT = (int64_t)T * T * T;
+    hipLaunchKernelGGL(k_cube_list, dim3(grid_for(TTT, 256, 8192)), dim3(256), 0, s, T, flag, idx, keys, ncubes, cap,
+                       ovf, done);
+}
+
+// Error of the subtree rooted at level LEV, node (i0, k0, j0) inside the cube.
+template <int LEV, int S, int MODE>
+SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double cl, const double (*nA)[S],
+                           const double (*nB)[S]) {
+    if constexpr (LEV == 0) {
+        double p = nA[i0][k0] * nB[k0][j0];
+        if constexpr (MODE == 0) {
+            return p < tm ? p : 0.0;
+        } else {
+            return p < t0 ? p : (p < tm ? cl * p : 0.0);
+        }
+    } else {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double e1 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0, 2 * j0 + c, tm, t0, cl, nA, nB);
+                double e2 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0 + 1, 2 * j0 + c, tm, t0, cl, nA, nB);
+                double t = e1 + e2;
+                double t2 = t * t;
+                acc = acc + t2;
+            }
+        return sqrt(acc);
+    }
+}
+
+template <int L0, int MODE>
+__global__ __launch_bounds__(256) void k_cube_eval(int nb, const uint32_t* __restrict__ keys,
+                                                  const int64_t* __restrict__ ncubes_p, int64_t cap,
+                                                  const int32_t* __restrict__ mapA, const double* __restrict__ normA,
+                                                  const int32_t* __restrict__ mapB, const double* __restrict__ normB,
+                                                  int btrans, const double* __restrict__ tau, int N,
+                                                  const double* __restrict__ tau0_p, double c_low,
+                                                  double* __restrict__ vals, const int32_t* __restrict__ done) {
+    constexpr int S = 1 << L0;
+    __shared__ double nA[S][S];
+    __shared__ double nB[S][S];
+    if (done && *done) return;
+    int64_t ncubes = *ncubes_p;
+    if (ncubes > cap) ncubes = cap;
+    const double t0 = (MODE == 1 && tau0_p) ? *tau0_p : 0.0;
+    for (int64_t cube = blockIdx.x; cube < ncubes; cube += gridDim.x) {
+        uint32_t I, K, J;
+        demorton3(keys[cube], I, K, J);
+        __syncthreads();
+        for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
+            int a = t / S, q = t % S;
+            int i = (int)I * S + a, k = (int)K * S + q;  // A_ik
+            double va = 0.0;
+            if (i < nb && k < nb) {
+                int sa = mapA[(size_t)i * nb + k];
+                if (sa >= 0) va = normA[sa];
+            }
+            nA[a][q] = va;
+            int kk = (int)K * S + a, j = (int)J * S + q;  // B_kj
+            double vb = 0.0;
+            if (kk < nb && j < nb) {
+                int sb = btrans ? mapB[(size_t)j * nb + kk] : mapB[(size_t)kk * nb + j];
+                if (sb >= 0) vb = normB[sb];
+            }
+            nB[a][q] = vb;
+        }
+        __syncthreads();
+        for (int m = threadIdx.x; m < N; m += blockDim.x)
+            vals[(size_t)cube * N + m] = cube_node<L0, S, MODE>(0, 0, 0, tau[m], t0, c_low, nA, nB);
+    }
+}
+
+void launch_cube_eval(int mode, int l0, int nb, const uint32_t* keys, const int64_t* ncubes, int64_t cap,
+                      const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB, int btrans,
+                      const double* tau, int N, const double* tau0, double c_low, double* vals, const int32_t* done,
+                      hipStream_t s) {
+    int grid = grid_for(cap, 1, 4096);
+    int threads = N >= 256 ? 256 : ((N + 63) / 64) * 64;
+#define SPAMM_CUBE(L0_, M_)                                                                                       \
+    hipLaunchKernelGGL((k_cube_eval<L0_, M_>), dim3(grid), dim3(threads), 0, s, nb, keys, ncubes, cap, mapA, normA, \
+                       mapB, normB, btrans, tau, N, tau0, c_low, vals, done)
+    if (mode == 0) {
+        switch (l0) {
+            case 0: SPAMM_CUBE(0, 0); break;
+            case 1: SPAMM_CUBE(1, 0); break;
+            case 2: SPAMM_CUBE(2, 0); break;
+            case 3: SPAMM_CUBE(3, 0); break;
+            case 4: SPAMM_CUBE(4, 0); break;
+        }
+    } else {
+        switch (l0) {
+            case 0: SPAMM_CUBE(0, 1); break;
+            case 1: SPAMM_CUBE(1, 1); break;
+            case 2: SPAMM_CUBE(2, 1); break;
+            case 3: SPAMM_CUBE(3, 1); break;
+            case 4: SPAMM_CUBE(4, 1); break;
+        }
+    }
+#undef SPAMM_CUBE
+}
+
+__global__ void k_level_flags(const uint32_t* __restrict__ keys, const int64_t* __restrict__ n_p, int64_t cap,
+                              int32_t* __restrict__ flag, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    int64_t n = *n_p;
+    if (n > cap) n = cap;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+        flag[c] = (c == 0 || (keys[c] >> 3) != (keys[c - 1] >> 3)) ? 1 : 0;
+}
+
+void launch_level_flags(const uint32_t* keys, const int64_t* n, int64_t cap, int32_t* flag, const int32_t* done,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_level_flags, dim3(grid_for(cap, 256, 4096)), dim3(256), 0, s, keys, n, cap, flag, done);
+}
+
+__global__ void k_level_build(const uint32_t* __restrict__ keys, const int64_t* __restrict__ n_p, int64_t cap,
+                              const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                              const int64_t* __restrict__ np_p, uint32_t* __restrict__ pkeys,
+                              int32_t* __restrict__ pstart, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    int64_t n = *n_p;
+    if (n > cap) n = cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) pstart[*np_p] = (int32_t)n;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+        if (flag[c]) {
+            int p = pos[c];
+            pkeys[p] = keys[c] >> 3;
+            pstart[p] = (int32_t)c;
+        }
+    }
+}
+
+void launch_level_build(const uint32_t* keys, const int64_t* n, int64_t cap, const int32_t* flag, const int32_t* pos,
+                        const int64_t* nparent, uint32_t* pkeys, int32_t* pstart, const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_build, dim3(grid_for(cap, 256, 4096)), dim3(256), 0, s, keys, n, cap, flag, pos,
+                       nparent, pkeys, pstart, done);
+}
+
+__global__ void k_level_eval(const uint32_t* __restrict__ ckeys, const double* __restrict__ cvals,
+                             const int32_t* __restrict__ pstart, const int64_t* __restrict__ np_p, int64_t cap, int N,
+                             double* __restrict__ pvals, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    int64_t np = *np_p;
+    if (np > cap) np = cap;
+    const int64_t total = np * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = idx / N;
+        const int m = (int)(idx - p * N);
+        double e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = 0.0;
+        for (int c = pstart[p]; c < pstart[p + 1]; ++c) {
+            const uint32_t o = ckeys[c] & 7u;
+            const double v = cvals[(size_t)c * N + m];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) e[q] = (o == (uint32_t)q) ? v : e[q];
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double t = e[(a << 2) | c] + e[(a << 2) | 2 | c];
+                double t2 = t * t;
+                acc = acc + t2;
+            }
+        pvals[(size_t)p * N + m] = sqrt(acc);
+    }
+}
+
+void launch_level_eval(const uint32_t* ckeys, const double* cvals, const int32_t* pstart, const int64_t* nparent,
+                       int64_t cap, int N, double* pvals, const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_eval, dim3(grid_for(cap * N, 256, 8192)), dim3(256), 0, s, ckeys, cvals, pstart, nparent,
+                       cap, N, pvals, done);
+}
+
+// Selection: the first (largest) candidate whose bound is below the budget;
+// none -> index N and tau = 0 (exact product).
+__global__ __launch_bounds__(1024) void k_select(const double* __restrict__ root, const int64_t* __restrict__ nroot,
+                                                const double* __restrict__ tau, int N,
+                                                const double* __restrict__ budget_dev, double budget_host,
+                                                double* __restrict__ bound_out, int32_t* __restrict__ idx_out,
+                                                double* __restrict__ tau_out, const int32_t* __restrict__ done) {
+    __shared__ int best;
+    if (done && *done) return;
+    if (threadIdx.x == 0) best = N;
+    __syncthreads();
+    const double budget = budget_dev ? *budget_dev : budget_host;
+    const bool have = *nroot > 0;
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        double bd = have ? root[m] : 0.0;
+        if (bound_out) bound_out[m] = bd;
+        if (bd < budget) atomicMin(&best, m);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *idx_out = best;
+        *tau_out = best < N ? tau[best] : 0.0;
+    }
+}
+
+void launch_select(const double* root, const int64_t* nroot, const double* tau, int N, const double* budget_dev,
+                   double budget_host, double* bound_out, int32_t* idx_out, double* tau_out, const int32_t* done,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, root, nroot, tau, N, budget_dev, budget_host, bound_out,
+                       idx_out, tau_out, done);
+}
+
+}  // namespace spamm

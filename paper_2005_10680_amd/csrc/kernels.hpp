@@ -1,0 +1,110 @@
+// Internal launcher interface between the C ABI (api.hip) and the kernels.
+#pragma once
+#include "common.hpp"
+
+namespace spamm {
+
+// A block-sparse matrix as the kernels see it (see spamm_bsm in spamm.h).
+struct MatView {
+    int64_t n;
+    int32_t b, nb;
+    int64_t cap;
+    int32_t* nslot;
+    int32_t* brow;
+    int32_t* bcol;
+    int32_t* map;
+    double* val;
+    double* norm;
+    double* sq;
+    double* sqlo;
+};
+
+// norms.hip
+void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, double* sq,
+                  double* sqlo, double* nrm, hipStream_t s);
+size_t traces_temp_bytes();
+void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
+                   const double* val, const double* sq, const double* sqlo, double* temp, double* out,
+                   const int32_t* done, hipStream_t s);
+
+// pairs.hip
+enum OccMode { kOccA = 0, kOccB = 1, kOccBt = 2 };
+void launch_occupancy(const MatView& M, int mode, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0,
+                      const int32_t* done, hipStream_t s);
+void launch_kept_count(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
+                       const double* normA, const int32_t* mapB, const double* normB, int btrans, int sym,
+                       const double* tau, const double* sigma, int32_t* cnt, int32_t* cnt_flag, int32_t* cnt_low,
+                       const int32_t* done, hipStream_t s);
+void launch_kept_fill(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
+                      const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
+                      const double* sigma, const int32_t* cnt, const int32_t* off, const int32_t* oidx,
+                      const int64_t* npairs, const int64_t* nout, int64_t cap_pairs, int64_t cap_out, int32_t* oi,
+                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* ovf, const int32_t* done, hipStream_t s);
+void launch_hat_flags(int nb, int P, const int32_t* cnt, int sym, const int32_t* mapX, const int32_t* branch,
+                      int32_t* flag, const int32_t* done, hipStream_t s);
+void launch_hat_assign(int nb, int P, const int32_t* cnt, int sym, const int32_t* flag, const int32_t* slot,
+                       const int64_t* nslot_total, int64_t cap, int32_t* map, int32_t* brow, int32_t* bcol,
+                       int32_t* nslot, uint8_t* fromc, int32_t* ovf, const int32_t* done, hipStream_t s);
+void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t* brow, const int32_t* bcol,
+                 const uint8_t* fromc, int nb, const int32_t* mapX, const double* valX, double* valH,
+                 const int32_t* branch, const int32_t* done, hipStream_t s);
+
+// cse.hip
+size_t cse_cube_cap(int nb);
+int cse_level0(int nb);
+void launch_cube_flags(int T, const uint8_t* tilesA, const uint8_t* tilesB, int32_t* flag, const int32_t* done,
+                       hipStream_t s);
+void launch_cube_list(int T, const int32_t* flag, const int32_t* idx, uint32_t* keys, const int64_t* ncubes,
+                      int64_t cap, int32_t* ovf, const int32_t* done, hipStream_t s);
+void launch_cube_eval(int mode, int l0, int nb, const uint32_t* keys, const int64_t* ncubes, int64_t cap,
+                      const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB, int btrans,
+                      const double* tau, int N, const double* tau0, double c_low, double* vals, const int32_t* done,
+                      hipStream_t s);
+void launch_level_flags(const uint32_t* keys, const int64_t* n, int64_t cap, int32_t* flag, const int32_t* done,
+                        hipStream_t s);
+void launch_level_build(const uint32_t* keys, const int64_t* n, int64_t cap, const int32_t* flag,
+                        const int32_t* pos, const int64_t* nparent, uint32_t* pkeys, int32_t* pstart,
+                        const int32_t* done, hipStream_t s);
+void launch_level_eval(const uint32_t* ckeys, const double* cvals, const int32_t* pstart, const int64_t* nparent,
+                       int64_t cap, int N, double* pvals, const int32_t* done, hipStream_t s);
+void launch_select(const double* root, const int64_t* nroot, const double* tau, int N, const double* budget_dev,
+                   double budget_host, double* bound_out, int32_t* idx_out, double* tau_out, const int32_t* done,
+                   hipStream_t s);
+
+// gemm.hip
+struct GemmArgs {
+    int b, nb;
+    const int32_t* oi;
+    const int32_t* oj;
+    const int32_t* optr;
+    const int2* pairs;
+    const int64_t* nout;
+    const int64_t* npairs;
+    const double* valA;
+    const double* valB;
+    int btrans;
+    int sym;
+    const int32_t* map_out;
+    double* val_out;
+    // combine with X (2X - C when *branch == 1); mapX/valX may be null
+    const int32_t* mapX;
+    const double* valX;
+    const int32_t* branch;
+    int32_t* counters;  // [16] work counters, reset by the launcher
+    const int32_t* ovf; // nonzero: an earlier capacity overflow, skip
+    const int32_t* done;
+};
+void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s);
+
+// trunc.hip
+size_t trunc_temp_bytes(int64_t cap);
+void launch_truncate(const MatView& X, const double* delta_dev, double delta_host, double delta_scale,
+                     void* temp, int64_t cap, int64_t* stats /* [4] */, int32_t* ovf, const int32_t* done,
+                     hipStream_t s);
+
+// x0.hip
+void launch_gersch(const MatView& F, double* rowtmp /* [nb*b*2] */, double* lam /* [2] */, hipStream_t s);
+void launch_x0(const MatView& F, const double* lam, const MatView& X, int32_t* diagflag, int32_t* diagpos,
+               void* scan_temp, int64_t* tmp_count, hipStream_t s);
+
+}  // namespace spamm

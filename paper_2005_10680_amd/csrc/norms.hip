@@ -1,0 +1,252 @@
+// K1: block Frobenius norms (skip test of Algorithm 2, leaf values of
+// Algorithm 3) and the traces used by the purification driver.
+//
+// nu(X) = sqrt_RN(RN(sum x^2)): the exact sum of squares rounded once,
+// then a correctly rounded square root.  One wave per block: coalesced
+// 16-byte loads, double-double accumulation of the exact squares
+// (x*x and fma(x, x, -x*x)), a butterfly reduction across the wave, then a
+// certificate that the double-double value rounds like the exact sum.  A
+// block whose sum lies too close to a rounding boundary (or holds values
+// outside [2^-480, 2^500]) is summed exactly with a 32-bit-limb long
+// accumulator by one lane.
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spamm {
+
+// Long accumulator: value * 2^2148 as an unsigned integer in 32-bit limbs.
+constexpr int kLimbs = 140;  // 4480 bits > 2148 + 2048 + 106 + carries
+
+SPAMM_DEV void limbs_add128(uint32_t* L, uint64_t lo, uint64_t hi, int shift) {
+    const int q = shift >> 5, o = shift & 31;
+    uint32_t v[5];
+    v[0] = (uint32_t)lo;
+    v[1] = (uint32_t)(lo >> 32);
+    v[2] = (uint32_t)hi;
+    v[3] = (uint32_t)(hi >> 32);
+    v[4] = 0;
+    uint32_t w[5];
+    if (o == 0) {
+        for (int t = 0; t < 5; ++t) w[t] = v[t];
+    } else {
+        w[0] = v[0] << o;
+        for (int t = 1; t < 5; ++t) w[t] = (v[t] << o) | (v[t - 1] >> (32 - o));
+    }
+    uint64_t carry = 0;
+    for (int t = 0; q + t < kLimbs; ++t) {
+        uint64_t s = (uint64_t)L[q + t] + carry + (t < 5 ? w[t] : 0u);
+        L[q + t] = (uint32_t)s;
+        carry = s >> 32;
+        if (t >= 4 && carry == 0) break;
+    }
+}
+
+// decompose finite nonzero x = m * 2^e, m < 2^53 integer
+SPAMM_DEV void split_double(double x, uint64_t& m, int& e) {
+    uint64_t bits = (uint64_t)__double_as_longlong(x);
+    int ex = (int)((bits >> 52) & 0x7ff);
+    m = bits & ((1ull << 52) - 1);
+    if (ex == 0) {
+        e = -1074;
+    } else {
+        m |= 1ull << 52;
+        e = ex - 1075;
+    }
+}
+
+SPAMM_DEV int limbs_bit(const uint32_t* L, int i) { return (int)((L[i >> 5] >> (i & 31)) & 1u); }
+
+// round value*2^-2148 to nearest double, ties to even
+SPAMM_DEV double limbs_round(const uint32_t* L) {
+    int top = -1;
+    for (int t = kLimbs - 1; t >= 0; --t)
+        if (L[t]) {
+            top = t * 32 + 31 - __clz(L[t]);
+            break;
+        }
+    if (top < 0) return 0.0;
+    if (top - 2148 >= 1024) return INFINITY;
+    int lsb = top - 52;
+    if (lsb < 1074) lsb = 1074;  // 2^-1074 is the subnormal step
+    uint64_t M = 0;
+    for (int i = top; i >= lsb; --i) M = (M << 1) | (uint64_t)limbs_bit(L, i);
+    int rb = lsb >= 1 ? limbs_bit(L, lsb - 1) : 0;
+    int sticky = 0;
+    for (int i = lsb - 2; i >= 0 && !sticky; --i) {
+        if ((i & 31) == 31 && L[i >> 5] == 0) {
+            i -= 31;
+            continue;
+        }
+        sticky = limbs_bit(L, i);
+    }
+    if (rb && (sticky || (M & 1u))) M += 1;
+    return ldexp((double)M, lsb - 2148);
+}
+
+SPAMM_DEV double exact_sumsq_lane(const double* v, int len, uint32_t* L) {
+    bool has_nan = false, has_inf = false;
+    for (int t = 0; t < kLimbs; ++t) L[t] = 0;
+    for (int t = 0; t < len; ++t) {
+        double x = v[t];
+        if (isnan(x)) { has_nan = true; continue; }
+        if (isinf(x)) { has_inf = true; continue; }
+        if (x == 0.0) continue;
+        uint64_t m;
+        int e;
+        split_double(x, m, e);
+        uint64_t lo = m * m, hi = __umul64hi(m, m);
+        limbs_add128(L, lo, hi, 2 * e + 2148);
+    }
+    if (has_nan) return NAN;
+    if (has_inf) return INFINITY;
+    return limbs_round(L);
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_norms(const int32_t* __restrict__ nslot_p, int64_t cap,
+                                              const int32_t* __restrict__ brow, const double* __restrict__ val,
+                                              double* __restrict__ sq, double* __restrict__ sqlo,
+                                              double* __restrict__ nrm) {
+    __shared__ uint32_t slow[4][kLimbs];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int64_t nslot = *nslot_p;
+    if (nslot > cap) nslot = cap;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < nslot; s += (int64_t)gridDim.x * 4) {
+        if (brow[s] < 0) continue;  // hole (wave-uniform)
+        const double2* v = reinterpret_cast<const double2*>(val + (size_t)s * B * B);
+        dd acc = {0.0, 0.0};
+        bool special = false, tiny = false;
+#pragma unroll 4
+        for (int it = 0; it < B * B / 128; ++it) {
+            double2 x2 = v[it * 64 + lane];
+            double xs[2] = {x2.x, x2.y};
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double x = xs[q];
+                double ax = fabs(x);
+                if (!(ax < 0x1p500)) special = true;          // huge, inf or NaN
+                if (ax != 0.0 && ax < 0x1p-480) tiny = true;   // two-product may be inexact
+                double p = x * x;
+                double pe = fma(x, x, -p);
+                acc = dd_add(acc, dd{p, pe});
+            }
+        }
+        acc = dd_wave_sum(acc);
+        const bool any_special = __any(special);
+        const bool any_tiny = __any(tiny);
+        // certificate: distance from hi+lo to the nearest rounding boundary
+        // must exceed the accumulated error bound
+        const double eb = acc.hi * 0x1p-80 + (any_tiny ? 0x1p-1000 : 0.0);
+        bool ok;
+        if (any_special) {
+            ok = false;
+        } else if (acc.lo >= 0.0) {
+            // boundary above: hi + up/2
+            double up = nextafter(acc.hi, INFINITY) - acc.hi;
+            ok = (up - 2.0 * acc.lo) > 2.0 * eb;
+        } else {
+            // boundary below: hi - dn/2
+            double dn = acc.hi - nextafter(acc.hi, 0.0);
+            ok = (dn + 2.0 * acc.lo) > 2.0 * eb;
+        }
+        double sres = acc.hi, slo = acc.lo;
+        if (!ok) {
+            if (lane == 0) {
+                double ex = exact_sumsq_lane(val + (size_t)s * B * B, B * B, slow[wv]);
+                slo = (acc.hi - ex) + acc.lo;
+                sres = ex;
+            }
+            sres = __shfl(sres, 0);
+            slo = __shfl(slo, 0);
+        }
+        if (lane == 0) {
+            sq[s] = sres;
+            sqlo[s] = slo;
+            nrm[s] = sqrt(sres);
+        }
+    }
+}
+
+void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, double* sq,
+                  double* sqlo, double* nrm, hipStream_t s) {
+    int grid = grid_for(cap, 4, 8192);
+    switch (b) {
+        case 32: hipLaunchKernelGGL(k_norms<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm); break;
+        case 64: hipLaunchKernelGGL(k_norms<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm); break;
+        case 128: hipLaunchKernelGGL(k_norms<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Traces: t1 = sum of diagonal entries (rows < n), t2 = sum over slots of
+// (sq + sqlo) = ||X||_F^2, both in double-double, fixed reduction order.
+// ---------------------------------------------------------------------------
+constexpr int kTrBlocks = 120;
+
+__global__ __launch_bounds__(256) void k_traces_part(const int32_t* __restrict__ nslot_p, int64_t cap, int b,
+                                                    int64_t n, const int32_t* __restrict__ brow,
+                                                    const int32_t* __restrict__ bcol, const double* __restrict__ val,
+                                                    const double* __restrict__ sq, const double* __restrict__ sqlo,
+                                                    double* __restrict__ part /* [kTrBlocks][4] */,
+                                                    const int32_t* __restrict__ done) {
+    __shared__ double sh[4][4];
+    if (done && *done) return;
+    int64_t nslot = *nslot_p;
+    if (nslot > cap) nslot = cap;
+    dd d1 = {0, 0}, d2 = {0, 0};
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslot; s += (int64_t)gridDim.x * blockDim.x) {
+        int r = brow[s];
+        if (r < 0) continue;
+        d2 = dd_add(d2, dd{sq[s], 0.0});
+        d2 = dd_add(d2, dd{sqlo[s], 0.0});
+        if (r == bcol[s]) {
+            const double* v = val + (size_t)s * b * b;
+            for (int t = 0; t < b; ++t) {
+                if ((int64_t)r * b + t >= n) break;
+                d1 = dd_add(d1, dd{v[(size_t)t * b + t], 0.0});
+            }
+        }
+    }
+    d1 = dd_wave_sum(d1);
+    d2 = dd_wave_sum(d2);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[w][0] = d1.hi; sh[w][1] = d1.lo; sh[w][2] = d2.hi; sh[w][3] = d2.lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        dd a = {0, 0}, c = {0, 0};
+        for (int q = 0; q < 4; ++q) {
+            a = dd_add(a, dd{sh[q][0], sh[q][1]});
+            c = dd_add(c, dd{sh[q][2], sh[q][3]});
+        }
+        part[blockIdx.x * 4 + 0] = a.hi; part[blockIdx.x * 4 + 1] = a.lo;
+        part[blockIdx.x * 4 + 2] = c.hi; part[blockIdx.x * 4 + 3] = c.lo;
+    }
+}
+
+__global__ void k_traces_final(const double* __restrict__ part, double* __restrict__ out /* t1hi,t1lo,t2hi,t2lo */,
+                               const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    if (threadIdx.x != 0) return;
+    dd a = {0, 0}, c = {0, 0};
+    for (int q = 0; q < kTrBlocks; ++q) {
+        a = dd_add(a, dd{part[q * 4 + 0], part[q * 4 + 1]});
+        c = dd_add(c, dd{part[q * 4 + 2], part[q * 4 + 3]});
+    }
+    out[0] = a.hi; out[1] = a.lo; out[2] = c.hi; out[3] = c.lo;
+}
+
+size_t traces_temp_bytes() { return sizeof(double) * 4 * kTrBlocks; }
+
+void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
+                   const double* val, const double* sq, const double* sqlo, double* temp, double* out,
+                   const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_traces_part, dim3(kTrBlocks), dim3(256), 0, s, nslot, cap, b, n, brow, bcol, val, sq, sqlo,
+                       temp, done);
+    hipLaunchKernelGGL(k_traces_final, dim3(1), dim3(64), 0, s, temp, out, done);
+}
+
+}  // namespace spamm

@@ -1,0 +1,275 @@
+// Kept-pair enumeration for Algorithm 2 at the leaf level and the output
+// pattern of the combined product.
+//
+// Row bitmaps of A (bit k of row i when A_ik is present) and column bitmaps
+// of B (bit k of column j when B_kj is present) turn the candidate inner
+// indices of output (i, j) into a word-wise AND.  Outputs are visited in
+// 2D Morton order, so after the scans the output list, the kept-pair list
+// and the slots of the result are all laid out along the linearised
+// quadtree.
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spamm {
+
+__global__ void k_occupancy(MatView M, int mode, uint32_t* __restrict__ bits, int nw, uint8_t* __restrict__ tiles,
+                            int T, int l0, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    int64_t nslot = *M.nslot;
+    if (nslot > M.cap) nslot = M.cap;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslot; s += (int64_t)gridDim.x * blockDim.x) {
+        int r = M.brow[s];
+        if (r < 0) continue;
+        int c = M.bcol[s];
+        if (r >= M.nb || c < 0 || c >= M.nb) continue;
+        int br, bit, tr, tc;
+        if (mode == kOccA) { br = r; bit = c; tr = r; tc = c; }
+        else if (mode == kOccB) { br = c; bit = r; tr = r; tc = c; }
+        else { br = r; bit = c; tr = c; tc = r; }
+        if (bits) atomicOr(&bits[(size_t)br * nw + (bit >> 5)], 1u << (bit & 31));
+        if (tiles) tiles[(size_t)(tr >> l0) * T + (tc >> l0)] = 1;
+    }
+}
+
+void launch_occupancy(const MatView& M, int mode, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0,
+                      const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_occupancy, dim3(grid_for(M.cap, 256, 2048)), dim3(256), 0, s, M, mode, bits, nw, tiles, T,
+                       l0, done);
+}
+
+// Visit the kept inner indices of output (i, j) in ascending k.
+template <typename F>
+SPAMM_DEV void for_each_kept(int i, int j, int nb, int nw, const uint32_t* bitsA, const uint32_t* bitsB,
+                             const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB,
+                             int btrans, double tau, F&& f) {
+    for (int w = 0; w < nw; ++w) {
+        uint32_t m = bitsA[(size_t)i * nw + w] & bitsB[(size_t)j * nw + w];
+        while (m) {
+            int t = __ffs(m) - 1;
+            m &= m - 1;
+            int k = w * 32 + t;
+            int sa = mapA[(size_t)i * nb + k];
+            int sb = btrans ? mapB[(size_t)j * nb + k] : mapB[(size_t)k * nb + j];
+            if (sa < 0 || sb < 0) continue;
+            double p = normA[sa] * normB[sb];
+            if (p >= tau) f(k, sa, sb, p);
+        }
+    }
+}
+
+__global__ void k_kept_count(int nb, int P, int nw, const uint32_t* __restrict__ bitsA,
+                             const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
+                             const double* __restrict__ normA, const int32_t* __restrict__ mapB,
+                             const double* __restrict__ normB, int btrans, int sym, const double* __restrict__ tau_p,
+                             const double* __restrict__ sigma_p, int32_t* __restrict__ cnt,
+                             int32_t* __restrict__ cnt_flag, int32_t* __restrict__ cnt_low,
+                             const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    const double tau = *tau_p;
+    const double sigma = sigma_p ? *sigma_p : 0.0;
+    const int64_t PP = (int64_t)P * P;
+    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < PP; z += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t i, j;
+        demorton2((uint32_t)z, i, j);
+        int c = 0, cl = 0;
+        if ((int)i < nb && (int)j < nb && !(sym && i > j)) {
+            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                          [&](int, int, int, double p) {
+                              ++c;
+                              if (p < sigma) ++cl;
+                          });
+        }
+        cnt[z] = c;
+        cnt_flag[z] = c > 0 ? 1 : 0;
+        if (cnt_low) cnt_low[z] = cl;
+    }
+}
+
+void launch_kept_count(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
+                       const double* normA, const int32_t* mapB, const double* normB, int btrans, int sym,
+                       const double* tau, const double* sigma, int32_t* cnt, int32_t* cnt_flag, int32_t* cnt_low,
+                       const int32_t* done, hipStream_t s) {
+    int64_t PP = (int64_t)P * P;
+    hipLaunchKernelGGL(k_kept_count, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB, mapA,
+                       normA, mapB, normB, btrans, sym, tau, sigma, cnt, cnt_flag, cnt_low, done);
+}
+
+// Pairs of one output: low-precision pairs (tau <= p < sigma) first, then the
+// FP64 ones, each group in ascending k.  Without tiers (sigma null) every
+// pair is FP64.
+__global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ bitsA,
+                            const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
+                            const double* __restrict__ normA, const int32_t* __restrict__ mapB,
+                            const double* __restrict__ normB, int btrans, const double* __restrict__ tau_p,
+                            const double* __restrict__ sigma_p, const int32_t* __restrict__ cnt,
+                            const int32_t* __restrict__ off, const int32_t* __restrict__ oidx,
+                            const int64_t* __restrict__ npairs_p, const int64_t* __restrict__ nout_p, int64_t cap_pairs,
+                            int64_t cap_out, int32_t* __restrict__ oi, int32_t* __restrict__ oj,
+                            int32_t* __restrict__ optr, int2* __restrict__ pairs, int32_t* __restrict__ ovf,
+                            const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    const double tau = *tau_p;
+    const double sigma = sigma_p ? *sigma_p : 0.0;
+    const int64_t PP = (int64_t)P * P;
+    const int64_t npairs = *npairs_p, nout = *nout_p;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (nout <= cap_out) optr[nout] = (int32_t)(npairs <= cap_pairs ? npairs : cap_pairs);
+        if (npairs > cap_pairs) atomicOr(ovf, kOvfPairs);
+        if (nout > cap_out) atomicOr(ovf, kOvfOut);
+    }
+    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < PP; z += (int64_t)gridDim.x * blockDim.x) {
+        if (cnt[z] == 0) continue;
+        uint32_t i, j;
+        demorton2((uint32_t)z, i, j);
+        int64_t o = oidx[z];
+        if (o >= cap_out) continue;
+        oi[o] = (int32_t)i;
+        oj[o] = (int32_t)j;
+        optr[o] = off[z];
+        int64_t w = off[z];
+        if (sigma_p) {
+            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                          [&](int, int sa, int sb, double p) {
+                              if (p < sigma) {
+                                  if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                                  ++w;
+                              }
+                          });
+            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                          [&](int, int sa, int sb, double p) {
+                              if (!(p < sigma)) {
+                                  if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                                  ++w;
+                              }
+                          });
+        } else {
+            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                          [&](int, int sa, int sb, double) {
+                              if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                              ++w;
+                          });
+        }
+    }
+}
+
+void launch_kept_fill(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
+                      const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
+                      const double* sigma, const int32_t* cnt, const int32_t* off, const int32_t* oidx,
+                      const int64_t* npairs, const int64_t* nout, int64_t cap_pairs, int64_t cap_out, int32_t* oi,
+                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* ovf, const int32_t* done, hipStream_t s) {
+    int64_t PP = (int64_t)P * P;
+    hipLaunchKernelGGL(k_kept_fill, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB, mapA,
+                       normA, mapB, normB, btrans, tau, sigma, cnt, off, oidx, npairs, nout, cap_pairs, cap_out, oi,
+                       oj, optr, pairs, ovf, done);
+}
+
+// Output pattern: block (r, c) of the result exists when the product has a
+// kept pair there (its upper-triangle mirror in symmetric mode) or, in the
+// 2X - X^2 branch, when X has the block.
+__global__ void k_hat_flags(int nb, int P, const int32_t* __restrict__ cnt, int sym, const int32_t* __restrict__ mapX,
+                            const int32_t* __restrict__ branch, int32_t* __restrict__ flag,
+                            const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    const int br = branch ? *branch : 0;
+    const int64_t PP = (int64_t)P * P;
+    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < PP; z += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t r, c;
+        demorton2((uint32_t)z, r, c);
+        int f = 0;
+        if ((int)r < nb && (int)c < nb) {
+            uint32_t cz = sym ? morton2(min(r, c), max(r, c)) : (uint32_t)z;
+            f = cnt[cz] > 0;
+            if (!f && mapX && br == 1) f = mapX[(size_t)r * nb + c] >= 0;
+        }
+        flag[z] = f;
+    }
+}
+
+void launch_hat_flags(int nb, int P, const int32_t* cnt, int sym, const int32_t* mapX, const int32_t* branch,
+                      int32_t* flag, const int32_t* done, hipStream_t s) {
+    int64_t PP = (int64_t)P * P;
+    hipLaunchKernelGGL(k_hat_flags, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, cnt, sym, mapX, branch,
+                       flag, done);
+}
+
+__global__ void k_hat_assign(int nb, int P, const int32_t* __restrict__ cnt, int sym, const int32_t* __restrict__ flag,
+                             const int32_t* __restrict__ slot, const int64_t* __restrict__ total, int64_t cap,
+                             int32_t* __restrict__ map, int32_t* __restrict__ brow, int32_t* __restrict__ bcol,
+                             int32_t* __restrict__ nslot, uint8_t* __restrict__ fromc, int32_t* __restrict__ ovf,
+                             const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    const int64_t PP = (int64_t)P * P;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t t = *total;
+        *nslot = (int32_t)(t <= cap ? t : cap);
+        if (t > cap) atomicOr(ovf, kOvfSlots);
+    }
+    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < PP; z += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t r, c;
+        demorton2((uint32_t)z, r, c);
+        if ((int)r >= nb || (int)c >= nb) continue;
+        int32_t m = -1;
+        if (flag[z]) {
+            int64_t sl = slot[z];
+            if (sl < cap) {
+                m = (int32_t)sl;
+                brow[sl] = (int32_t)r;
+                bcol[sl] = (int32_t)c;
+                uint32_t cz = sym ? morton2(min(r, c), max(r, c)) : (uint32_t)z;
+                if (fromc) fromc[sl] = cnt[cz] > 0 ? 1 : 0;
+            }
+        }
+        map[(size_t)r * nb + c] = m;
+    }
+}
+
+void launch_hat_assign(int nb, int P, const int32_t* cnt, int sym, const int32_t* flag, const int32_t* slot,
+                       const int64_t* nslot_total, int64_t cap, int32_t* map, int32_t* brow, int32_t* bcol,
+                       int32_t* nslot, uint8_t* fromc, int32_t* ovf, const int32_t* done, hipStream_t s) {
+    int64_t PP = (int64_t)P * P;
+    hipLaunchKernelGGL(k_hat_assign, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, cnt, sym, flag, slot,
+                       nslot_total, cap, map, brow, bcol, nslot, fromc, ovf, done);
+}
+
+// Blocks of 2X - X^2 that no kept pair touches: X^ = 2 X.
+template <int B>
+__global__ __launch_bounds__(256) void k_rest(const int32_t* __restrict__ nslot_p, int64_t cap,
+                                             const int32_t* __restrict__ brow, const int32_t* __restrict__ bcol,
+                                             const uint8_t* __restrict__ fromc, int nb, const int32_t* __restrict__ mapX,
+                                             const double* __restrict__ valX, double* __restrict__ valH,
+                                             const int32_t* __restrict__ branch, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    if (*branch != 1) return;
+    int64_t nslot = *nslot_p;
+    if (nslot > cap) nslot = cap;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < nslot; s += (int64_t)gridDim.x * 4) {
+        int r = brow[s];
+        if (r < 0 || fromc[s]) continue;
+        int sx = mapX[(size_t)r * nb + bcol[s]];
+        if (sx < 0) continue;
+        const double2* src = reinterpret_cast<const double2*>(valX + (size_t)sx * B * B);
+        double2* dst = reinterpret_cast<double2*>(valH + (size_t)s * B * B);
+        for (int t = lane; t < B * B / 2; t += 64) {
+            double2 v = src[t];
+            v.x = 2.0 * v.x;
+            v.y = 2.0 * v.y;
+            dst[t] = v;
+        }
+    }
+}
+
+void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t* brow, const int32_t* bcol,
+                 const uint8_t* fromc, int nb, const int32_t* mapX, const double* valX, double* valH,
+                 const int32_t* branch, const int32_t* done, hipStream_t s) {
+    int grid = grid_for(cap_hat, 4, 4096);
+    switch (b) {
+        case 32: hipLaunchKernelGGL(k_rest<32>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done); break;
+        case 64: hipLaunchKernelGGL(k_rest<64>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done); break;
+        case 128: hipLaunchKernelGGL(k_rest<128>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done); break;
+    }
+}
+
+}  // namespace spamm

@@ -1,0 +1,148 @@
+// A1: the starting matrix of the purification.  Gerschgorin discs bound the
+// spectrum of F by [lmin, lmax]; X_0 = (lmax I - F) / (lmax - lmin) maps it
+// into [0, 1] with occupied states near 1.  X_0 has the block pattern of F
+// plus every diagonal block.
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace spamm {
+
+// per-row disc: centre f_rr, radius RN(sum_{c != r} |f_rc|) (double-double sum)
+__global__ void k_gersch_rows(MatView F, double* __restrict__ lo, double* __restrict__ hi) {
+    const int64_t n = F.n;
+    const int b = F.b, nb = F.nb;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        const int I = (int)(g / b), r = (int)(g % b);
+        dd rad = {0.0, 0.0};
+        double cen = 0.0;
+        for (int J = 0; J < nb; ++J) {
+            const int s = F.map[(size_t)I * nb + J];
+            if (s < 0) continue;
+            const double* v = F.val + (size_t)s * b * b;
+            for (int c = 0; c < b; ++c) {
+                const int64_t gj = (int64_t)J * b + c;
+                if (gj >= n) break;
+                const double x = v[(size_t)c * b + r];
+                if (gj == g) cen = x;
+                else rad = dd_add(rad, dd{fabs(x), 0.0});
+            }
+        }
+        const double R = rad.hi;
+        lo[g] = cen - R;
+        hi[g] = cen + R;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_gersch_final(const double* __restrict__ lo, const double* __restrict__ hi,
+                                                      int64_t n, double* __restrict__ lam) {
+    __shared__ double sl[1024], sh[1024];
+    double a = INFINITY, z = -INFINITY;
+    for (int64_t g = threadIdx.x; g < n; g += blockDim.x) {
+        a = fmin(a, lo[g]);
+        z = fmax(z, hi[g]);
+    }
+    sl[threadIdx.x] = a;
+    sh[threadIdx.x] = z;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + st]);
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        lam[0] = sl[0];
+        lam[1] = sh[0];
+    }
+}
+
+void launch_gersch(const MatView& F, double* rowtmp, double* lam, hipStream_t s) {
+    hipLaunchKernelGGL(k_gersch_rows, dim3(grid_for(F.n, 256, 4096)), dim3(256), 0, s, F, rowtmp, rowtmp + F.n);
+    hipLaunchKernelGGL(k_gersch_final, dim3(1), dim3(1024), 0, s, rowtmp, rowtmp + F.n, F.n, lam);
+}
+
+__global__ void k_x0_diagflags(MatView F, int32_t* __restrict__ flag) {
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < F.nb; d += gridDim.x * blockDim.x)
+        flag[d] = F.map[(size_t)d * F.nb + d] < 0 ? 1 : 0;
+}
+
+__global__ void k_x0_meta(MatView F, MatView X, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                          const int64_t* __restrict__ nmiss) {
+    int64_t nf = *F.nslot;
+    if (nf > F.cap) nf = F.cap;
+    const int64_t tot = nf + *nmiss;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *X.nslot = (int32_t)(tot <= X.cap ? tot : X.cap);
+    const int nb = F.nb;
+    const int64_t nn = (int64_t)nb * nb;
+    const int64_t span = nn > nf ? nn : nf;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < span; t += (int64_t)gridDim.x * blockDim.x) {
+        if (t < nf && t < X.cap) {
+            X.brow[t] = F.brow[t];
+            X.bcol[t] = F.bcol[t];
+        }
+        if (t < nn) X.map[t] = F.map[t];
+    }
+}
+
+__global__ void k_x0_diagslots(MatView F, MatView X, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos) {
+    int64_t nf = *F.nslot;
+    if (nf > F.cap) nf = F.cap;
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < F.nb; d += gridDim.x * blockDim.x) {
+        if (!flag[d]) continue;
+        const int64_t s = nf + pos[d];
+        if (s >= X.cap) continue;
+        X.brow[s] = d;
+        X.bcol[s] = d;
+        X.map[(size_t)d * F.nb + d] = (int32_t)s;
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_x0_vals(MatView F, MatView X, const double* __restrict__ lam) {
+    int64_t nf = *F.nslot;
+    if (nf > F.cap) nf = F.cap;
+    int64_t nx = *X.nslot;
+    if (nx > X.cap) nx = X.cap;
+    const double lmin = lam[0], lmax = lam[1];
+    const double W = lmax - lmin;
+    const int64_t n = F.n;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < nx; s += (int64_t)gridDim.x * 4) {
+        const int r = X.brow[s];
+        if (r < 0) continue;
+        const int c = X.bcol[s];
+        const double* src = s < nf ? F.val + (size_t)s * B * B : nullptr;
+        double* dst = X.val + (size_t)s * B * B;
+        for (int t = lane; t < B * B; t += 64) {
+            const int col = t / B, row = t % B;
+            const int64_t gi = (int64_t)r * B + row, gj = (int64_t)c * B + col;
+            const double f = src ? src[t] : 0.0;
+            double x;
+            if (gi >= n || gj >= n) x = 0.0;
+            else if (gi == gj) x = (lmax - f) / W;
+            else x = (-f) / W;
+            dst[t] = x;
+        }
+    }
+}
+
+void launch_x0(const MatView& F, const double* lam, const MatView& X, int32_t* diagflag, int32_t* diagpos,
+               void* scan_temp, int64_t* tmp_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_x0_diagflags, dim3(grid_for(F.nb, 256, 64)), dim3(256), 0, s, F, diagflag);
+    scan_i32(diagflag, diagpos, F.nb, nullptr, tmp_count, scan_temp, s);
+    const int64_t nn = (int64_t)F.nb * F.nb;
+    hipLaunchKernelGGL(k_x0_meta, dim3(grid_for(nn > F.cap ? nn : F.cap, 256, 4096)), dim3(256), 0, s, F, X, diagflag,
+                       diagpos, tmp_count);
+    hipLaunchKernelGGL(k_x0_diagslots, dim3(grid_for(F.nb, 256, 64)), dim3(256), 0, s, F, X, diagflag, diagpos);
+    const int grid = grid_for(X.cap, 4, 4096);
+    switch (F.b) {
+        case 32: hipLaunchKernelGGL(k_x0_vals<32>, dim3(grid), dim3(256), 0, s, F, X, lam); break;
+        case 64: hipLaunchKernelGGL(k_x0_vals<64>, dim3(grid), dim3(256), 0, s, F, X, lam); break;
+        case 128: hipLaunchKernelGGL(k_x0_vals<128>, dim3(grid), dim3(256), 0, s, F, X, lam); break;
+    }
+}
+
+}  // namespace spamm
