@@ -29,6 +29,10 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def load_spectrum(name):
     path = os.path.join(ROOT, "tests", "golden", "spectra.json")
     with open(path) as f:
@@ -73,8 +77,10 @@ def main():
     def run_once(keep=False):
         return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap, max_pairs=max_pairs)
 
-    for _ in range(args.warmup):
+    log(f"input ready: n={n} leaf={b} blocks={Fh.nblk}")
+    for w in range(args.warmup):
         run_once()
+        log(f"warmup {w + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     times, flops, gemm_ms, gemm_flops, logs_all = [], 0.0, 0.0, 0.0, []
     res = None
@@ -85,6 +91,7 @@ def main():
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         steps = [l for l in res.logs if l["branch"] >= 0]
+        log(f"step {len(times)}/{args.steps}: {times[-1]:.3f} s, {len(steps)} iterations")
         f = sum(l["npairs"] for l in steps) * 2.0 * b ** 3
         flops += f
         gemm_ms += sum(l["ms_gemm"] for l in steps)
@@ -141,6 +148,7 @@ def main():
         del Fd, U, Uo, Dref
 
     if not args.no_cpu:
+        log("timing the oracle on a sample (cpu baseline)")
         out["cpu_baseline"] = cpu_baseline(res, Fh, taus, b, args.cpu_seconds)
 
     print(json.dumps(out), flush=True)
