@@ -413,6 +413,22 @@ def combine(X: BSM, C: BSM, branch: int) -> BSM:
     return BSM(X.n, b, (keys // nb).astype(np.int32), (keys % nb).astype(np.int32), vals)
 
 
+def tier_constant(precision: int, b: int) -> float:
+    """Per-pair rounding factor of the FP32 leaf-product tier (not in the
+    paper): inputs rounded to FP32 (unit roundoff u = 2^-24 each) and b-term
+    products accumulated in FP32 with an assumed unit roundoff of 2u give
+    |fl(AB) - AB| <= (2u + u^2 + gamma_b(2u) (1+u)^2) |A||B| entrywise,
+    gamma_m(x) = m x / (1 - m x), hence ||fl(AB) - AB||_F <= c ||A||_F ||B||_F
+    (Cauchy-Schwarz per entry).  Rounded up by a factor 1 + 2^-40."""
+    if precision != 1:
+        return 0.0
+    u = 2.0 ** -24
+    ue = 2.0 * u
+    m = float(b)
+    gam = m * ue / (1.0 - m * ue)
+    return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 2.0 ** -40)
+
+
 @dataclass
 class SP2Params:
     n_occ: int
@@ -424,6 +440,8 @@ class SP2Params:
     variant: str = "hybrid"       # "hybrid" (Alg. 5), "spamm" (Alg. 4), "truncmul" (Alg. 1)
     delta_const: float = float("nan")  # explicit per-step delta when no gap is given
     e_tol: float = 0.0
+    precision: int = 0            # 1: FP32 tier for tau <= p < sigma (rounding folded into the bound)
+    tier_split: float = 0.5       # share of the product budget given to skipping when tiered
 
 
 @dataclass
@@ -479,6 +497,9 @@ class StepLog:
     t1: float
     t2: float
     e: float
+    sidx: int = -1
+    sigma: float = 0.0
+    npairs_low: int = 0
 
 
 def sp2_step(X: BSM, st: SP2State, p: SP2Params):
@@ -495,20 +516,31 @@ def sp2_step(X: BSM, st: SP2State, p: SP2Params):
     delta = step_delta(p, xh - xl)
     taus = np.asarray(p.taus, dtype=np.float64)
     nu = norms(X)[1]
+    budget = delta / 2.0 if p.variant == "hybrid" else delta
     if p.variant == "truncmul":
         bound, idx, tau = np.zeros(len(taus)), len(taus), 0.0
     else:
-        budget = delta / 2.0 if p.variant == "hybrid" else delta
+        skip_budget = p.tier_split * budget if p.precision else budget
         bound = cse_tree(X, X, taus, nu, nu)
-        idx, tau = select(bound, taus, budget)
+        idx, tau = select(bound, taus, skip_budget)
+    sidx, sigma, nlow = len(taus), 0.0, 0
+    if p.precision:
+        # the largest low-precision limit whose bound (skipped p, plus c p for
+        # pairs evaluated in the low tier) stays below the product budget
+        c_low = tier_constant(p.precision, X.b)
+        bound2 = cse_tree(X, X, taus, nu, nu, mode=1, tau0=tau, c_low=c_low)
+        sidx, sigma = select(bound2, taus, budget)
     C, K = spamm(X, X, tau, sym=True, nuA=nu, nuB=nu)
+    if p.precision:
+        nlow = int(kept(X, X, tau, True, nu, nu).npairs - kept(X, X, max(sigma, tau), True, nu, nu).npairs) \
+            if sigma > tau else 0
     Xh = combine(X, C, br)
     if p.variant == "spamm":
         Xt, ti = Xh.sorted(), None
     else:
         tb = delta / 2.0 if p.variant == "hybrid" else delta
         Xt, ti = truncate(Xh.sorted(), tb)
-    log = StepLog(st.i, br, delta, bound, idx, tau, K.npairs, int(K.oi.shape[0]), ti, t1, t2, e)
+    log = StepLog(st.i, br, delta, bound, idx, tau, K.npairs, int(K.oi.shape[0]), ti, t1, t2, e, sidx, sigma, nlow)
     return Xt, Xh, log, SP2State(st.i + 1, xh, xl, e_hist)
 
 

@@ -284,3 +284,50 @@ def test_paper_tau_list():
     assert t.shape[0] == fx["N"] and t[0] == fx["first"]
     assert np.all(t[1:] < t[:-1])
     assert abs(math.log10(t[-1]) - fx["last_order_of_magnitude"]) < 0.5
+
+
+# ---------------------------------------------------------------------------
+# precision-tier mode of the bound (mixed-precision leaf products)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_tier_mode_special_cases(seed):
+    rng = np.random.default_rng(300 + seed)
+    A = rand_bsm(rng, 6, 3, 0.7, decay=0.8)
+    B = rand_bsm(rng, 6, 3, 0.7, decay=0.8, n=A.n)
+    taus = synth.tau_log(24, -12.0) * 10.0
+    base = oracle.cse_tree(A, B, taus)
+    for t0 in [taus[5], taus[12], 0.0]:
+        b0 = oracle.cse_tree(A, B, np.array([t0 if t0 > 0 else 1e-300]))[0]
+        # no low tier below tau0: every sigma <= tau0 gives the plain bound at tau0
+        low = np.array([t for t in taus if t <= t0]) if t0 > 0 else np.array([1e-300])
+        if low.size:
+            m1 = oracle.cse_tree(A, B, low, mode=1, tau0=t0, c_low=0.3)
+            assert np.all(m1 == b0)
+        # c = 1: the tier costs as much as skipping, i.e. the plain bound at sigma
+        hi = np.array([t for t in taus if t >= t0])
+        m1 = oracle.cse_tree(A, B, hi, mode=1, tau0=t0, c_low=1.0)
+        assert np.array_equal(m1, base[:hi.shape[0]])
+        # c = 0: a free tier gives the plain bound at tau0 for every sigma
+        m0 = oracle.cse_tree(A, B, hi, mode=1, tau0=t0, c_low=0.0)
+        assert np.all(m0 == b0)
+
+
+@pytest.mark.parametrize("b", [32, 64])
+def test_fp32_tier_constant_bounds_fp32_products(b):
+    """||fl32(A) fl32(B) (FP32 arithmetic) - AB||_F <= c_32 ||A||_F ||B||_F."""
+    rng = np.random.default_rng(b)
+    c = oracle.tier_constant(1, b)
+    assert 3e-6 < c < 1e-5
+    worst = 0.0
+    for _ in range(200):
+        A = rng.standard_normal((b, b)) * np.exp(rng.uniform(-20, 5))
+        B = rng.standard_normal((b, b)) * np.exp(rng.uniform(-20, 5))
+        if rng.random() < 0.3:
+            A = np.abs(A); B = np.abs(B)            # no cancellation: the worst case for the bound
+        P32 = (A.astype(np.float32) @ B.astype(np.float32)).astype(np.float64)
+        err = np.linalg.norm(P32 - A @ B)
+        ratio = err / (np.linalg.norm(A) * np.linalg.norm(B))
+        worst = max(worst, ratio)
+        assert ratio <= c
+    assert worst > 1e-9                             # the FP32 path really rounded

@@ -104,3 +104,20 @@ def test_other_variants_step_conditions(variant):
             assert log.tau == 0.0
         X = Xn
     assert np.linalg.norm(X.to_dense() - Dref) < 1e-6
+
+
+def test_fp32_tier_selection_converges():
+    """The tiered selection (tau from half the budget, then the largest sigma
+    whose Algorithm 3 bound with folded c_32 p terms fits the budget) keeps
+    every step within delta/2 (the oracle's products are FP64, so this checks
+    the budget split) and converges."""
+    n = 768
+    F = oracle.BSM.of(synth.sys3d(n, 7, 32))
+    Dref, w = eigh_density(F, n // 2)
+    p = oracle.SP2Params(n_occ=n // 2, eps=1e-6, taus=synth.tau_log(32), homo=w[n // 2 - 1], lumo=w[n // 2],
+                         precision=1)
+    D, logs, info = oracle.sp2(F, p)
+    steps = [l for l in logs if l.branch >= 0]
+    assert any(l.npairs_low > 0 for l in steps)
+    assert all(l.sigma == 0.0 or l.sigma > l.tau for l in steps if l.npairs_low > 0)
+    assert np.linalg.norm(D.to_dense() - Dref) < 1e-6
