@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verify", action="store_true", help="check ||D - D~||_F with a dense eigensolver")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision purification")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -74,8 +77,9 @@ def main():
     max_pairs = nb * nb * (nb + 1) // 2
     eps = 1e-6
 
-    def run_once(keep=False):
-        return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap, max_pairs=max_pairs)
+    def run_once(precision="fp64"):
+        return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap, max_pairs=max_pairs,
+                        precision=precision)
 
     log(f"input ready: n={n} leaf={b} blocks={Fh.nblk}")
     for w in range(args.warmup):
@@ -131,6 +135,29 @@ def main():
                      "flops_per_launch": gemm_flops / ngemm},
     }
 
+    # mixed precision (FP32 leaf-product tier) on the same workload
+    res_mixed = None
+    if not args.no_mixed:
+        run_once("fp32")
+        mtimes = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res_mixed = run_once("fp32")
+            torch.cuda.synchronize()
+            mtimes.append(time.perf_counter() - t0)
+        msteps = [l for l in res_mixed.logs if l["branch"] >= 0]
+        mpairs = sum(l["npairs"] for l in msteps)
+        mlow = sum(l["npairs_low"] for l in msteps)
+        log(f"mixed: {float(np.median(mtimes)):.3f} s, {len(msteps)} iterations, low-tier share {mlow / max(mpairs, 1):.3f}")
+        out["mixed"] = {"precision": "fp32 tier", "sp2_time_s": round(float(np.median(mtimes)), 4),
+                        "iterations": len(msteps), "kept_pairs_per_run": int(mpairs),
+                        "low_tier_pairs_per_run": int(mlow),
+                        "kept_TFLOP_per_s": round(mpairs * 2.0 * b ** 3 / float(np.median(mtimes)) / 1e12, 4),
+                        "speedup_vs_fp64": round(float(np.median(times)) / float(np.median(mtimes)), 4),
+                        "phase_ms_per_run": {k: round(sum(l[k] for l in msteps), 3)
+                                             for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc")}}
+
     if args.verify:
         D = res.D.to_host()
         Dd = np.zeros((n, n))
@@ -145,7 +172,26 @@ def main():
         Dref = Uo @ Uo.T
         err = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
         out["verify_fro_err"] = err
+        if res_mixed is not None:
+            Dm = res_mixed.D.to_host()
+            Dd[:] = 0.0
+            for k in range(Dm.brow.shape[0]):
+                r, c = int(Dm.brow[k]), int(Dm.bcol[k])
+                blk = Dm.vals[k].T
+                rr, cc = min(b, n - r * b), min(b, n - c * b)
+                Dd[r * b:r * b + rr, c * b:c * b + cc] = blk[:rr, :cc]
+            out["mixed"]["verify_fro_err"] = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
+        log(f"verified: fp64 {err:.3e}" + (f", mixed {out['mixed']['verify_fro_err']:.3e}" if res_mixed else ""))
         del Fd, U, Uo, Dref
+
+    if args.copy_mb:
+        src = torch.ones(args.copy_mb * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"plain copy of {args.copy_mb} MiB done")
+        del src, dst
 
     if not args.no_cpu:
         log("timing the oracle on a sample (cpu baseline)")

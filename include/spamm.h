@@ -133,6 +133,24 @@ int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev
  * removed sum of w*sq}; may be NULL.
  * Workspace: spamm_truncate_workspace_bytes(cap).
  */
+/*
+ * SpAMM product with an FP32 precision tier (mixed-precision leaf products;
+ * not in the paper): kept pairs with tau <= p < sigma use FP32 copies of the
+ * blocks on FP32 MFMA, each pair's FP32 product added into the FP64
+ * accumulator, so ||fl(A_ik B_kj) - A_ik B_kj||_F <= c_32 p with
+ * c_32 = 2u + u^2 + gamma_b(2u)(1+u)^2, u = 2^-24 (spamm_tier_constant).
+ * Pairs with p >= sigma are FP64.  Leaf 32 or 64.  kept_out: device [3] =
+ * {kept pairs, output blocks, low-tier pairs}; may be NULL.
+ * Workspace: spamm_multiply_tiered_workspace_bytes(nb, capA, capB, b, max_pairs).
+ */
+size_t spamm_multiply_tiered_workspace_bytes(int32_t nb, int64_t capA, int64_t capB, int32_t b, int64_t max_pairs);
+int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev, const double* sigma_dev,
+                          uint32_t flags, spamm_bsm* C, int64_t* kept_out, void* ws, size_t ws_bytes,
+                          spamm_stream_t stream);
+/* c_t of a precision tier (1 = FP32) for leaf size b: the per-pair factor of
+ * the rounding bound ||fl(A B) - A B||_F <= c_t ||A||_F ||B||_F. */
+double spamm_tier_constant(int32_t precision, int32_t b);
+
 size_t spamm_truncate_workspace_bytes(int64_t cap);
 int spamm_truncate(spamm_bsm* X, double delta, uint32_t flags, double* removed_out, void* ws,
                    size_t ws_bytes, spamm_stream_t stream);
@@ -149,7 +167,8 @@ typedef struct sp2_params {
     double delta_const;  /* explicit per-step delta when homo/lumo are NaN (else NaN) */
     double e_tol;        /* stop when |tr X - ||X||_F^2| <= e_tol (0: noise-floor rule only) */
     int32_t keep_tape;   /* nonzero: keep every X~_i in the workspace (adjoint, inspection) */
-    int32_t reserved;
+    int32_t precision;   /* 0 FP64 leaf products; 1 FP32 tier for pairs with tau <= p < sigma (leaf 32/64) */
+    double tier_split;   /* share of the product budget given to skipping when precision != 0 (e.g. 0.5) */
 } sp2_params;
 
 /* Per-iteration record written by purify_sp2 (host memory). */
@@ -159,6 +178,9 @@ typedef struct sp2_iter_log {
     int64_t npairs, nout, nslot_hat, nslot_kept, removed_units;
     double removed_fro2;
     float ms_sweep, ms_pairs, ms_gemm, ms_norms, ms_trunc, ms_total;
+    int64_t npairs_low;  /* pairs evaluated in the low-precision tier */
+    double sigma;        /* low-precision limit of the step (0: none) */
+    int32_t sidx, pad;
 } sp2_iter_log;
 
 /*
@@ -171,11 +193,11 @@ typedef struct sp2_iter_log {
  *   F     : symmetric input with norms NOT required (computed internally).
  *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise).
  *   log   : host [n_max + 2] records; nlog_out: records written.
- * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, keep_tape ? n_max : 0).
+ * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, keep_tape ? n_max : 0, precision).
  * Reads scalars back every iteration (synchronises the stream).
  */
 size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
-                                  int32_t tape_steps);
+                                  int32_t tape_steps, int32_t precision);
 int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out,
                void* ws, size_t ws_bytes, spamm_stream_t stream);
 

@@ -53,7 +53,8 @@ class sp2_params(ctypes.Structure):
     _fields_ = [("n_occ", ctypes.c_int64), ("eps", ctypes.c_double), ("n_max", ctypes.c_int32),
                 ("variant", ctypes.c_int32), ("tau", ctypes.c_void_p), ("N", ctypes.c_int32),
                 ("homo", ctypes.c_double), ("lumo", ctypes.c_double), ("delta_const", ctypes.c_double),
-                ("e_tol", ctypes.c_double), ("keep_tape", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("e_tol", ctypes.c_double), ("keep_tape", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("tier_split", ctypes.c_double)]
 
 
 class sp2_iter_log(ctypes.Structure):
@@ -63,7 +64,9 @@ class sp2_iter_log(ctypes.Structure):
                 ("nout", ctypes.c_int64), ("nslot_hat", ctypes.c_int64), ("nslot_kept", ctypes.c_int64),
                 ("removed_units", ctypes.c_int64), ("removed_fro2", ctypes.c_double),
                 ("ms_sweep", ctypes.c_float), ("ms_pairs", ctypes.c_float), ("ms_gemm", ctypes.c_float),
-                ("ms_norms", ctypes.c_float), ("ms_trunc", ctypes.c_float), ("ms_total", ctypes.c_float)]
+                ("ms_norms", ctypes.c_float), ("ms_trunc", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("npairs_low", ctypes.c_int64), ("sigma", ctypes.c_double), ("sidx", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -90,11 +93,16 @@ def lib() -> ctypes.CDLL:
     L.spamm_truncate_workspace_bytes.argtypes = [i64]
     L.spamm_truncate_workspace_bytes.restype = sz
     L.spamm_truncate.argtypes = [B, d, u32, P, P, sz, P]
-    L.purify_sp2_workspace_bytes.argtypes = [i32, i32, i32, i64, i64, i32]
+    L.purify_sp2_workspace_bytes.argtypes = [i32, i32, i32, i64, i64, i32, i32]
     L.purify_sp2_workspace_bytes.restype = sz
     L.purify_sp2.argtypes = [B, ctypes.POINTER(sp2_params), B, ctypes.POINTER(sp2_iter_log),
                              ctypes.POINTER(i32), P, sz, P]
     L.purify_sp2_tape_view.argtypes = [P, i32, i32, i32, i64, i64, i32, i32, B]
+    L.spamm_multiply_tiered_workspace_bytes.argtypes = [i32, i64, i64, i32, i64]
+    L.spamm_multiply_tiered_workspace_bytes.restype = sz
+    L.spamm_multiply_tiered.argtypes = [B, B, P, P, u32, B, P, P, sz, P]
+    L.spamm_tier_constant.argtypes = [i32, i32]
+    L.spamm_tier_constant.restype = d
     L.spamm_status_str.argtypes = [ctypes.c_int]
     L.spamm_status_str.restype = ctypes.c_char_p
     L.spamm_last_error.restype = ctypes.c_char_p
@@ -314,6 +322,33 @@ def multiply(A: BlockSparse, B: BlockSparse, tau, symmetric=False, b_transposed=
     return C, kept
 
 
+def multiply_tiered(A: BlockSparse, B: BlockSparse, tau, sigma, symmetric=False, b_transposed=False, cap=None,
+                    max_pairs=None):
+    """SpAMM with an FP32 tier for pairs with tau <= p < sigma.  Returns
+    (C, kept[3] = pairs, outputs, low-tier pairs)."""
+    dev = A.device
+    nb = A.nb
+    if cap is None:
+        cap = nb * nb
+    if max_pairs is None:
+        max_pairs = max(1, nb * nb * nb // (2 if symmetric else 1))
+    C = BlockSparse(A.n, A.b, cap, dev)
+    tau_t = torch.tensor([float(tau)], dtype=torch.float64, device=dev)
+    sig_t = torch.tensor([float(sigma)], dtype=torch.float64, device=dev)
+    kept = torch.zeros(3, dtype=torch.int64, device=dev)
+    base = lib().spamm_multiply_tiered_workspace_bytes(nb, A.cap, B.cap, A.b, 0)
+    ws = _ws(base + 8 * int(max_pairs) + 1024, dev)
+    flags = (SYMMETRIC if symmetric else 0) | (B_TRANSPOSED if b_transposed else 0)
+    _check(lib().spamm_multiply_tiered(ctypes.byref(A.struct()), ctypes.byref(B.struct()), _ptr(tau_t), _ptr(sig_t),
+                                       flags, ctypes.byref(C.struct()), _ptr(kept), _ptr(ws), ws.numel(), _stream()))
+    return C, kept
+
+
+def tier_constant(precision: int, b: int) -> float:
+    """Per-pair rounding factor c_t of a precision tier (1 = FP32)."""
+    return float(lib().spamm_tier_constant(int(precision), int(b)))
+
+
 def truncate(X: BlockSparse, delta: float, sync=False):
     """Remove symmetric units with ||E||_F < delta (in place).  Returns
     removed[2] = (units, bound of the removed squared norm)."""
@@ -344,7 +379,7 @@ class PurifyResult:
 
 def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo=float("nan"),
            variant="hybrid", n_max=60, delta_const=float("nan"), e_tol=0.0, cap=None, max_pairs=None,
-           keep_tape=False) -> PurifyResult:
+           keep_tape=False, precision="fp64", tier_split=0.5) -> PurifyResult:
     """SP2 purification with SpAMM and error control (Algorithms 1, 4, 5)."""
     dev = F.device
     nb, b = F.nb, F.b
@@ -355,12 +390,13 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
     if max_pairs is None:
         max_pairs = max(1, nb * nb * (nb + 1) // 2)
     tape_steps = n_max if keep_tape else 0
-    base = lib().purify_sp2_workspace_bytes(nb, b, N, int(cap), 0, tape_steps)
+    prec = {"fp64": 0, "fp32": 1}[precision]
+    base = lib().purify_sp2_workspace_bytes(nb, b, N, int(cap), 0, tape_steps, prec)
     ws = _ws(base + 8 * int(max_pairs) + 1024, dev)
     mp = (ws.numel() - base - 512) // 8   # the pair capacity the library derives
     D = BlockSparse(F.n, b, cap, dev)
     p = sp2_params(int(n_occ), float(eps), int(n_max), VARIANTS[variant], taus.data_ptr(), N, float(homo),
-                   float(lumo), float(delta_const), float(e_tol), 1 if keep_tape else 0, 0)
+                   float(lumo), float(delta_const), float(e_tol), 1 if keep_tape else 0, prec, float(tier_split))
     logs = (sp2_iter_log * (n_max + 2))()
     nlog = ctypes.c_int32(0)
     rc = lib().purify_sp2(ctypes.byref(F.struct()), ctypes.byref(p), ctypes.byref(D.struct()), logs,

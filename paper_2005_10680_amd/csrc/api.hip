@@ -163,7 +163,7 @@ struct MulWs {
     int nb, P, nw;
     int64_t PP, cap_out, cap_pairs;
     uint32_t *bitsA, *bitsB;
-    int32_t *cnt, *cflag, *off, *oidx, *oi, *oj, *optr, *hflag, *hslot;
+    int32_t *cnt, *cflag, *off, *oidx, *oi, *oj, *optr, *hflag, *hslot, *cnt_low, *olow;
     int2* pairs;
     int64_t* sc;  // [8]: npairs, nout, nslot_total
     int32_t* counters;
@@ -189,6 +189,8 @@ void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
     w.oi = c.take<int32_t>(w.cap_out);
     w.oj = c.take<int32_t>(w.cap_out);
     w.optr = c.take<int32_t>(w.cap_out + 1);
+    w.cnt_low = c.take<int32_t>(w.PP);
+    w.olow = c.take<int32_t>(w.cap_out);
     w.pairs = c.take<int2>(w.cap_pairs > 0 ? w.cap_pairs : 1);
     w.sc = c.take<int64_t>(8);
     w.counters = c.take<int32_t>(16);
@@ -198,21 +200,23 @@ void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
 
 // Kept pairs of SpAMM(A, B, *tau) and the output pattern written into C
 // (map, brow, bcol, nslot); with X given, the pattern of 2X - C (branch 1).
-void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const double* tau_dev, const MatView& C,
-               uint8_t* fromc, MulWs& w, const int32_t* mapX, const int32_t* branch_dev, const int32_t* done,
-               hipStream_t s) {
+void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const double* tau_dev, const double* sigma_dev,
+               const MatView& C, uint8_t* fromc, MulWs& w, const int32_t* mapX, const int32_t* branch_dev,
+               const int32_t* done, hipStream_t s) {
     const int nb = A.nb;
     fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
     fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
     launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
     launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
-    launch_kept_count(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, nullptr,
-                      w.cnt, w.cflag, nullptr, done, s);
+    launch_kept_count(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, sigma_dev,
+                      w.cnt, w.cflag, sigma_dev ? w.cnt_low : nullptr, done, s);
     scan_i32(w.cnt, w.off, w.PP, nullptr, &w.sc[0], w.scan_tmp, s);
     scan_i32(w.cflag, w.oidx, w.PP, nullptr, &w.sc[1], w.scan_tmp, s);
-    launch_kept_fill(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, tau_dev, nullptr, w.cnt,
-                     w.off, w.oidx, &w.sc[0], &w.sc[1], w.cap_pairs, w.cap_out, w.oi, w.oj, w.optr, w.pairs, w.ovf,
-                     done, s);
+    if (sigma_dev) scan_i32(w.cnt_low, w.hslot, w.PP, nullptr, &w.sc[3], w.scan_tmp, s);  // total low pairs
+    else fill_i64(&w.sc[3], 1, 0, s);
+    launch_kept_fill(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, tau_dev, sigma_dev, w.cnt,
+                     w.off, w.oidx, &w.sc[0], &w.sc[1], w.cap_pairs, w.cap_out, w.oi, w.oj, w.optr, w.pairs,
+                     sigma_dev ? w.olow : nullptr, w.ovf, done, s);
     launch_hat_flags(nb, w.P, w.cnt, sym, mapX, branch_dev, w.hflag, done, s);
     scan_i32(w.hflag, w.hslot, w.PP, nullptr, &w.sc[2], w.scan_tmp, s);
     launch_hat_assign(nb, w.P, w.cnt, sym, w.hflag, w.hslot, &w.sc[2], C.cap, C.map, C.brow, C.bcol, C.nslot, fromc,
@@ -222,7 +226,7 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
 // Leaf products of the kept pairs into C's slots (combined with X when given).
 void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatView& C, const uint8_t* fromc,
               MulWs& w, const int32_t* mapX, const double* valX, const int32_t* branch_dev, const int32_t* done,
-              hipStream_t s) {
+              hipStream_t s, const float* valA32 = nullptr, const float* valB32 = nullptr) {
     const int nb = A.nb;
     GemmArgs g;
     g.b = A.b;
@@ -245,6 +249,9 @@ void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const Mat
     g.counters = w.counters;
     g.ovf = w.ovf;
     g.done = done;
+    g.valA32 = valA32;
+    g.valB32 = valB32;
+    g.olow = valA32 ? w.olow : nullptr;
     launch_gemm_f64(g, num_cus(), s);
     if (mapX) launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s);
 }
@@ -276,6 +283,18 @@ double dd_diff(double ahi, double alo, double bhi, double blo) {
     double e = (ahi - (s - bb)) + (-bhi - bb);
     e = e + (alo - blo);
     return s + e;
+}
+
+// c_t of the FP32 tier: inputs rounded to FP32 (u = 2^-24 each), products
+// of length b accumulated by the FP32 MFMA with an assumed unit roundoff of
+// 2u (no better than round-to-nearest is assumed), so
+// |fl(AB) - AB| <= (2u + u^2 + gamma_b(2u)(1+u)^2) |A||B| entrywise and
+// ||fl(AB) - AB||_F <= c ||A||_F ||B||_F.  Rounded up by 2^-40.
+double tier_constant(int precision, int b) {
+    if (precision != 1) return 0.0;
+    const double u = 0x1p-24, ue = 2.0 * u, m = (double)b;
+    const double gam = m * ue / (1.0 - m * ue);
+    return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 0x1p-40);
 }
 
 double trunc_quantum(double delta) {
@@ -335,10 +354,13 @@ struct Sp2Ws {
     int32_t* dpos;
     int64_t* dcount;
     double* bound;  // [N]
+    double* bound2; // [N] sweep over the low-precision limit
+    float* x32;     // FP32 copy of the current iterate (precision tier)
     Sp2Ctl* ctl;
 };
 
-void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, int tape_steps, Sp2Ws& w) {
+void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, int tape_steps, Sp2Ws& w,
+               int precision = 0) {
     const int64_t n = (int64_t)nb * b;
     carve_mat(c, n, b, cap, w.X[0]);
     carve_mat(c, n, b, cap, w.X[1]);
@@ -357,7 +379,9 @@ void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, 
     w.dpos = c.take<int32_t>(nb);
     w.dcount = c.take<int64_t>(2);
     w.bound = c.take<double>(N);
+    w.bound2 = c.take<double>(N);
     w.ctl = c.take<Sp2Ctl>(1);
+    w.x32 = precision ? c.take<float>((size_t)cap * b * b) : nullptr;
 }
 
 }  // namespace
@@ -465,7 +489,7 @@ int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev
     carve_mul(c, A->nb, max_pairs, w);
     if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
     fill_i32(w.ovf, 1, 0, s);
-    run_pairs(view(A), view(B), btrans, sym, tau_dev, view(C), nullptr, w, nullptr, nullptr, nullptr, s);
+    run_pairs(view(A), view(B), btrans, sym, tau_dev, nullptr, view(C), nullptr, w, nullptr, nullptr, nullptr, s);
     run_gemm(view(A), view(B), btrans, sym, view(C), nullptr, w, nullptr, nullptr, nullptr, nullptr, s);
     HIP_TRY(hipGetLastError());
     int64_t sc[3];
@@ -482,6 +506,61 @@ int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev
         return fail(SPAMM_ECAPACITY, "capacity exceeded: pairs %lld (cap %lld), slots %lld (cap %lld)",
                     (long long)sc[0], (long long)max_pairs, (long long)sc[2], (long long)C->cap);
     }
+    return SPAMM_OK;
+}
+
+double spamm_tier_constant(int32_t precision, int32_t b) { return tier_constant(precision, b); }
+
+size_t spamm_multiply_tiered_workspace_bytes(int32_t nb, int64_t capA, int64_t capB, int32_t b, int64_t max_pairs) {
+    if (nb < 1) return 0;
+    Carver c(nullptr);
+    c.take<float>((size_t)capA * b * b);
+    c.take<float>((size_t)capB * b * b);
+    MulWs w;
+    carve_mul(c, nb, max_pairs, w);
+    return c.off + 256;
+}
+
+int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev, const double* sigma_dev,
+                          uint32_t flags, spamm_bsm* C, int64_t* kept_out, void* ws, size_t ws_bytes,
+                          spamm_stream_t stream) {
+    int rc = check_bsm(A, "A", true);
+    if (!rc) rc = check_bsm(B, "B", true);
+    if (!rc) rc = check_bsm(C, "C", false);
+    if (rc) return rc;
+    if (A->nb != B->nb || A->b != B->b || C->nb != A->nb || C->b != A->b)
+        return fail(SPAMM_EINVAL, "A, B and C must share n and leaf size");
+    if (A->b > 64) return fail(SPAMM_ENOTSUP, "the FP32 tier supports leaf 32 and 64");
+    if (!tau_dev || !sigma_dev) return fail(SPAMM_EINVAL, "tau_dev and sigma_dev are required");
+    const int sym = (flags & SPAMM_SYMMETRIC) ? 1 : 0;
+    const int btrans = (flags & SPAMM_B_TRANSPOSED) ? 1 : 0;
+    const size_t base = spamm_multiply_tiered_workspace_bytes(A->nb, A->cap, B->cap, A->b, 0);
+    if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "tiered multiply needs at least %zu bytes", base);
+    const int64_t max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    float* a32 = c.take<float>((size_t)A->cap * A->b * A->b);
+    float* b32 = c.take<float>((size_t)B->cap * B->b * B->b);
+    MulWs w;
+    carve_mul(c, A->nb, max_pairs, w);
+    if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
+    fill_i32(w.ovf, 1, 0, s);
+    launch_to_f32(A->b, A->nslot, A->cap, A->brow, A->val, a32, nullptr, s);
+    launch_to_f32(B->b, B->nslot, B->cap, B->brow, B->val, b32, nullptr, s);
+    run_pairs(view(A), view(B), btrans, sym, tau_dev, sigma_dev, view(C), nullptr, w, nullptr, nullptr, nullptr, s);
+    run_gemm(view(A), view(B), btrans, sym, view(C), nullptr, w, nullptr, nullptr, nullptr, nullptr, s, a32, b32);
+    HIP_TRY(hipGetLastError());
+    int64_t sc[4];
+    int32_t ovf = 0;
+    HIP_TRY(hipMemcpyAsync(sc, w.sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ovf, w.ovf, sizeof(ovf), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (kept_out) {
+        int64_t ko[3] = {sc[0], sc[1], sc[3]};
+        HIP_TRY(hipMemcpyAsync(kept_out, ko, sizeof(ko), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (ovf) return fail(SPAMM_ECAPACITY, "capacity exceeded (pairs %lld of %lld)", (long long)sc[0], (long long)max_pairs);
     return SPAMM_OK;
 }
 
@@ -508,11 +587,11 @@ int spamm_truncate(spamm_bsm* X, double delta, uint32_t flags, double* removed_o
 }
 
 size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
-                                  int32_t tape_steps) {
+                                  int32_t tape_steps, int32_t precision) {
     if (nb < 1 || N < 1 || cap_blocks < 1) return 0;
     Carver c(nullptr);
     Sp2Ws w;
-    carve_sp2(c, nb, b, N, cap_blocks, max_pairs, tape_steps, w);
+    carve_sp2(c, nb, b, N, cap_blocks, max_pairs, tape_steps, w, precision);
     return c.off + 256;
 }
 
@@ -542,6 +621,12 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
     if (!have_gap && isnan(p->delta_const)) return fail(SPAMM_EINVAL, "need homo/lumo or delta_const");
     if (have_gap && !(p->homo < p->lumo)) return fail(SPAMM_EINVAL, "need homo < lumo");
     if (!(p->eps > 0.0)) return fail(SPAMM_EINVAL, "eps must be > 0");
+    if (p->precision != 0 && p->precision != 1) return fail(SPAMM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 tier)");
+    if (p->precision == 1 && F->b > 64) return fail(SPAMM_ENOTSUP, "the FP32 tier supports leaf 32 and 64");
+    if (p->precision == 1 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
+        return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
+    const bool tiered = p->precision == 1;
+    const double c_low = tier_constant(p->precision, F->b);
     const int nb = F->nb, b = F->b;
     const int tape_steps = p->keep_tape ? p->n_max : 0;
     // internal capacity: whatever the workspace holds (the binding sizes it)
@@ -553,14 +638,14 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
     }
     int64_t max_pairs = 0;
     {
-        size_t base = purify_sp2_workspace_bytes(nb, b, p->N, cap, 0, tape_steps);
+        size_t base = purify_sp2_workspace_bytes(nb, b, p->N, cap, 0, tape_steps, p->precision);
         if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "purify needs at least %zu workspace bytes", base);
         max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
     }
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     Sp2Ws w;
-    carve_sp2(c, nb, b, p->N, cap, max_pairs, tape_steps, w);
+    carve_sp2(c, nb, b, p->N, cap, max_pairs, tape_steps, w, p->precision);
     if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
     int64_t nf = 0;
     {
@@ -626,7 +711,7 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
         launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp, w.trace_out,
                       nullptr, s);
         double tr[4];
-        int64_t msc[3], ts[2];
+        int64_t msc[4], ts[2];
         int32_t ovf[2];
         Sp2Ctl cs;
         HIP_TRY(hipMemcpyAsync(tr, w.trace_out, sizeof(tr), hipMemcpyDeviceToHost, s));
@@ -653,6 +738,9 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
             L.removed_units = ts[0];
             L.removed_fro2 = (double)ts[1] * trunc_quantum(L.delta * tb_scale);
             L.nslot_kept = nsl;
+            L.npairs_low = tiered ? msc[3] : 0;
+            L.sigma = cs.sigma;
+            L.sidx = cs.sidx;
             float ms = 0;
             hipEventElapsedTime(&ms, ev[0], ev[1]); L.ms_sweep = ms;
             hipEventElapsedTime(&ms, ev[1], ev[2]); L.ms_pairs = ms;
@@ -688,19 +776,31 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
         hc.branch = br;
         hc.delta = delta;
         hc.budget = p->variant == 0 ? delta / 2.0 : delta;
+        hc.budget_skip = tiered ? p->tier_split * hc.budget : hc.budget;
         hc.tau = 0.0;
         hc.idx = p->N;
+        hc.sigma = 0.0;
+        hc.sidx = p->N;
         HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
         MatView nv = view(Xn);
         HIP_TRY(hipEventRecord(ev[0], s));
         if (p->variant != 2)
-            run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
+            run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
                       &w.ctl->tau, w.sw, nullptr, s);
+        if (tiered) {
+            // largest low-precision limit whose bound (skipped p plus c_low p for the low
+            // tier) stays below the whole product budget
+            run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2, &w.ctl->sidx,
+                      &w.ctl->sigma, w.sw, nullptr, s);
+            launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, nullptr, s);
+        }
         HIP_TRY(hipEventRecord(ev[1], s));
         // kept pairs, output pattern and the leaf products (combined with X)
-        run_pairs(xv, xv, 1, 1, &w.ctl->tau, nv, w.fromc, w.mw, xv.map, &w.ctl->branch, nullptr, s);
+        run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
+                  &w.ctl->branch, nullptr, s);
         HIP_TRY(hipEventRecord(ev[2], s));
-        run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, nullptr, s);
+        run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, nullptr, s, tiered ? w.x32 : nullptr,
+                 tiered ? w.x32 : nullptr);
         HIP_TRY(hipEventRecord(ev[3], s));
         launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, s);
         HIP_TRY(hipEventRecord(ev[4], s));

@@ -127,6 +127,9 @@ struct Sp2Ctl {
     int64_t ncand;
     double trunc_Q;
     int64_t trunc_kt;
+    // precision tiers: low-precision limit sigma and its candidate index
+    double sigma, budget_skip;
+    int32_t sidx, pad5;
 };
 
 // flags in Sp2Ctl::overflow

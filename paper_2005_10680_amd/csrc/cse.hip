@@ -86,10 +86,13 @@ SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double 
             return p < t0 ? p : (p < tm ? cl * p : 0.0);
         }
     } else {
+        // canonical order: a (row half) outer, c (column half) inner; only the
+        // two children of the current (a, c) are live, so the levels above the
+        // first are left rolled to keep the recursion in registers
         double acc = 0.0;
-#pragma unroll
+#pragma unroll(LEV == 1 ? 2 : 1)
         for (int a = 0; a < 2; ++a)
-#pragma unroll
+#pragma unroll(LEV == 1 ? 2 : 1)
             for (int c = 0; c < 2; ++c) {
                 double e1 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0, 2 * j0 + c, tm, t0, cl, nA, nB);
                 double e2 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0 + 1, 2 * j0 + c, tm, t0, cl, nA, nB);

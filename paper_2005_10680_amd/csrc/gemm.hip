@@ -1,14 +1,25 @@
-// K3: leaf products of the kept pairs (the "lowest level" of Algorithm 2),
-// FP64 on the CDNA matrix cores.
+// K3: leaf products of the kept pairs (the "lowest level" of Algorithm 2)
+// on the CDNA matrix cores, FP64 with an optional FP32 precision tier.
 //
 // One workgroup (4 waves) owns one output block C_ij = sum_k A_ik B_kj and
-// walks its kept pairs in ascending k.  The inner dimension of all pairs is
-// streamed in chunks of KC: the A chunk (KC columns of the column-major A_ik)
-// and the B chunk (KC rows of B_kj) are staged through a double-buffered LDS
-// tile while the next chunk is in flight.  Each wave accumulates a
-// (B/2) x (B/2) quadrant with V_MFMA_F64_16X16X4_F64.  The SP2 combine
-// (X^ = C or 2X - C) is fused into the epilogue, and in symmetric mode the
-// mirrored block C_ji = C_ij^T is written from the same registers.
+// walks its kept pairs in list order (ascending k inside each tier).  The
+// inner dimension of all pairs is streamed in chunks of KC: the A chunk (KC
+// columns of the column-major A_ik) and the B chunk (KC rows of B_kj) are
+// staged through a double-buffered LDS tile while the next chunk is in
+// flight.  Each wave accumulates a (B/2) x (B/2) quadrant.
+//
+// Precision tiers: an output's list holds its low-tier pairs first.  Those
+// use FP32 copies of the blocks and V_MFMA_F32_16X16X4_F32; the FP32 result
+// of each pair is added into an FP64 accumulator before the next pair
+// starts, so every pair's rounding error stays within c_32 * ||A_ik|| ||B_kj||
+// (the factor the sweep folds into its bound).  The remaining pairs use
+// V_MFMA_F64_16X16X4_F64.
+//
+// Epilogue: the accumulators go through an LDS tile (the two MFMA result
+// layouts differ: FP64 register r of lane l holds row (l>>4) + 4r, FP32
+// holds row 4(l>>4) + r, column l&15 in both), the SP2 combine
+// (X^ = C or 2X - C) is applied once, and the block and, in symmetric
+// mode, its mirror C_ji = C_ij^T are written with coalesced stores.
 //
 // The kernel is persistent: the grid is a multiple of the 8 XCDs, the output
 // list (Morton order) is cut into 8 contiguous ranges of equal kept-pair
@@ -16,12 +27,15 @@
 // counter, so neighbouring outputs -- which share A rows and B columns --
 // run under the same L2.  Every output is computed by exactly one workgroup
 // in a fixed order: results are bitwise reproducible.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace spamm {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <int B>
 struct GemmCfg {
@@ -29,47 +43,59 @@ struct GemmCfg {
     static constexpr int TN = B / 32;  // along columns (2 waves)
     static constexpr int KC = 16;      // inner indices per LDS stage
     static constexpr int CH = B / KC;  // stages per kept pair
-    static constexpr int LD = B + 4;   // LDS row stride (doubles)
-    static constexpr int V2PT = KC * B / 2 / 256;  // double2 loads per thread per operand
+    static constexpr int LD = B + 4;   // LDS row stride of the staging tiles (elements)
+    static constexpr int V2PT = KC * B / 2 / 256;  // 2-element loads per thread per operand
+    static constexpr int PC = B < 64 ? B : 64;     // epilogue columns per pass
+    static constexpr int NPASS = B / PC;
+    static constexpr int LDT = B + 1;              // epilogue tile stride (doubles)
+    static constexpr int STAGE_BYTES = 2 * 2 * KC * LD * 8;
+    static constexpr int TILE_BYTES = PC * LDT * 8;
+    static constexpr int LDS_BYTES = STAGE_BYTES > TILE_BYTES ? STAGE_BYTES : TILE_BYTES;
 };
 
-// Staging registers as one vector value (kept in VGPRs, never in scratch).
 template <int N>
 struct DVec {
     typedef double type __attribute__((ext_vector_type(N)));
 };
+template <int N>
+struct FVec {
+    typedef float type __attribute__((ext_vector_type(N)));
+};
 template <int B>
-using StageV = typename DVec<2 * GemmCfg<B>::V2PT>::type;
+using StageD = typename DVec<2 * GemmCfg<B>::V2PT>::type;
+template <int B>
+using StageF = typename FVec<2 * GemmCfg<B>::V2PT>::type;
 
-// Global -> register stage of one chunk: the A chunk is KC contiguous columns
-// of A_ik; the B chunk is KC contiguous columns of Bt_jk (BT) or KC rows of
-// the column-major B_kj.
-template <int B, bool BT>
-SPAMM_DEV void load_stage(StageV<B>& sa, StageV<B>& sb, const double* __restrict__ valA, const double* __restrict__ valB, int2 pr, int chunk) {
+// Global -> register stage of one chunk (E = double or float).  The A chunk
+// is KC contiguous columns of A_ik; the B chunk is KC contiguous columns of
+// Bt_jk (BT) or KC rows of the column-major B_kj.
+template <int B, bool BT, typename E, typename V>
+SPAMM_DEV void load_stage(V& sa, V& sb, const E* __restrict__ valA, const E* __restrict__ valB, int2 pr, int chunk) {
     using C = GemmCfg<B>;
+    using E2 = typename std::conditional<sizeof(E) == 8, double2, float2>::type;
     const int t = threadIdx.x;
-    const double* a0 = valA + (size_t)pr.x * B * B + (size_t)chunk * C::KC * B;
+    const E* a0 = valA + (size_t)pr.x * B * B + (size_t)chunk * C::KC * B;
 #pragma unroll
     for (int v = 0; v < C::V2PT; ++v) {
-        const double2 x = reinterpret_cast<const double2*>(a0)[t + 256 * v];
+        const E2 x = reinterpret_cast<const E2*>(a0)[t + 256 * v];
         sa[2 * v] = x.x;
         sa[2 * v + 1] = x.y;
     }
     if constexpr (BT) {
-        const double* b0 = valB + (size_t)pr.y * B * B + (size_t)chunk * C::KC * B;
+        const E* b0 = valB + (size_t)pr.y * B * B + (size_t)chunk * C::KC * B;
 #pragma unroll
         for (int v = 0; v < C::V2PT; ++v) {
-            const double2 x = reinterpret_cast<const double2*>(b0)[t + 256 * v];
+            const E2 x = reinterpret_cast<const E2*>(b0)[t + 256 * v];
             sb[2 * v] = x.x;
             sb[2 * v + 1] = x.y;
         }
     } else {
-        const double* b0 = valB + (size_t)pr.y * B * B + (size_t)chunk * C::KC;
+        const E* b0 = valB + (size_t)pr.y * B * B + (size_t)chunk * C::KC;
 #pragma unroll
         for (int v = 0; v < C::V2PT; ++v) {
             const int idx = t + 256 * v;
             const int col = idx / (C::KC / 2), kp = idx % (C::KC / 2);
-            const double2 x = *reinterpret_cast<const double2*>(b0 + (size_t)col * B + 2 * kp);
+            const E2 x = *reinterpret_cast<const E2*>(b0 + (size_t)col * B + 2 * kp);
             sb[2 * v] = x.x;
             sb[2 * v + 1] = x.y;
         }
@@ -77,22 +103,23 @@ SPAMM_DEV void load_stage(StageV<B>& sa, StageV<B>& sb, const double* __restrict
 }
 
 // Register -> LDS: both tiles are stored [k][row or column].
-template <int B, bool BT>
-SPAMM_DEV void store_stage(const StageV<B>& sa, const StageV<B>& sb, double* As, double* Bs) {
+template <int B, bool BT, typename E, typename V>
+SPAMM_DEV void store_stage(const V& sa, const V& sb, E* As, E* Bs) {
     using C = GemmCfg<B>;
+    using E2 = typename std::conditional<sizeof(E) == 8, double2, float2>::type;
     const int t = threadIdx.x;
 #pragma unroll
     for (int v = 0; v < C::V2PT; ++v) {
         const int e = 2 * (t + 256 * v);
         const int k = e / B, r = e % B;
-        *reinterpret_cast<double2*>(As + k * C::LD + r) = double2{sa[2 * v], sa[2 * v + 1]};
+        *reinterpret_cast<E2*>(As + k * C::LD + r) = E2{sa[2 * v], sa[2 * v + 1]};
     }
     if constexpr (BT) {
 #pragma unroll
         for (int v = 0; v < C::V2PT; ++v) {
             const int e = 2 * (t + 256 * v);
             const int k = e / B, c = e % B;
-            *reinterpret_cast<double2*>(Bs + k * C::LD + c) = double2{sb[2 * v], sb[2 * v + 1]};
+            *reinterpret_cast<E2*>(Bs + k * C::LD + c) = E2{sb[2 * v], sb[2 * v + 1]};
         }
     } else {
 #pragma unroll
@@ -105,17 +132,17 @@ SPAMM_DEV void store_stage(const StageV<B>& sa, const StageV<B>& sb, double* As,
     }
 }
 
-template <int B, bool BT>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
+template <int B, bool BT, int LOWT>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     using C = GemmCfg<B>;
-    __shared__ __attribute__((aligned(16))) double lds[2][2][C::KC * C::LD];
+    __shared__ __attribute__((aligned(16))) char lds_raw[C::LDS_BYTES];
     __shared__ int s_o, s_lo, s_hi;
     if (g.done && *g.done) return;
     if (g.ovf && *g.ovf) return;
+    double* ldsd = reinterpret_cast<double*>(lds_raw);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int64_t nout = *g.nout;
-    const int nx = gridDim.x / 8;
     const int xcd = blockIdx.x % 8;
     if (tid == 0) {
         // pair-balanced contiguous range of outputs for this XCD
@@ -136,8 +163,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
     }
     __syncthreads();
     const int lo = s_lo, hi = s_hi;
-    (void)nx;
     const bool beta = g.mapX && g.branch && (*g.branch == 1);
+    // staging buffers: [buf][A or B] regions of KC*LD doubles each
+    char* const stg = lds_raw;
+    constexpr size_t SB = (size_t)C::KC * C::LD * 8;
 
     while (true) {
         if (tid == 0) s_o = lo + atomicAdd(&g.counters[xcd], 1);
@@ -147,74 +176,473 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
         if (o >= hi) break;
         const int i = g.oi[o], j = g.oj[o];
         const int p0 = g.optr[o], p1 = g.optr[o + 1];
+        const int nlow = LOWT ? g.olow[o] : 0;
         const int nch = (p1 - p0) * C::CH;
+        const int nch_low = nlow * C::CH;
 
         d4 acc[C::TM][C::TN];
+        d4 dlow[C::TM][C::TN];  // FP64 sum of the low-tier pairs (FP32 result layout)
+        f4 acc32[C::TM][C::TN];
 #pragma unroll
         for (int a = 0; a < C::TM; ++a)
 #pragma unroll
-            for (int b = 0; b < C::TN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int b = 0; b < C::TN; ++b) {
+                acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                if constexpr (LOWT != 0) {
+                    dlow[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                    acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+                }
+            }
 
-        StageV<B> sa, sb;
+        StageD<B> sa, sb;
+        StageF<B> fa, fb;
         if (nch > 0) {
-            load_stage<B, BT>(sa, sb, g.valA, g.valB, g.pairs[p0], 0);
-            store_stage<B, BT>(sa, sb, lds[0][0], lds[0][1]);
+            const int2 pr = g.pairs[p0];
+            if (LOWT && 0 < nch_low) {
+                load_stage<B, BT, float>(fa, fb, g.valA32, g.valB32, pr, 0);
+                store_stage<B, BT, float>(fa, fb, (float*)(stg), (float*)(stg + SB));
+            } else {
+                load_stage<B, BT, double>(sa, sb, g.valA, g.valB, pr, 0);
+                store_stage<B, BT, double>(sa, sb, (double*)(stg), (double*)(stg + SB));
+            }
         }
         __syncthreads();
         for (int gi = 0; gi < nch; ++gi) {
             const int buf = gi & 1;
+            const bool low_now = LOWT && gi < nch_low;
+            const bool low_next = LOWT && (gi + 1) < nch_low;
             if (gi + 1 < nch) {
-                const int gn = gi + 1;
-                load_stage<B, BT>(sa, sb, g.valA, g.valB, g.pairs[p0 + gn / C::CH], gn % C::CH);
+                const int2 pr = g.pairs[p0 + (gi + 1) / C::CH];
+                if (low_next) load_stage<B, BT, float>(fa, fb, g.valA32, g.valB32, pr, (gi + 1) % C::CH);
+                else load_stage<B, BT, double>(sa, sb, g.valA, g.valB, pr, (gi + 1) % C::CH);
             }
-            const double* As = lds[buf][0];
-            const double* Bs = lds[buf][1];
+            if constexpr (LOWT != 0) {
+                if (low_now) {
+                    const float* As = (const float*)(stg + (size_t)(2 * buf) * SB);
+                    const float* Bs = (const float*)(stg + (size_t)(2 * buf + 1) * SB);
 #pragma unroll
-            for (int ks = 0; ks < C::KC / 4; ++ks) {
-                const int kr = ks * 4 + (lane >> 4);
-                double av[C::TM], bv[C::TN];
+                    for (int ks = 0; ks < C::KC / 4; ++ks) {
+                        const int kr = ks * 4 + (lane >> 4);
+                        float av[C::TM], bv[C::TN];
 #pragma unroll
-                for (int a = 0; a < C::TM; ++a) av[a] = As[kr * C::LD + wm * C::TM * 16 + a * 16 + (lane & 15)];
+                        for (int a = 0; a < C::TM; ++a) av[a] = As[kr * C::LD + wm * C::TM * 16 + a * 16 + (lane & 15)];
 #pragma unroll
-                for (int b = 0; b < C::TN; ++b) bv[b] = Bs[kr * C::LD + wn * C::TN * 16 + b * 16 + (lane & 15)];
+                        for (int b = 0; b < C::TN; ++b) bv[b] = Bs[kr * C::LD + wn * C::TN * 16 + b * 16 + (lane & 15)];
 #pragma unroll
-                for (int a = 0; a < C::TM; ++a)
+                        for (int a = 0; a < C::TM; ++a)
 #pragma unroll
-                    for (int b = 0; b < C::TN; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                            for (int b = 0; b < C::TN; ++b)
+                                acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc32[a][b], 0, 0, 0);
+                    }
+                    if ((gi % C::CH) == C::CH - 1) {
+                        // end of one low-tier pair: fold its FP32 product into FP64
+#pragma unroll
+                        for (int a = 0; a < C::TM; ++a)
+#pragma unroll
+                            for (int b = 0; b < C::TN; ++b) {
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) dlow[a][b][r] = dlow[a][b][r] + (double)acc32[a][b][r];
+                                acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+                            }
+                    }
+                }
             }
-            if (gi + 1 < nch) store_stage<B, BT>(sa, sb, lds[buf ^ 1][0], lds[buf ^ 1][1]);
+            if (!low_now) {
+                const double* As = (const double*)(stg + (size_t)(2 * buf) * SB);
+                const double* Bs = (const double*)(stg + (size_t)(2 * buf + 1) * SB);
+#pragma unroll
+                for (int ks = 0; ks < C::KC / 4; ++ks) {
+                    const int kr = ks * 4 + (lane >> 4);
+                    double av[C::TM], bv[C::TN];
+#pragma unroll
+                    for (int a = 0; a < C::TM; ++a) av[a] = As[kr * C::LD + wm * C::TM * 16 + a * 16 + (lane & 15)];
+#pragma unroll
+                    for (int b = 0; b < C::TN; ++b) bv[b] = Bs[kr * C::LD + wn * C::TN * 16 + b * 16 + (lane & 15)];
+#pragma unroll
+                    for (int a = 0; a < C::TM; ++a)
+#pragma unroll
+                        for (int b = 0; b < C::TN; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+                }
+            }
+            if (gi + 1 < nch) {
+                char* nA = stg + (size_t)(2 * (buf ^ 1)) * SB;
+                char* nB = stg + (size_t)(2 * (buf ^ 1) + 1) * SB;
+                if (low_next) store_stage<B, BT, float>(fa, fb, (float*)nA, (float*)nB);
+                else store_stage<B, BT, double>(sa, sb, (double*)nA, (double*)nB);
+            }
             __syncthreads();
         }
 
-        // epilogue: combine and write (plus the mirrored block)
+        // ---------------- epilogue through LDS ----------------
         const int sh = g.map_out[(size_t)i * g.nb + j];
         const int sht = (g.sym && i != j) ? g.map_out[(size_t)j * g.nb + i] : -1;
         const int sx = beta ? g.mapX[(size_t)i * g.nb + j] : -1;
-        if (sh >= 0) {
-            double* dst = g.val_out + (size_t)sh * B * B;
-            double* dstt = sht >= 0 ? g.val_out + (size_t)sht * B * B : nullptr;
-            const double* xs = sx >= 0 ? g.valX + (size_t)sx * B * B : nullptr;
-            // V_MFMA_F64_16X16X4_F64 result layout: register r of lane l holds
-            // row (l >> 4) + 4 r, column l & 15 of the 16x16 tile.
+        double* dst = sh >= 0 ? g.val_out + (size_t)sh * B * B : nullptr;
+        double* dstt = sht >= 0 ? g.val_out + (size_t)sht * B * B : nullptr;
+        const double* xs = sx >= 0 ? g.valX + (size_t)sx * B * B : nullptr;
+#pragma unroll
+        for (int pass = 0; pass < C::NPASS; ++pass) {
+            const int c0 = pass * C::PC;
+            // FP64 accumulators: register r of lane l = row (l >> 4) + 4 r
 #pragma unroll
             for (int a = 0; a < C::TM; ++a)
 #pragma unroll
                 for (int b = 0; b < C::TN; ++b) {
                     const int col = wn * C::TN * 16 + b * 16 + (lane & 15);
+                    if (col < c0 || col >= c0 + C::PC) continue;
                     const int rowb = wm * C::TM * 16 + a * 16 + (lane >> 4);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = rowb + 4 * r;
-                        double v = acc[a][b][r];
-                        if (beta) {
-                            const double x = xs ? xs[(size_t)col * B + row] : 0.0;
-                            v = 2.0 * x - v;
-                        }
-                        dst[(size_t)col * B + row] = v;
-                        if (dstt) dstt[(size_t)row * B + col] = v;
-                    }
+                    for (int r = 0; r < 4; ++r) ldsd[(col - c0) * C::LDT + rowb + 4 * r] = acc[a][b][r];
                 }
+            if constexpr (LOWT != 0) {
+                if (nlow > 0) {
+                    __syncthreads();
+                    // low-tier sums: register r of lane l = row 4 (l >> 4) + r
+#pragma unroll
+                    for (int a = 0; a < C::TM; ++a)
+#pragma unroll
+                        for (int b = 0; b < C::TN; ++b) {
+                            const int col = wn * C::TN * 16 + b * 16 + (lane & 15);
+                            if (col < c0 || col >= c0 + C::PC) continue;
+                            const int rowb = wm * C::TM * 16 + a * 16 + 4 * (lane >> 4);
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                double* p = &ldsd[(col - c0) * C::LDT + rowb + r];
+                                *p = *p + dlow[a][b][r];
+                            }
+                        }
+                }
+            }
+            __syncthreads();
+            // combine and write the block (coalesced along columns)
+            for (int e = tid; e < C::PC * B; e += 256) {
+                const int cl = e / B, row = e % B;
+                double v = ldsd[cl * C::LDT + row];
+                if (beta) {
+                    const double x = xs ? xs[(size_t)(c0 + cl) * B + row] : 0.0;
+                    v = 2.0 * x - v;
+                    ldsd[cl * C::LDT + row] = v;
+                }
+                if (dst) dst[(size_t)(c0 + cl) * B + row] = v;
+            }
+            if (dstt) {
+                __syncthreads();
+                // mirror block: element (r', c') = C(c', r'); r' runs over this pass
+                for (int e = tid; e < C::PC * B; e += 256) {
+                    const int cp = e / C::PC, rp = e % C::PC;
+                    dstt[(size_t)cp * B + c0 + rp] = ldsd[rp * C::LDT + cp];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transposed-B layout (the symmetric square and the adjoint products): both
+// operand chunks are contiguous, so they are copied global -> LDS directly
+// (global_load_lds_dwordx4, 16 B per lane, lane-contiguous) into a ring of NS
+// stages, NS - 1 stages in flight while one is multiplied; no staging
+// registers.  An FP32-tier stage covers 32 inner indices, an FP64 stage 16,
+// so every stage moves the same bytes and every wave issues the same number
+// of copies per stage: the wait before a stage is a fixed vmcnt.
+// ---------------------------------------------------------------------------
+template <int B>
+struct RingCfg {
+    static constexpr int KC64 = 16, KC32 = 32;
+    static constexpr int CH64 = B / KC64, CH32 = B / KC32;
+    static constexpr int OPB = KC64 * B * 8;           // bytes per operand chunk
+    static constexpr int STAGE = 2 * OPB;              // A chunk then B chunk
+    static constexpr int NS = B == 32 ? 4 : (B == 64 ? 3 : 2);
+    static constexpr int NI = OPB / 1024 / 4;          // copies per wave per operand (1 KB per copy)
+    static constexpr int PC = B == 128 ? 32 : B;       // epilogue columns per pass
+    static constexpr int NPASS = B / PC;
+    static constexpr int LDT = B + 1;
+    static constexpr int TM = B / 32, TN = B / 32;
+};
+
+template <int V>
+SPAMM_DEV void wait_vmcnt() {
+    static_assert(V >= 0 && V < 64, "vmcnt range");
+    // gfx9 s_waitcnt: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt_hi[15:14]
+    __builtin_amdgcn_s_waitcnt((V & 0xF) | (0x7 << 4) | (0xF << 8) | (((V >> 4) & 0x3) << 14));
+}
+
+// copy one operand chunk (OPB contiguous bytes) into LDS; wave w takes the
+// 1 KB pieces w, w+4, ...
+template <int B>
+SPAMM_DEV void dma_chunk(const char* __restrict__ src, char* lds_dst) {
+    using R = RingCfg<B>;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < R::NI; ++q) {
+        const int piece = w + 4 * q;
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void*)(src + (size_t)piece * 1024 + lane * 16),
+            (__attribute__((address_space(3))) void*)(lds_dst + piece * 1024), 16, 0, 0);
+    }
+}
+
+// Read-only (for the whole launch) data at a wave-uniform index, through the
+// constant address space: a scalar load, which never waits behind vector
+// memory operations in flight.
+SPAMM_DEV int32_t const_ld(const int32_t* p, int idx) {
+    const __attribute__((address_space(4))) int32_t* q = (const __attribute__((address_space(4))) int32_t*)(uintptr_t)p;
+    return q[idx];
+}
+SPAMM_DEV int2 const_ld(const int2* p, int idx) {
+    const __attribute__((address_space(4))) int64_t* q = (const __attribute__((address_space(4))) int64_t*)(uintptr_t)p;
+    const int64_t v = q[idx];
+    return make_int2((int32_t)(v & 0xffffffff), (int32_t)(v >> 32));
+}
+
+// One LDS object per ring slot, and the stage loop unrolled by NS so every
+// access names its slot statically: the compiler can then see that the
+// copies in flight (other slots) never alias the slot being read, and only
+// the explicit vmcnt waits order them.
+template <int B, int S>
+struct RingSlot {
+    static SPAMM_DEV char* get() {
+        __shared__ __attribute__((aligned(1024))) char mem[RingCfg<B>::STAGE];
+        return mem;
+    }
+};
+
+template <int B, int LOWT>
+struct RingCtx {
+    using R = RingCfg<B>;
+    const GemmArgs& g;
+    int p0, nlow, nst_low, nst;
+    d4 acc[R::TM][R::TN];
+    d4 dlow[R::TM][R::TN];
+    f4 acc32[R::TM][R::TN];
+
+    SPAMM_DEV RingCtx(const GemmArgs& g_) : g(g_) {}
+
+    template <int SLOT>
+    SPAMM_DEV void issue(int st) {
+        char* dst = RingSlot<B, SLOT>::get();
+        int pr_i, chunk;
+        bool low;
+        if (LOWT && st < nst_low) {
+            pr_i = st / R::CH32; chunk = st % R::CH32; low = true;
+        } else {
+            const int s2 = st - nst_low;
+            pr_i = nlow + s2 / R::CH64; chunk = s2 % R::CH64; low = false;
+        }
+        // the pair list is read-only during the launch: read it through the
+        // constant address space (scalar loads, counted apart from the copies)
+        const int2 pr = const_ld(g.pairs, p0 + pr_i);
+        const char* a0;
+        const char* b0;
+        if (low) {
+            a0 = reinterpret_cast<const char*>(g.valA32 + (size_t)pr.x * B * B + (size_t)chunk * R::KC32 * B);
+            b0 = reinterpret_cast<const char*>(g.valB32 + (size_t)pr.y * B * B + (size_t)chunk * R::KC32 * B);
+        } else {
+            a0 = reinterpret_cast<const char*>(g.valA + (size_t)pr.x * B * B + (size_t)chunk * R::KC64 * B);
+            b0 = reinterpret_cast<const char*>(g.valB + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
+        }
+        dma_chunk<B>(a0, dst);
+        dma_chunk<B>(b0, dst + R::OPB);
+    }
+
+    template <int SLOT>
+    SPAMM_DEV void compute(int st) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int wm = w >> 1, wn = w & 1;
+        const char* sl = RingSlot<B, SLOT>::get();
+        if (LOWT && st < nst_low) {
+            const float* As = reinterpret_cast<const float*>(sl);
+            const float* Bs = reinterpret_cast<const float*>(sl + R::OPB);
+#pragma unroll
+            for (int ks = 0; ks < R::KC32 / 4; ++ks) {
+                const int kr = ks * 4 + (lane >> 4);
+                float av[R::TM], bv[R::TN];
+#pragma unroll
+                for (int a = 0; a < R::TM; ++a) av[a] = As[kr * B + wm * R::TM * 16 + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < R::TN; ++b) bv[b] = Bs[kr * B + wn * R::TN * 16 + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < R::TN; ++b)
+                        acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc32[a][b], 0, 0, 0);
+            }
+            if ((st % R::CH32) == R::CH32 - 1) {
+                // end of one low-tier pair: fold its FP32 product into FP64
+#pragma unroll
+                for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < R::TN; ++b) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) dlow[a][b][r] = dlow[a][b][r] + (double)acc32[a][b][r];
+                        acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+        } else {
+            const double* As = reinterpret_cast<const double*>(sl);
+            const double* Bs = reinterpret_cast<const double*>(sl + R::OPB);
+#pragma unroll
+            for (int ks = 0; ks < R::KC64 / 4; ++ks) {
+                const int kr = ks * 4 + (lane >> 4);
+                double av[R::TM], bv[R::TN];
+#pragma unroll
+                for (int a = 0; a < R::TM; ++a) av[a] = As[kr * B + wm * R::TM * 16 + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < R::TN; ++b) bv[b] = Bs[kr * B + wn * R::TN * 16 + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < R::TN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+
+    // one pipeline step on ring slot SLOT (stage st): wait for this stage,
+    // barrier, refill the slot freed by the previous step, multiply
+    template <int SLOT>
+    SPAMM_DEV void step(int st) {
+        const int ahead = min(R::NS - 2, nst - 1 - st);
+        if (ahead >= 2) wait_vmcnt<2 * 2 * R::NI>();
+        else if (ahead == 1) wait_vmcnt<2 * R::NI>();
+        else wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+        if (st + R::NS - 1 < nst) issue<(SLOT + R::NS - 1) % R::NS>(st + R::NS - 1);
+        compute<SLOT>(st);
+    }
+};
+
+template <int B, int LOWT>
+__global__ __launch_bounds__(256) void k_gemm_ring(GemmArgs g) {
+    using R = RingCfg<B>;
+    static_assert(R::NS >= 2 && R::NS <= 4, "ring depth");
+    constexpr int PC = 8;  // epilogue columns per pass, in a tile of its own
+    __shared__ double ldsd[PC * R::LDT];
+    __shared__ int s_o, s_lo, s_hi;
+    if (g.done && *g.done) return;
+    if (g.ovf && *g.ovf) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int64_t nout = *g.nout;
+    const int xcd = blockIdx.x % 8;
+    if (tid == 0) {
+        const int64_t np = g.optr[nout];
+        const int64_t t_lo = np * xcd / 8, t_hi = np * (xcd + 1) / 8;
+        int64_t lo = 0, hi = nout;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (g.optr[mid] < t_lo) lo = mid + 1; else hi = mid;
+        }
+        s_lo = (int)lo;
+        int64_t l2 = 0, h2 = nout;
+        while (l2 < h2) {
+            int64_t mid = (l2 + h2) >> 1;
+            if (g.optr[mid] < t_hi) l2 = mid + 1; else h2 = mid;
+        }
+        s_hi = xcd == 7 ? (int)nout : (int)l2;
+    }
+    __syncthreads();
+    const int lo = __builtin_amdgcn_readfirstlane(s_lo), hi = __builtin_amdgcn_readfirstlane(s_hi);
+    const bool beta = g.mapX && g.branch && (*g.branch == 1);
+    RingCtx<B, LOWT> cx(g);
+
+    while (true) {
+        if (tid == 0) s_o = lo + atomicAdd(&g.counters[xcd], 1);
+        __syncthreads();
+        // wave-uniform values in scalar registers, so the pair list is read
+        // with scalar loads that never wait behind the copies in flight
+        const int o = __builtin_amdgcn_readfirstlane(s_o);
+        __syncthreads();
+        if (o >= hi) break;
+        const int i = const_ld(g.oi, o), j = const_ld(g.oj, o);
+        const int p0 = const_ld(g.optr, o);
+        const int p1 = const_ld(g.optr, o + 1);
+        cx.p0 = p0;
+        cx.nlow = LOWT ? const_ld(g.olow, o) : 0;
+        cx.nst_low = cx.nlow * R::CH32;
+        cx.nst = cx.nst_low + (p1 - p0 - cx.nlow) * R::CH64;
+        const int nst = cx.nst;
+#pragma unroll
+        for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+            for (int b = 0; b < R::TN; ++b) {
+                cx.acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                if constexpr (LOWT != 0) {
+                    cx.dlow[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                    cx.acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+                }
+            }
+        wait_vmcnt<0>();  // nothing of the previous output stays in flight
+        if (0 < nst) cx.template issue<0>(0);
+        if (R::NS > 2 && 1 < nst) cx.template issue<1 % R::NS>(1);
+        if (R::NS > 3 && 2 < nst) cx.template issue<2 % R::NS>(2);
+        for (int st = 0; st < nst; st += R::NS) {
+            cx.template step<0>(st);
+            if (st + 1 < nst) cx.template step<1 % R::NS>(st + 1);
+            if (R::NS > 2 && st + 2 < nst) cx.template step<2 % R::NS>(st + 2);
+            if (R::NS > 3 && st + 3 < nst) cx.template step<3 % R::NS>(st + 3);
+        }
+        wait_vmcnt<0>();
+        __syncthreads();
+
+        // ---------------- epilogue through the LDS tile ----------------
+        const int sh = g.map_out[(size_t)i * g.nb + j];
+        const int sht = (g.sym && i != j) ? g.map_out[(size_t)j * g.nb + i] : -1;
+        const int sx = beta ? g.mapX[(size_t)i * g.nb + j] : -1;
+        double* dst = sh >= 0 ? g.val_out + (size_t)sh * B * B : nullptr;
+        double* dstt = sht >= 0 ? g.val_out + (size_t)sht * B * B : nullptr;
+        const double* xs = sx >= 0 ? g.valX + (size_t)sx * B * B : nullptr;
+        for (int pass = 0; pass < B / PC; ++pass) {
+            const int c0 = pass * PC;
+#pragma unroll
+            for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < R::TN; ++b) {
+                    const int col = wn * R::TN * 16 + b * 16 + (lane & 15);
+                    if (col < c0 || col >= c0 + PC) continue;
+                    const int rowb = wm * R::TM * 16 + a * 16 + (lane >> 4);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ldsd[(col - c0) * R::LDT + rowb + 4 * r] = cx.acc[a][b][r];
+                }
+            if constexpr (LOWT != 0) {
+                if (cx.nlow > 0) {
+                    __syncthreads();
+#pragma unroll
+                    for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+                        for (int b = 0; b < R::TN; ++b) {
+                            const int col = wn * R::TN * 16 + b * 16 + (lane & 15);
+                            if (col < c0 || col >= c0 + PC) continue;
+                            const int rowb = wm * R::TM * 16 + a * 16 + 4 * (lane >> 4);
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                double* pp = &ldsd[(col - c0) * R::LDT + rowb + r];
+                                *pp = *pp + cx.dlow[a][b][r];
+                            }
+                        }
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < PC * B; e += 256) {
+                const int cl = e / B, row = e % B;
+                double v = ldsd[cl * R::LDT + row];
+                if (beta) {
+                    const double x = xs ? xs[(size_t)(c0 + cl) * B + row] : 0.0;
+                    v = 2.0 * x - v;
+                    ldsd[cl * R::LDT + row] = v;
+                }
+                if (dst) dst[(size_t)(c0 + cl) * B + row] = v;
+            }
+            if (dstt) {
+                __syncthreads();
+                for (int e = tid; e < PC * B; e += 256) {
+                    const int cp = e / PC, rp = e % PC;
+                    dstt[(size_t)cp * B + c0 + rp] = ldsd[rp * R::LDT + cp];
+                }
+            }
+            __syncthreads();
         }
     }
 }
@@ -228,21 +656,59 @@ void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s) {
     const int per_cu = g.b == 128 ? 2 : 4;
     int grid = num_cu * per_cu;
     grid = (grid + 7) / 8 * 8;
-#define SPAMM_G(B_, T_) hipLaunchKernelGGL((k_gemm_f64<B_, T_>), dim3(grid), dim3(256), 0, s, g)
+    const bool low = g.valA32 != nullptr;
+#define SPAMM_G(B_, T_, L_) hipLaunchKernelGGL((k_gemm<B_, T_, L_>), dim3(grid), dim3(256), 0, s, g)
+#define SPAMM_GB(T_)                                                     \
+    switch (g.b) {                                                       \
+        case 32: if (low) SPAMM_G(32, T_, 1); else SPAMM_G(32, T_, 0); break; \
+        case 64: if (low) SPAMM_G(64, T_, 1); else SPAMM_G(64, T_, 0); break; \
+        case 128: SPAMM_G(128, T_, 0); break; /* no FP32 tier at leaf 128 */ \
+    }
     if (g.btrans) {
+        const int per_cu_ring = g.b == 64 ? 3 : (g.b == 32 ? 4 : 2);
+        int gr = (num_cu * per_cu_ring + 7) / 8 * 8;
         switch (g.b) {
-            case 32: SPAMM_G(32, true); break;
-            case 64: SPAMM_G(64, true); break;
-            case 128: SPAMM_G(128, true); break;
+            case 32: if (low) hipLaunchKernelGGL((k_gemm_ring<32, 1>), dim3(gr), dim3(256), 0, s, g);
+                     else hipLaunchKernelGGL((k_gemm_ring<32, 0>), dim3(gr), dim3(256), 0, s, g); break;
+            case 64: if (low) hipLaunchKernelGGL((k_gemm_ring<64, 1>), dim3(gr), dim3(256), 0, s, g);
+                     else hipLaunchKernelGGL((k_gemm_ring<64, 0>), dim3(gr), dim3(256), 0, s, g); break;
+            case 128: hipLaunchKernelGGL((k_gemm_ring<128, 0>), dim3(gr), dim3(256), 0, s, g); break;
         }
     } else {
-        switch (g.b) {
-            case 32: SPAMM_G(32, false); break;
-            case 64: SPAMM_G(64, false); break;
-            case 128: SPAMM_G(128, false); break;
+        SPAMM_GB(false)
+    }
+#undef SPAMM_GB
+#undef SPAMM_G
+}
+
+// FP32 copies of the live blocks (round to nearest), for the low tier.
+template <int B>
+__global__ __launch_bounds__(256) void k_to_f32(const int32_t* __restrict__ nslot_p, int64_t cap,
+                                               const int32_t* __restrict__ brow, const double* __restrict__ val,
+                                               float* __restrict__ out, const int32_t* __restrict__ done) {
+    if (done && *done) return;
+    int64_t nslot = *nslot_p;
+    if (nslot > cap) nslot = cap;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < nslot; s += (int64_t)gridDim.x * 4) {
+        if (brow[s] < 0) continue;
+        const double2* src = reinterpret_cast<const double2*>(val + (size_t)s * B * B);
+        float2* dst = reinterpret_cast<float2*>(out + (size_t)s * B * B);
+        for (int t = lane; t < B * B / 2; t += 64) {
+            const double2 v = src[t];
+            dst[t] = float2{(float)v.x, (float)v.y};
         }
     }
-#undef SPAMM_G
+}
+
+void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
+                   const int32_t* done, hipStream_t s) {
+    const int grid = grid_for(cap, 4, 4096);
+    switch (b) {
+        case 32: hipLaunchKernelGGL(k_to_f32<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, done); break;
+        case 64: hipLaunchKernelGGL(k_to_f32<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, done); break;
+        case 128: hipLaunchKernelGGL(k_to_f32<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, done); break;
+    }
 }
 
 }  // namespace spamm

@@ -39,7 +39,8 @@ void launch_kept_fill(int nb, int P, int nw, const uint32_t* bitsA, const uint32
                       const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
                       const double* sigma, const int32_t* cnt, const int32_t* off, const int32_t* oidx,
                       const int64_t* npairs, const int64_t* nout, int64_t cap_pairs, int64_t cap_out, int32_t* oi,
-                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* ovf, const int32_t* done, hipStream_t s);
+                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int32_t* ovf, const int32_t* done,
+                      hipStream_t s);
 void launch_hat_flags(int nb, int P, const int32_t* cnt, int sym, const int32_t* mapX, const int32_t* branch,
                       int32_t* flag, const int32_t* done, hipStream_t s);
 void launch_hat_assign(int nb, int P, const int32_t* cnt, int sym, const int32_t* flag, const int32_t* slot,
@@ -93,8 +94,15 @@ struct GemmArgs {
     int32_t* counters;  // [16] work counters, reset by the launcher
     const int32_t* ovf; // nonzero: an earlier capacity overflow, skip
     const int32_t* done;
+    // FP32 tier (null when off): FP32 copies of A and B, and per output the
+    // number of low-tier pairs at the head of its pair list
+    const float* valA32 = nullptr;
+    const float* valB32 = nullptr;
+    const int32_t* olow = nullptr;
 };
 void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s);
+void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
+                   const int32_t* done, hipStream_t s);
 
 // trunc.hip
 size_t trunc_temp_bytes(int64_t cap);

@@ -107,8 +107,8 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
                             const int32_t* __restrict__ off, const int32_t* __restrict__ oidx,
                             const int64_t* __restrict__ npairs_p, const int64_t* __restrict__ nout_p, int64_t cap_pairs,
                             int64_t cap_out, int32_t* __restrict__ oi, int32_t* __restrict__ oj,
-                            int32_t* __restrict__ optr, int2* __restrict__ pairs, int32_t* __restrict__ ovf,
-                            const int32_t* __restrict__ done) {
+                            int32_t* __restrict__ optr, int2* __restrict__ pairs, int32_t* __restrict__ olow,
+                            int32_t* __restrict__ ovf, const int32_t* __restrict__ done) {
     if (done && *done) return;
     const double tau = *tau_p;
     const double sigma = sigma_p ? *sigma_p : 0.0;
@@ -137,6 +137,7 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
                                   ++w;
                               }
                           });
+            if (olow) olow[o] = (int32_t)(w - off[z]);
             for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
                           [&](int, int sa, int sb, double p) {
                               if (!(p < sigma)) {
@@ -158,11 +159,12 @@ void launch_kept_fill(int nb, int P, int nw, const uint32_t* bitsA, const uint32
                       const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
                       const double* sigma, const int32_t* cnt, const int32_t* off, const int32_t* oidx,
                       const int64_t* npairs, const int64_t* nout, int64_t cap_pairs, int64_t cap_out, int32_t* oi,
-                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* ovf, const int32_t* done, hipStream_t s) {
+                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int32_t* ovf, const int32_t* done,
+                      hipStream_t s) {
     int64_t PP = (int64_t)P * P;
     hipLaunchKernelGGL(k_kept_fill, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB, mapA,
                        normA, mapB, normB, btrans, tau, sigma, cnt, off, oidx, npairs, nout, cap_pairs, cap_out, oi,
-                       oj, optr, pairs, ovf, done);
+                       oj, optr, pairs, olow, ovf, done);
 }
 
 // Output pattern: block (r, c) of the result exists when the product has a

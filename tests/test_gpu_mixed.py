@@ -1,0 +1,130 @@
+"""GPU parity of the FP32 leaf-product tier (mixed precision, not in the
+paper): the kept set and the tier split are bit-exact against the oracle;
+the product differs from the oracle's FP64 product by no more than the
+Algorithm 3 bound over the folded rounding terms c_32 * p of the low-tier
+pairs; mixed purification still meets ||D~ - D||_F < 1e-6."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2005_10680_amd as P  # noqa: E402
+
+
+def to_oracle(M):
+    brow, bcol, vals, _, _, _ = M.live()
+    return oracle.BSM(M.n, M.b, brow, bcol, vals)
+
+
+def sym_x(n, b, seed):
+    F = oracle.BSM.of(synth.sys3d(n, seed, b))
+    lmin, lmax = oracle.gerschgorin(F)
+    return oracle.x0(F, lmin, lmax)
+
+
+def test_tier_constant_matches_oracle():
+    for b in (32, 64):
+        assert P.tier_constant(1, b) == oracle.tier_constant(1, b)
+
+
+@pytest.mark.parametrize("n,b,seed", [(2000, 64, 2), (1024, 32, 5)])
+def test_multiply_tiered_within_folded_bound(n, b, seed):
+    X = sym_x(n, b, seed)
+    # a squared iterate has the spread of norms the tier is meant for
+    C0, _ = oracle.spamm(X, X, 0.0, sym=True)
+    X = C0
+    _, nu = oracle.norms(X)
+    tau = float(np.quantile(nu, 0.2)) ** 2
+    sigma = float(np.quantile(nu, 0.6)) ** 2
+    M = P.BlockSparse.from_host(X)
+    P.build_norms(M)
+    C, kept = P.multiply_tiered(M, M, tau, sigma, symmetric=True, b_transposed=True)
+    Co, Ko = oracle.spamm(X, X, tau, sym=True)
+    kg = kept.cpu().numpy()
+    assert int(kg[0]) == Ko.npairs
+    nlow = Ko.npairs - oracle.kept(X, X, sigma, True).npairs
+    assert int(kg[2]) == nlow and nlow > 0
+    G = to_oracle(C)
+    assert np.array_equal(G.keys(), Co.keys())
+    # Algorithm 3 over the rounding terms of the low tier only
+    nb = X.nb
+    mp = X.block_map()
+    c = oracle.tier_constant(1, b)
+    lv = np.zeros((nb, nb, nb))
+    for i in range(nb):
+        for k in range(nb):
+            sa = mp[i * nb + k]
+            if sa < 0:
+                continue
+            for j in range(nb):
+                sb = mp[k * nb + j]
+                if sb < 0:
+                    continue
+                p = nu[sa] * nu[sb]
+                if tau <= p < sigma:
+                    lv[i, k, j] = c * p
+    bound_sym = oracle.cse_tree_leafvals(X, X, lv)
+    diff = G.to_dense() - Co.to_dense()
+    ref = np.linalg.norm(Co.to_dense())
+    # the bound runs over all triples, so it covers both mirrored triangles
+    assert np.linalg.norm(diff) <= bound_sym * 1.0000001 + 1e-13 * ref
+    assert np.linalg.norm(diff) > 0.0          # the FP32 tier really ran
+
+
+def test_purify_fp32_tier_chain():
+    Fm = synth.chain1d(1024, 1, 32)
+    F = oracle.BSM.of(Fm)
+    w, U = np.linalg.eigh(F.to_dense())
+    Dref = U[:, :512] @ U[:, :512].T
+    taus = synth.tau_paper()
+    G = P.BlockSparse.from_host(Fm)
+    res = P.purify(G, 512, 1e-6, taus, homo=w[511], lumo=w[512], precision="fp32")
+    Dg = to_oracle(res.D).to_dense()
+    assert np.linalg.norm(Dg - Dref) < 1e-6
+    # every kept pair of the chain has c_32 p above the budget, so no pair is
+    # eligible for the tier (the oracle's selection agrees) and the result is
+    # the FP64 one, bit for bit
+    p = oracle.SP2Params(n_occ=512, eps=1e-6, taus=taus, homo=w[511], lumo=w[512], precision=1)
+    _, logs_o, _ = oracle.sp2(F, p)
+    assert sum(l.npairs_low for l in logs_o) == 0
+    assert sum(l["npairs_low"] for l in res.logs) == 0
+    res64 = P.purify(G, 512, 1e-6, taus, homo=w[511], lumo=w[512])
+    D64 = to_oracle(res64.D)
+    Dm = to_oracle(res.D)
+    assert np.array_equal(D64.keys(), Dm.keys()) and np.array_equal(D64.vals, Dm.vals)
+
+
+def test_purify_fp32_tier_teacher_forced():
+    n, b = 2048, 64
+    Fm = synth.sys3d(n, 12, b)
+    F = oracle.BSM.of(Fm)
+    w, U = np.linalg.eigh(F.to_dense())
+    n_occ = n // 2
+    Dref = U[:, :n_occ] @ U[:, :n_occ].T
+    taus = synth.tau_log(32)
+    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=taus, homo=w[n_occ - 1], lumo=w[n_occ], precision=1)
+    G = P.BlockSparse.from_host(Fm)
+    res = P.purify(G, n_occ, 1e-6, taus, homo=w[n_occ - 1], lumo=w[n_occ], keep_tape=True, precision="fp32")
+    steps = [lg for lg in res.logs if lg["branch"] >= 0]
+    _, _, st, _ = oracle.sp2_start(F, p)
+    xh, xl, e_hist = st.xh, st.xl, []
+    low_total = 0
+    for t, lg in enumerate(steps):
+        Xprev = to_oracle(res.tape(t))
+        Xn, Xh, log, st2 = oracle.sp2_step(Xprev, oracle.SP2State(t + 1, xh, xl, list(e_hist)), p)
+        assert lg["branch"] == log.branch
+        assert lg["idx"] == log.idx and lg["tau"] == log.tau
+        assert lg["sidx"] == log.sidx and lg["sigma"] == log.sigma
+        assert lg["npairs"] == log.npairs and lg["npairs_low"] == log.npairs_low
+        low_total += lg["npairs_low"]
+        xh, xl, e_hist = st2.xh, st2.xl, st2.e_hist
+    assert low_total > 0
+    Dg = to_oracle(res.D).to_dense()
+    assert np.linalg.norm(Dg - Dref) < 1e-6
