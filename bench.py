@@ -128,9 +128,10 @@ def main():
         "kept_pairs_per_run": int(sum(l["npairs"] for l in steps)),
         "phase_ms_per_run": {k: round(sum(l[k] for l in steps), 3)
                              for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc", "ms_total")},
-        "roofline": {"kernel": "k_gemm_f64<64,true>", "bound": "mfma", "achieved": round(achieved, 3),
+        "roofline": {"kernel": f"k_gemm_ring<{b},0>", "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
+                     "traffic": measured_traffic(n, b, args.seed),
                      "avg_launch_ms": round(avg_gemm_ms, 4),
                      "flops_per_launch": gemm_flops / ngemm},
     }
@@ -200,6 +201,41 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+GEMM_SOURCES = ("paper_2005_10680_amd/csrc/gemm.hip", "paper_2005_10680_amd/csrc/kernels.hpp",
+                "paper_2005_10680_amd/csrc/common.hpp")
+
+
+def gemm_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in GEMM_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n, b, seed):
+    """HBM bytes per launch of the leaf-product kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary of this workload, each counter scaled by
+    what it reads for a plain 1 GiB device copy.  None when no summary exists
+    or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"k_gemm_ring_f64_sys3d_n{n}_s{seed}_leaf{b}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("#", " ", "\t")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != gemm_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(res, Fh, taus, b, seconds):
     """The oracle timed on the host cores on a bounded sample of the same
     workload: the last purification step's SpAMM (the sweep over the whole
@@ -227,7 +263,7 @@ def cpu_baseline(res, Fh, taus, b, seconds):
         oracle.block_products(X, X, K, sel)
         done_s += time.perf_counter() - t
         done_pairs += int(pairs_per[pos:pos + chunk].sum())
-        pos += chunk
+        pos = min(pos + chunk, order.shape[0])
         chunk = min(chunk * 2, 4096)
     tflops = done_pairs * 2.0 * b ** 3 / done_s / 1e12
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))

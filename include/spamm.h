@@ -177,6 +177,9 @@ typedef struct sp2_iter_log {
     double delta, tau, t1, t2, e;
     int64_t npairs, nout, nslot_hat, nslot_kept, removed_units;
     double removed_fro2;
+    /* stream-event times in ms: threshold sweep (and FP32 copies), kept pairs
+       and output pattern, the leaf-product kernel alone, pass-through blocks
+       and block norms, truncation, whole iteration */
     float ms_sweep, ms_pairs, ms_gemm, ms_norms, ms_trunc, ms_total;
     int64_t npairs_low;  /* pairs evaluated in the low-precision tier */
     double sigma;        /* low-precision limit of the step (0: none) */

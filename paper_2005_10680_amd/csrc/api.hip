@@ -226,7 +226,8 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
 // Leaf products of the kept pairs into C's slots (combined with X when given).
 void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatView& C, const uint8_t* fromc,
               MulWs& w, const int32_t* mapX, const double* valX, const int32_t* branch_dev, const int32_t* done,
-              hipStream_t s, const float* valA32 = nullptr, const float* valB32 = nullptr) {
+              hipStream_t s, const float* valA32 = nullptr, const float* valB32 = nullptr,
+              hipEvent_t ev_start = nullptr, hipEvent_t ev_end = nullptr) {
     const int nb = A.nb;
     GemmArgs g;
     g.b = A.b;
@@ -252,7 +253,7 @@ void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const Mat
     g.valA32 = valA32;
     g.valB32 = valB32;
     g.olow = valA32 ? w.olow : nullptr;
-    launch_gemm_f64(g, num_cus(), s);
+    launch_gemm_f64(g, num_cus(), s, ev_start, ev_end);
     if (mapX) launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s);
 }
 
@@ -798,10 +799,9 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
         // kept pairs, output pattern and the leaf products (combined with X)
         run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
                   &w.ctl->branch, nullptr, s);
-        HIP_TRY(hipEventRecord(ev[2], s));
+        // ev[2]/ev[3] bracket the product kernel alone
         run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, nullptr, s, tiered ? w.x32 : nullptr,
-                 tiered ? w.x32 : nullptr);
-        HIP_TRY(hipEventRecord(ev[3], s));
+                 tiered ? w.x32 : nullptr, ev[2], ev[3]);
         launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, s);
         HIP_TRY(hipEventRecord(ev[4], s));
         if (p->variant != 1)

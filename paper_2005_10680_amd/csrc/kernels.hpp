@@ -100,7 +100,9 @@ struct GemmArgs {
     const float* valB32 = nullptr;
     const int32_t* olow = nullptr;
 };
-void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s);
+// ev_start/ev_end (optional) are recorded right around the product kernel.
+void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start = nullptr,
+                     hipEvent_t ev_end = nullptr);
 void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
                    const int32_t* done, hipStream_t s);
 
