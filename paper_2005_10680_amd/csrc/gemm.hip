@@ -360,6 +360,10 @@ struct RingCfg {
     static constexpr int NPASS = B / PC;
     static constexpr int LDT = B + 1;
     static constexpr int TM = B / 32, TN = B / 32;
+    // waves per SIMD the register allocation aims for (LDS allows 3
+    // workgroups per CU at leaf 64)
+    template <int LOWT>
+    static constexpr int waves() { return B == 32 ? 4 : (B == 64 ? (LOWT ? 2 : 3) : 1); }
 };
 
 template <int V>
@@ -415,7 +419,6 @@ struct RingCtx {
     const GemmArgs& g;
     int p0, nlow, nst_low, nst;
     d4 acc[R::TM][R::TN];
-    d4 dlow[R::TM][R::TN];
     f4 acc32[R::TM][R::TN];
 
     SPAMM_DEV RingCtx(const GemmArgs& g_) : g(g_) {}
@@ -455,12 +458,18 @@ struct RingCtx {
         if (LOWT && st < nst_low) {
             const float* As = reinterpret_cast<const float*>(sl);
             const float* Bs = reinterpret_cast<const float*>(sl + R::OPB);
+            // The f32 16x16x4 result puts row 4(l>>4)+r in register r of lane
+            // l; the f64 one puts row (l>>4)+4r there.  Feeding the f32 MFMA
+            // the A rows in the order pi(m) = m/4 + 4(m%4) makes both results
+            // share one layout, so a finished FP32 pair product adds straight
+            // into the FP64 accumulator.
+            const int mrow = ((lane & 15) >> 2) + 4 * (lane & 3);
 #pragma unroll
             for (int ks = 0; ks < R::KC32 / 4; ++ks) {
                 const int kr = ks * 4 + (lane >> 4);
                 float av[R::TM], bv[R::TN];
 #pragma unroll
-                for (int a = 0; a < R::TM; ++a) av[a] = As[kr * B + wm * R::TM * 16 + a * 16 + (lane & 15)];
+                for (int a = 0; a < R::TM; ++a) av[a] = As[kr * B + wm * R::TM * 16 + a * 16 + mrow];
 #pragma unroll
                 for (int b = 0; b < R::TN; ++b) bv[b] = Bs[kr * B + wn * R::TN * 16 + b * 16 + (lane & 15)];
 #pragma unroll
@@ -476,7 +485,7 @@ struct RingCtx {
 #pragma unroll
                     for (int b = 0; b < R::TN; ++b) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) dlow[a][b][r] = dlow[a][b][r] + (double)acc32[a][b][r];
+                        for (int r = 0; r < 4; ++r) acc[a][b][r] = acc[a][b][r] + (double)acc32[a][b][r];
                         acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
                     }
             }
@@ -515,7 +524,8 @@ struct RingCtx {
 };
 
 template <int B, int LOWT>
-__global__ __launch_bounds__(256) void k_gemm_ring(GemmArgs g) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void k_gemm_ring(GemmArgs g) {
     using R = RingCfg<B>;
     static_assert(R::NS >= 2 && R::NS <= 4, "ring depth");
     constexpr int PC = 8;  // epilogue columns per pass, in a tile of its own
@@ -569,10 +579,7 @@ __global__ __launch_bounds__(256) void k_gemm_ring(GemmArgs g) {
 #pragma unroll
             for (int b = 0; b < R::TN; ++b) {
                 cx.acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-                if constexpr (LOWT != 0) {
-                    cx.dlow[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-                    cx.acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-                }
+                if constexpr (LOWT != 0) cx.acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
             }
         wait_vmcnt<0>();  // nothing of the previous output stays in flight
         if (0 < nst) cx.template issue<0>(0);
@@ -606,24 +613,6 @@ __global__ __launch_bounds__(256) void k_gemm_ring(GemmArgs g) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) ldsd[(col - c0) * R::LDT + rowb + 4 * r] = cx.acc[a][b][r];
                 }
-            if constexpr (LOWT != 0) {
-                if (cx.nlow > 0) {
-                    __syncthreads();
-#pragma unroll
-                    for (int a = 0; a < R::TM; ++a)
-#pragma unroll
-                        for (int b = 0; b < R::TN; ++b) {
-                            const int col = wn * R::TN * 16 + b * 16 + (lane & 15);
-                            if (col < c0 || col >= c0 + PC) continue;
-                            const int rowb = wm * R::TM * 16 + a * 16 + 4 * (lane >> 4);
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                double* pp = &ldsd[(col - c0) * R::LDT + rowb + r];
-                                *pp = *pp + cx.dlow[a][b][r];
-                            }
-                        }
-                }
-            }
             __syncthreads();
             for (int e = tid; e < PC * B; e += 256) {
                 const int cl = e / B, row = e % B;
