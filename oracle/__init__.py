@@ -575,3 +575,117 @@ def sp2(F: BSM, p: SP2Params, keep_tape: bool = False):
             tape.append(X)
     return X, logs, {"lmin": info[0], "lmax": info[1], "delta0": info[2], "tape": tape,
                      "converged": logs[-1].branch == -1 and st.i <= p.n_max}
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode of the purification with frozen decisions (not in the paper).
+#
+# With the kept sets K_t, the truncation patterns S_t, the branches and the
+# Gerschgorin bounds held fixed at their values in a forward run, the
+# purification is a polynomial map F -> D~:
+#   X~_0 = mask_{S_0}((lmax I - F) / (lmax - lmin)),
+#   X~_t = mask_{S_t}(f_t(C_t(X~_{t-1}))),  C_t(X) = sum_{(i,k,j) in K_t} X_ik X_kj,
+#   f_t(C) = C (x^2 branch) or 2 X~_{t-1} - C (2x - x^2 branch).
+# Gradients are for symmetric perturbations: <Fbar, H> = dL[H] for every
+# symmetric H, Fbar symmetric.
+# ---------------------------------------------------------------------------
+
+def _blocks(X: BSM) -> dict:
+    """(r, c) -> row-major b x b block."""
+    return {(int(X.brow[t]), int(X.bcol[t])): X.vals[t].T for t in range(X.nblk)}
+
+
+def _from_blocks(X: BSM, blk: dict) -> BSM:
+    """Values on X's pattern and block order from a (r, c) -> block dict
+    (absent keys give zero blocks)."""
+    b = X.b
+    vals = np.zeros((X.nblk, b, b))
+    for t in range(X.nblk):
+        key = (int(X.brow[t]), int(X.bcol[t]))
+        if key in blk:
+            vals[t] = blk[key].T
+    return BSM(X.n, b, X.brow.copy(), X.bcol.copy(), np.ascontiguousarray(vals))
+
+
+def sym_part(D: BSM) -> BSM:
+    """(D + D^T)/2 on D's pattern (which must be symmetric)."""
+    d = _blocks(D)
+    return _from_blocks(D, {(r, c): 0.5 * (v + d[(c, r)].T) for (r, c), v in d.items()})
+
+
+def adjoint_step(X: BSM, G: BSM, tau: float, branch: int, nu=None) -> BSM:
+    """Reverse of one frozen step X~' = mask_{S'}(f(C(X))) at X = X~_{t-1}.
+    G is the (symmetric) gradient with respect to X~' on its pattern S', so
+    mask_{S'} is already applied.  K = {(i,k,j): RN(nu(X_ik) nu(X_kj)) >= tau}
+    is the leaf-level kept set of Algorithm 2 at X.  By the product rule,
+      first factor   A_ik = sum_{j: (i,k,j) in K} G_ij X_kj^T,
+      second factor  B_kj = sum_{i: (i,k,j) in K} X_ik^T G_ij,
+    the gradient of <G, C(X)> is sym(A + B), and the step's gradient with
+    respect to X, restricted to the pattern of X (outside it X~_{t-1} is an
+    exact zero fixed by the previous truncation), is
+      sym(A + B)            (x^2 branch),
+      2 G - sym(A + B)      (2x - x^2 branch; G read as 0 outside S').
+    Returns it on X's pattern and block order."""
+    nu = norms(X)[1] if nu is None else nu
+    K = kept(X, X, tau, False, nu, nu)       # all outputs (i, j), no symmetry shortcut
+    xb, gb = _blocks(X), _blocks(G)
+    acc = {}
+    for o in range(K.oi.shape[0]):
+        i, j = int(K.oi[o]), int(K.oj[o])
+        if (i, j) not in gb:
+            continue
+        g = gb[(i, j)]
+        for k in K.klist[K.kptr[o]:K.kptr[o + 1]]:
+            k = int(k)
+            a = g @ xb[(k, j)].T                 # first factor X_ik
+            acc[(i, k)] = acc.get((i, k), 0.0) + a
+            bb = xb[(i, k)].T @ g                # second factor X_kj
+            acc[(k, j)] = acc.get((k, j), 0.0) + bb
+    out = {}
+    z = np.zeros((X.b, X.b))
+    for (r, c) in xb:
+        s = 0.5 * (acc.get((r, c), z) + acc.get((c, r), z).T)
+        if branch == 1:
+            s = 2.0 * gb.get((r, c), z) - s
+        out[(r, c)] = s
+    return _from_blocks(X, out)
+
+
+def sp2_adjoint(F: BSM, tape: list, logs: list, lmin: float, lmax: float, Dbar: BSM) -> BSM:
+    """Gradient of L with respect to F (on F's pattern and block order) from
+    Dbar = dL/dD~ on the pattern of D~ = tape[-1], by the reverse of every
+    frozen step (adjoint_step) and of X~_0 = mask_{S_0}((lmax I - F)/W):
+    Fbar = -Xbar_0 / W on S_0, zero on blocks of F that the first truncation
+    removed.  tape[t] = X~_t; logs[t-1] holds tau and the branch of step t."""
+    G = sym_part(Dbar)
+    for t in range(len(tape) - 1, 0, -1):
+        lg = logs[t - 1]
+        G = adjoint_step(tape[t - 1], G, lg.tau, lg.branch)
+    W = lmax - lmin
+    g0 = _blocks(G)
+    return _from_blocks(F, {k: -v / W for k, v in g0.items()})
+
+
+def _mask(X: BSM, S: BSM) -> BSM:
+    """X restricted to the pattern of S, in S's block order (zeros where X
+    has no block)."""
+    return _from_blocks(S, _blocks(X))
+
+
+def sp2_replay(F: BSM, tape: list, logs: list, lmin: float, lmax: float) -> BSM:
+    """The frozen map F -> D~ of a recorded run: the kept set of step t is
+    recomputed from tape[t-1] (the recorded iterate) and tau_t, the
+    truncation keeps exactly the pattern of tape[t]."""
+    X = _mask(x0(F, lmin, lmax), tape[0])
+    for t in range(1, len(tape)):
+        lg = logs[t - 1]
+        Xr = tape[t - 1]
+        nu = norms(Xr)[1]
+        K = kept(Xr, Xr, lg.tau, True, nu, nu)
+        V = block_products(X, X, K)
+        off = K.oi != K.oj
+        C = BSM(X.n, X.b, np.concatenate([K.oi, K.oj[off]]).astype(np.int32),
+                np.concatenate([K.oj, K.oi[off]]).astype(np.int32),
+                np.ascontiguousarray(np.concatenate([V, V[off].transpose(0, 2, 1)]))).sorted()
+        X = _mask(combine(X, C, lg.branch), tape[t])
+    return X
