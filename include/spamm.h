@@ -213,6 +213,60 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
 int purify_sp2_tape_view(void* ws, int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
                          int32_t tape_steps, int32_t step, spamm_bsm* out);
 
+/*
+ * Reverse mode (not in the paper).  With the decisions of a forward run held
+ * fixed -- the kept set K_t of every step (leaf-level skip test of
+ * Algorithm 2 at tau_t), the truncation pattern S_t of every iterate, the
+ * branch f_t and the Gerschgorin bounds of the starting matrix -- the
+ * purification of Algorithms 1/4/5 is a polynomial map F -> D~.  These
+ * entry points evaluate its gradient for symmetric perturbations: for a
+ * loss L(D~), Fbar satisfies <Fbar, H> = dL[H] for every symmetric H, and
+ * Fbar is symmetric.
+ *
+ * One frozen step X~' = mask_{S'}(f(C(X))), C(X)_ij = sum over (i,k,j) in K
+ * of X_ik X_kj, K = {(i,k,j): RN(nu(X_ik) nu(X_kj)) >= tau}, f = x^2
+ * (branch 0) or 2x - x^2 (branch 1):
+ *   X        : X~_{t-1}, norms valid (spamm_build_norms, or a tape entry).
+ *   G        : gradient with respect to X~' on its pattern (the pattern of
+ *              X~_t), symmetric in pattern and values; only its pattern
+ *              arrays and val are read.
+ *   xbar_val : output, device [X->cap * b * b] doubles in X's slot layout:
+ *              the gradient with respect to X~_{t-1} on its pattern,
+ *              Xbar = A + A^T (branch 0) or 2G - (A + A^T) (branch 1),
+ *              A_ik = sum_{j: (i,k,j) in K} G_ij X_kj^T.  Slots that are
+ *              holes (brow = -1) are not written.
+ *   counts_out : optional device int64[2]: output blocks (i <= k) and block
+ *              pairs of the step's product launch.
+ * Workspace: spamm_adjoint_step_workspace_bytes(nb, X->cap, max_pairs);
+ * SPAMM_ECAPACITY when the pair list needs more than max_pairs.
+ * Synchronises the stream (it reads the overflow flag back).
+ */
+size_t spamm_adjoint_step_workspace_bytes(int32_t nb, int64_t cap_blocks, int64_t max_pairs);
+int spamm_adjoint_step(const spamm_bsm* X, const spamm_bsm* G, double tau, int32_t branch, double* xbar_val,
+                       int64_t* counts_out, void* ws, size_t ws_bytes, spamm_stream_t stream);
+
+/*
+ * Gradient of a loss with respect to F through a whole recorded purification.
+ *   F        : the input of the forward run (pattern arrays, n, b).
+ *   tape     : host array of ntape handles X~_0 .. X~_{ntape-1}
+ *              (purify_sp2_tape_view of a run with keep_tape); the last one
+ *              is D~.  The forward workspace must be unchanged.
+ *   log      : the forward run's records (nlog == ntape): record t-1 holds
+ *              tau and the branch of step t; the last record is the stop.
+ *   dbar_val : device [cap * b * b]: dL/dD~ in the slot layout of
+ *              tape[ntape-1] (only its symmetric part is used).
+ *   fbar_val : output, device [F->cap * b * b] in F's slot layout:
+ *              Fbar = -Xbar_0 / (lmax - lmin) on the blocks of F that the
+ *              first truncation kept, zero on those it removed.
+ * Workspace: purify_sp2_adjoint_workspace_bytes(nb, b, cap, max_pairs) with
+ * cap the tape entries' capacity; SPAMM_ECAPACITY when a step's pair list
+ * needs more than max_pairs (a bound: nb^2 (nb + 1)).  Synchronises.
+ */
+size_t purify_sp2_adjoint_workspace_bytes(int32_t nb, int32_t b, int64_t cap_blocks, int64_t max_pairs);
+int purify_sp2_adjoint(const spamm_bsm* F, const spamm_bsm* tape, int32_t ntape, const sp2_iter_log* log,
+                       int32_t nlog, const double* dbar_val, double* fbar_val, void* ws, size_t ws_bytes,
+                       spamm_stream_t stream);
+
 const char* spamm_status_str(int code);
 const char* spamm_last_error(void);
 int spamm_version(void);

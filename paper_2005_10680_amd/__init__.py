@@ -103,6 +103,12 @@ def lib() -> ctypes.CDLL:
     L.spamm_multiply_tiered.argtypes = [B, B, P, P, u32, B, P, P, sz, P]
     L.spamm_tier_constant.argtypes = [i32, i32]
     L.spamm_tier_constant.restype = d
+    L.spamm_adjoint_step_workspace_bytes.argtypes = [i32, i64, i64]
+    L.spamm_adjoint_step_workspace_bytes.restype = sz
+    L.spamm_adjoint_step.argtypes = [B, B, d, i32, P, P, P, sz, P]
+    L.purify_sp2_adjoint_workspace_bytes.argtypes = [i32, i32, i64, i64]
+    L.purify_sp2_adjoint_workspace_bytes.restype = sz
+    L.purify_sp2_adjoint.argtypes = [B, B, i32, ctypes.POINTER(sp2_iter_log), i32, P, P, P, sz, P]
     L.spamm_status_str.argtypes = [ctypes.c_int]
     L.spamm_status_str.restype = ctypes.c_char_p
     L.spamm_last_error.restype = ctypes.c_char_p
@@ -367,6 +373,8 @@ class PurifyResult:
     status: int
     ws: torch.Tensor
     tape_args: tuple | None
+    raw_logs: object = None
+    nlog: int = 0
 
     def tape(self, step: int) -> BlockSparse:
         """X~_step of a run with keep_tape (a view into the workspace)."""
@@ -404,7 +412,84 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
     _check(rc)
     out = [{k: getattr(logs[i], k) for k, _ in sp2_iter_log._fields_} for i in range(nlog.value)]
     targs = (nb, b, N, int(cap), int(mp), tape_steps) if keep_tape else None
-    return PurifyResult(D, out, rc, ws, targs)
+    return PurifyResult(D, out, rc, ws, targs, logs, nlog.value)
+
+
+def adjoint_step(X: BlockSparse, G: BlockSparse, tau: float, branch: int, max_pairs=None):
+    """Reverse of one frozen purification step (spamm_adjoint_step): the
+    gradient with respect to X on X's slot layout, from the symmetric
+    gradient G on the pattern of the step's output.  Returns (xbar values
+    [X.cap*b*b], device int64[2] = (output blocks, block pairs))."""
+    nb, b = X.nb, X.b
+    if max_pairs is None:
+        max_pairs = max(1, nb * nb * (nb + 1))
+    base = lib().spamm_adjoint_step_workspace_bytes(nb, X.cap, 0)
+    ws = _ws(base + 8 * int(max_pairs) + 1024, X.device)
+    xbar = torch.zeros(X.cap * b * b, dtype=torch.float64, device=X.device)
+    counts = torch.zeros(2, dtype=torch.int64, device=X.device)
+    _check(lib().spamm_adjoint_step(ctypes.byref(X.struct()), ctypes.byref(G.struct()), float(tau), int(branch),
+                                    xbar.data_ptr(), counts.data_ptr(), _ptr(ws), ws.numel(), _stream()))
+    return xbar, counts
+
+
+def with_values(M: BlockSparse, val: torch.Tensor) -> BlockSparse:
+    """M's pattern arrays with another value array (no copy)."""
+    st = M.struct()
+    st2 = spamm_bsm(st.n, st.b, st.nb, st.cap, st.nslot, st.brow, st.bcol, st.map, val.data_ptr(), st.norm, st.sq,
+                    st.sqlo)
+    return BlockSparse.wrap(st2, keepalive=val)
+
+
+def purify_adjoint(res: PurifyResult, F: BlockSparse, dbar: torch.Tensor, max_pairs=None) -> torch.Tensor:
+    """dL/dF (values in F's slot layout) from dbar = dL/dD~ (values in the
+    slot layout of res.D) through the recorded run res (purify with
+    keep_tape), decisions held fixed (purify_sp2_adjoint)."""
+    if res.tape_args is None:
+        raise ValueError("purify was run without keep_tape")
+    nb, b = F.nb, F.b
+    ntape = res.nlog
+    tape = (spamm_bsm * ntape)()
+    for t in range(ntape):
+        _check(lib().purify_sp2_tape_view(_ptr(res.ws), *res.tape_args, t, ctypes.byref(tape[t])))
+    cap = res.tape_args[3]
+    if max_pairs is None:
+        max_pairs = max(1, nb * nb * (nb + 1))
+    base = lib().purify_sp2_adjoint_workspace_bytes(nb, b, cap, 0)
+    ws = _ws(base + 8 * int(max_pairs) + 1024, F.device)
+    dbar = dbar.to(torch.float64).contiguous()
+    if dbar.numel() < cap * b * b:
+        raise ValueError("dbar must hold the slots of D")
+    fbar = torch.zeros(F.cap * b * b, dtype=torch.float64, device=F.device)
+    _check(lib().purify_sp2_adjoint(ctypes.byref(F.struct()), tape, ntape, res.raw_logs, res.nlog,
+                                    dbar.data_ptr(), fbar.data_ptr(), _ptr(ws), ws.numel(), _stream()))
+    return fbar
+
+
+class _Purify(torch.autograd.Function):
+    """F values -> D~ values; backward through purify_sp2_adjoint."""
+
+    @staticmethod
+    def forward(ctx, fval, F, kw, holder):
+        Fv = with_values(F, fval.detach().contiguous())
+        res = purify(Fv, keep_tape=True, **kw)
+        ctx.res, ctx.F = res, Fv
+        holder["res"] = res
+        return res.D.val
+
+    @staticmethod
+    def backward(ctx, dval):
+        return purify_adjoint(ctx.res, ctx.F, dval), None, None, None
+
+
+def purify_autograd(F: BlockSparse, fval: torch.Tensor, n_occ: int, eps: float, taus, **kw):
+    """Differentiable purification: returns (D~ values, PurifyResult); the
+    values are in the slot layout of result.D.  Gradients flow to fval (F's
+    value array, F's slot layout) for symmetric perturbations, with the
+    run's decisions (kept sets, truncation patterns, branches, Gerschgorin
+    bounds) held fixed."""
+    holder = {}
+    dval = _Purify.apply(fval, F, dict(kw, n_occ=n_occ, eps=eps, taus=taus), holder)
+    return dval, holder["res"]
 
 
 def version() -> int:

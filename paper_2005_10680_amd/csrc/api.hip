@@ -385,6 +385,79 @@ void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, 
     w.x32 = precision ? c.take<float>((size_t)cap * b * b) : nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// adjoint workspace: one reverse step (pair list on the pattern of X)
+// ---------------------------------------------------------------------------
+struct AdjWs {
+    int nb, nw;
+    int64_t cap, cap_pairs;
+    uint32_t *bitsX, *bitsG;
+    int32_t *flag, *pos, *oi, *oj, *cnt, *optr;
+    int2* pairs;
+    int64_t* sc;        // [0] outputs, [1] pairs
+    int32_t* counters;  // [16]
+    int32_t* ovf;       // [4]
+    int32_t* branch;    // [1]
+    void* scan_tmp;
+};
+
+void carve_adj(Carver& c, int nb, int64_t cap, int64_t max_pairs, AdjWs& w) {
+    w.nb = nb;
+    w.nw = (nb + 31) / 32;
+    w.cap = cap;
+    w.cap_pairs = max_pairs;
+    w.bitsX = c.take<uint32_t>((size_t)nb * w.nw);
+    w.bitsG = c.take<uint32_t>((size_t)nb * w.nw);
+    w.flag = c.take<int32_t>(cap);
+    w.pos = c.take<int32_t>(cap);
+    w.oi = c.take<int32_t>(cap);
+    w.oj = c.take<int32_t>(cap);
+    w.cnt = c.take<int32_t>(cap);
+    w.optr = c.take<int32_t>(cap + 1);
+    w.sc = c.take<int64_t>(4);
+    w.counters = c.take<int32_t>(16);
+    w.ovf = c.take<int32_t>(4);
+    w.branch = c.take<int32_t>(1);
+    w.scan_tmp = c.take<char>(scan_temp_bytes(cap));
+    w.pairs = c.take<int2>(max_pairs);
+}
+
+// Xbar (values on X's slots) of one frozen step: X = X~_{t-1} with norms,
+// G the symmetric gradient on the pattern of X~_t.
+void run_adjoint_step(const MatView& X, const MatView& G, double tau, int branch, double* xbar, AdjWs& w,
+                      hipStream_t s) {
+    fill_u32(w.bitsX, (int64_t)w.nb * w.nw, 0u, s);
+    fill_u32(w.bitsG, (int64_t)w.nb * w.nw, 0u, s);
+    launch_occupancy(X, kOccA, w.bitsX, w.nw, nullptr, 0, 0, nullptr, s);
+    launch_occupancy(G, kOccA, w.bitsG, w.nw, nullptr, 0, 0, nullptr, s);
+    fill_i32(w.branch, 1, branch, s);
+    launch_adj_outputs(X, w.flag, w.pos, w.oi, w.oj, &w.sc[0], w.scan_tmp, s);
+    launch_adj_pairs(w.nb, w.nw, w.cap, &w.sc[0], w.oi, w.oj, w.bitsX, w.bitsG, X.map, X.norm, G.map, tau, w.cnt,
+                     w.optr, &w.sc[1], w.cap_pairs, w.pairs, w.ovf, w.scan_tmp, s);
+    GemmArgs g;
+    g.b = X.b;
+    g.nb = X.nb;
+    g.oi = w.oi;
+    g.oj = w.oj;
+    g.optr = w.optr;
+    g.pairs = w.pairs;
+    g.nout = &w.sc[0];
+    g.npairs = &w.sc[1];
+    g.valA = G.val;
+    g.valB = X.val;
+    g.btrans = 1;
+    g.sym = 1;
+    g.map_out = X.map;
+    g.val_out = xbar;
+    g.mapX = G.map;
+    g.valX = G.val;
+    g.branch = w.branch;
+    g.counters = w.counters;
+    g.ovf = w.ovf;
+    g.done = nullptr;
+    launch_gemm_f64(g, num_cus(), s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -825,6 +898,114 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
     }
     *nlog_out = nlog;
     return status;
+}
+
+size_t spamm_adjoint_step_workspace_bytes(int32_t nb, int64_t cap_blocks, int64_t max_pairs) {
+    if (nb < 1 || cap_blocks < 1 || max_pairs < 0) return 0;
+    Carver c(nullptr);
+    AdjWs w;
+    carve_adj(c, nb, cap_blocks, max_pairs, w);
+    return c.off + 256;
+}
+
+int spamm_adjoint_step(const spamm_bsm* X, const spamm_bsm* G, double tau, int32_t branch, double* xbar_val,
+                       int64_t* counts_out, void* ws, size_t ws_bytes, spamm_stream_t stream) {
+    int rc = check_bsm(X, "X", true);
+    if (!rc) rc = check_bsm(G, "G", false);
+    if (rc) return rc;
+    if (X->nb != G->nb || X->b != G->b) return fail(SPAMM_EINVAL, "X and G must have the same block grid");
+    if (!(tau >= 0.0)) return fail(SPAMM_EINVAL, "tau must be >= 0");
+    if (branch != 0 && branch != 1) return fail(SPAMM_EINVAL, "branch must be 0 or 1");
+    if (!xbar_val) return fail(SPAMM_EINVAL, "xbar_val is NULL");
+    const int64_t cap = X->cap;
+    const size_t base = spamm_adjoint_step_workspace_bytes(X->nb, cap, 0);
+    if (!ws || ws_bytes < base + 512) return fail(SPAMM_EWORKSPACE, "adjoint step needs more than %zu workspace bytes", base);
+    const int64_t max_pairs = (int64_t)((ws_bytes - base - 512) / sizeof(int2));
+    if (max_pairs >= ((int64_t)1 << 31)) return fail(SPAMM_EINVAL, "pair capacity must stay below 2^31");
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    AdjWs w;
+    carve_adj(c, X->nb, cap, max_pairs, w);
+    if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
+    fill_i32(w.ovf, 1, 0, s);
+    run_adjoint_step(view(X), view(G), tau, branch, xbar_val, w, s);
+    if (counts_out) HIP_TRY(hipMemcpyAsync(counts_out, w.sc, 2 * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    int32_t ovf = 0;
+    int64_t sc[2];
+    HIP_TRY(hipMemcpyAsync(&ovf, w.ovf, sizeof(ovf), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sc, w.sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    if (ovf) return fail(SPAMM_ECAPACITY, "adjoint step needs %lld pairs, workspace holds %lld", (long long)sc[1],
+                         (long long)max_pairs);
+    return SPAMM_OK;
+}
+
+size_t purify_sp2_adjoint_workspace_bytes(int32_t nb, int32_t b, int64_t cap_blocks, int64_t max_pairs) {
+    if (nb < 1 || cap_blocks < 1 || max_pairs < 0) return 0;
+    Carver c(nullptr);
+    c.take<double>((size_t)cap_blocks * b * b);
+    c.take<double>((size_t)cap_blocks * b * b);
+    c.take<double>(2 * (size_t)nb * b);
+    c.take<double>(2);
+    AdjWs w;
+    carve_adj(c, nb, cap_blocks, max_pairs, w);
+    return c.off + 256;
+}
+
+int purify_sp2_adjoint(const spamm_bsm* F, const spamm_bsm* tape, int32_t ntape, const sp2_iter_log* log,
+                       int32_t nlog, const double* dbar_val, double* fbar_val, void* ws, size_t ws_bytes,
+                       spamm_stream_t stream) {
+    int rc = check_bsm(F, "F", false);
+    if (rc) return rc;
+    if (!tape || ntape < 1 || !log || !dbar_val || !fbar_val) return fail(SPAMM_EINVAL, "NULL or empty argument");
+    if (nlog != ntape) return fail(SPAMM_EINVAL, "a run with %d tape entries has %d log records, not %d", ntape, ntape, nlog);
+    const int nb = F->nb, b = F->b;
+    int64_t cap = 0;
+    for (int t = 0; t < ntape; ++t) {
+        rc = check_bsm(&tape[t], "tape entry", true);
+        if (rc) return rc;
+        // tape entries carry the padded size nb * b
+        if (tape[t].nb != nb || tape[t].b != b) return fail(SPAMM_EINVAL, "tape entry %d does not match F", t);
+        cap = std::max<int64_t>(cap, tape[t].cap);
+    }
+    for (int t = 1; t < ntape; ++t)
+        if (log[t - 1].branch != 0 && log[t - 1].branch != 1)
+            return fail(SPAMM_EINVAL, "log record %d is not a step", t - 1);
+    const size_t base = purify_sp2_adjoint_workspace_bytes(nb, b, cap, 0);
+    if (!ws || ws_bytes < base + 512) return fail(SPAMM_EWORKSPACE, "adjoint needs more than %zu workspace bytes", base);
+    const int64_t max_pairs = (int64_t)((ws_bytes - base - 512) / sizeof(int2));
+    if (max_pairs >= ((int64_t)1 << 31)) return fail(SPAMM_EINVAL, "pair capacity must stay below 2^31");
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    double* gbuf[2];
+    gbuf[0] = c.take<double>((size_t)cap * b * b);
+    gbuf[1] = c.take<double>((size_t)cap * b * b);
+    double* rowtmp = c.take<double>(2 * (size_t)nb * b);
+    double* lam = c.take<double>(2);
+    AdjWs w;
+    carve_adj(c, nb, cap, max_pairs, w);
+    if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
+
+    fill_i32(w.ovf, 1, 0, s);
+    // gradient of the last iterate, symmetrised
+    launch_sym_half(view(&tape[ntape - 1]), dbar_val, gbuf[0], s);
+    int cur = 0;
+    for (int t = ntape - 1; t >= 1; --t) {
+        MatView gv = view(&tape[t]);
+        gv.val = gbuf[cur];
+        run_adjoint_step(view(&tape[t - 1]), gv, log[t - 1].tau, log[t - 1].branch, gbuf[1 - cur], w, s);
+        cur = 1 - cur;
+    }
+    // X~_0 = mask((lmax I - F) / (lmax - lmin)) with the same bounds as the forward run
+    launch_gersch(view(F), rowtmp, lam, s);
+    launch_adj_fbar(view(F), tape[0].map, gbuf[cur], lam, fbar_val, s);
+    int32_t ovf = 0;
+    HIP_TRY(hipMemcpyAsync(&ovf, w.ovf, sizeof(ovf), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    if (ovf) return fail(SPAMM_ECAPACITY, "adjoint pair list exceeded %lld pairs", (long long)max_pairs);
+    return SPAMM_OK;
 }
 
 }  // extern "C"

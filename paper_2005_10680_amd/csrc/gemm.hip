@@ -442,9 +442,14 @@ struct RingCtx {
         if (low) {
             a0 = reinterpret_cast<const char*>(g.valA32 + (size_t)pr.x * B * B + (size_t)chunk * R::KC32 * B);
             b0 = reinterpret_cast<const char*>(g.valB32 + (size_t)pr.y * B * B + (size_t)chunk * R::KC32 * B);
-        } else {
+        } else if (pr.x >= 0) {
             a0 = reinterpret_cast<const char*>(g.valA + (size_t)pr.x * B * B + (size_t)chunk * R::KC64 * B);
             b0 = reinterpret_cast<const char*>(g.valB + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
+        } else {
+            // a pair of the second kind (one's complement first slot): the
+            // first operand comes from the B pool, the second from the A pool
+            a0 = reinterpret_cast<const char*>(g.valB + (size_t)(~pr.x) * B * B + (size_t)chunk * R::KC64 * B);
+            b0 = reinterpret_cast<const char*>(g.valA + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
         }
         dma_chunk<B>(a0, dst);
         dma_chunk<B>(b0, dst + R::OPB);

@@ -78,6 +78,8 @@ struct GemmArgs {
     const int32_t* oi;
     const int32_t* oj;
     const int32_t* optr;
+    // (slot in valA, slot in valB); with btrans, a pair whose first slot is
+    // negative holds (~slot in valB, slot in valA) instead (FP64 pairs only)
     const int2* pairs;
     const int64_t* nout;
     const int64_t* npairs;
@@ -105,6 +107,17 @@ void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev
                      hipEvent_t ev_end = nullptr);
 void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
                    const int32_t* done, hipStream_t s);
+
+// adjoint.hip
+void launch_sym_half(const MatView& D, const double* dval, double* gval, hipStream_t s);
+void launch_adj_outputs(const MatView& X, int32_t* flag, int32_t* pos, int32_t* oi, int32_t* oj, int64_t* nout,
+                        void* scan_tmp, hipStream_t s);
+void launch_adj_pairs(int nb, int nw, int64_t cap_out, const int64_t* nout, const int32_t* oi, const int32_t* oj,
+                      const uint32_t* bitsX, const uint32_t* bitsG, const int32_t* mapX, const double* normX,
+                      const int32_t* mapG, double tau, int32_t* cnt, int32_t* optr, int64_t* npairs,
+                      int64_t cap_pairs, int2* pairs, int32_t* ovf, void* scan_tmp, hipStream_t s);
+void launch_adj_fbar(const MatView& F, const int32_t* map0, const double* g0, const double* lam, double* fbar,
+                     hipStream_t s);
 
 // trunc.hip
 size_t trunc_temp_bytes(int64_t cap);
