@@ -169,6 +169,11 @@ typedef struct sp2_params {
     int32_t keep_tape;   /* nonzero: keep every X~_i in the workspace (adjoint, inspection) */
     int32_t precision;   /* 0 FP64 leaf products; 1 FP32 tier for pairs with tau <= p < sigma (leaf 32/64) */
     double tier_split;   /* share of the product budget given to skipping when precision != 0 (e.g. 0.5) */
+    int32_t graph_steps; /* 0: host-driven loop (per-iteration phase timings); K > 0: the step is
+                            captured once as a HIP graph with its decisions taken on the device
+                            and replayed, the host polling the stop flag every K iterations
+                            (requires keep_tape == 0; phase timings are 0) */
+    int32_t pad_;
 } sp2_params;
 
 /* Per-iteration record written by purify_sp2 (host memory). */
@@ -197,7 +202,10 @@ typedef struct sp2_iter_log {
  *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise).
  *   log   : host [n_max + 2] records; nlog_out: records written.
  * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, keep_tape ? n_max : 0, precision).
- * Reads scalars back every iteration (synchronises the stream).
+ * Host-driven loop: reads scalars back every iteration (synchronises the
+ * stream).  Graph mode (graph_steps > 0): same decisions, same kernels and
+ * bit-identical results; the stream is synchronised once per graph_steps
+ * iterations.
  */
 size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
                                   int32_t tape_steps, int32_t precision);

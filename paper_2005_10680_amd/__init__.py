@@ -54,7 +54,7 @@ class sp2_params(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("tau", ctypes.c_void_p), ("N", ctypes.c_int32),
                 ("homo", ctypes.c_double), ("lumo", ctypes.c_double), ("delta_const", ctypes.c_double),
                 ("e_tol", ctypes.c_double), ("keep_tape", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("tier_split", ctypes.c_double)]
+                ("tier_split", ctypes.c_double), ("graph_steps", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class sp2_iter_log(ctypes.Structure):
@@ -387,8 +387,11 @@ class PurifyResult:
 
 def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo=float("nan"),
            variant="hybrid", n_max=60, delta_const=float("nan"), e_tol=0.0, cap=None, max_pairs=None,
-           keep_tape=False, precision="fp64", tier_split=0.5) -> PurifyResult:
-    """SP2 purification with SpAMM and error control (Algorithms 1, 4, 5)."""
+           keep_tape=False, precision="fp64", tier_split=0.5, graph_steps=0) -> PurifyResult:
+    """SP2 purification with SpAMM and error control (Algorithms 1, 4, 5).
+    graph_steps > 0: the step runs as a replayed HIP graph with its
+    decisions taken on the device, the host polling every graph_steps
+    iterations (keep_tape must be off; phase timings are 0)."""
     dev = F.device
     nb, b = F.nb, F.b
     taus = torch.as_tensor(taus, dtype=torch.float64, device=dev).contiguous()
@@ -404,7 +407,8 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
     mp = (ws.numel() - base - 512) // 8   # the pair capacity the library derives
     D = BlockSparse(F.n, b, cap, dev)
     p = sp2_params(int(n_occ), float(eps), int(n_max), VARIANTS[variant], taus.data_ptr(), N, float(homo),
-                   float(lumo), float(delta_const), float(e_tol), 1 if keep_tape else 0, prec, float(tier_split))
+                   float(lumo), float(delta_const), float(e_tol), 1 if keep_tape else 0, prec, float(tier_split),
+                   int(graph_steps), 0)
     logs = (sp2_iter_log * (n_max + 2))()
     nlog = ctypes.c_int32(0)
     rc = lib().purify_sp2(ctypes.byref(F.struct()), ctypes.byref(p), ctypes.byref(D.struct()), logs,

@@ -262,28 +262,15 @@ void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const Mat
 // algorithm's statement; double precision, one rounding per operation)
 // ---------------------------------------------------------------------------
 double step_delta(const sp2_params* p, double gap) {
-    if (!isnan(p->delta_const)) return p->delta_const;
-    return p->eps * gap / (4.0 * (double)p->n_max);
+    return sp2_step_delta(p->eps, p->n_max, p->delta_const, gap);
 }
-int choose_branch(double t1, double t2, int64_t n_occ) {
-    const double no = (double)n_occ;
-    return fabs(t2 - no) <= fabs((2.0 * t1 - t2) - no) ? 0 : 1;
-}
-double map_gap(double x, int br) { return br == 0 ? x * x : 2.0 * x - x * x; }
+int choose_branch(double t1, double t2, int64_t n_occ) { return sp2_choose_branch(t1, t2, n_occ); }
+double map_gap(double x, int br) { return sp2_map_gap(x, br); }
 bool should_stop(const std::vector<double>& eh, double e_tol) {
-    if (eh.empty()) return false;
-    if (fabs(eh.back()) <= e_tol) return true;
-    const size_t n = eh.size();
-    if (n >= 3 && fabs(eh[n - 3]) < 1e-3 && fabs(eh[n - 1]) >= fabs(eh[n - 3])) return true;
-    return false;
-}
-// RN(a - b) for double-doubles a, b (the trace difference)
-double dd_diff(double ahi, double alo, double bhi, double blo) {
-    double s = ahi - bhi;
-    double bb = s - ahi;
-    double e = (ahi - (s - bb)) + (-bhi - bb);
-    e = e + (alo - blo);
-    return s + e;
+    double e[3];
+    const int n = (int)std::min<size_t>(eh.size(), 3);
+    for (int q = 0; q < n; ++q) e[q] = eh[eh.size() - 1 - q];
+    return sp2_should_stop(e, n, e_tol);
 }
 
 // c_t of the FP32 tier: inputs rounded to FP32 (u = 2^-24 each), products
@@ -298,15 +285,7 @@ double tier_constant(int precision, int b) {
     return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 0x1p-40);
 }
 
-double trunc_quantum(double delta) {
-    const double T = delta * delta;
-    if (!(T > 0.0) || !isfinite(T)) return 0.0;
-    int e;
-    frexp(T, &e);
-    int eq = e - 1 - 40;
-    if (eq < -1000) eq = -1000;
-    return ldexp(1.0, eq);
-}
+double trunc_quantum(double delta) { return sp2_trunc_quantum(delta); }
 
 __global__ void k_trunc_report(const int64_t* stats, const double* delta_dev, double delta_host, double scale,
                                double* out) {
@@ -358,7 +337,10 @@ struct Sp2Ws {
     double* bound2; // [N] sweep over the low-precision limit
     float* x32;     // FP32 copy of the current iterate (precision tier)
     Sp2Ctl* ctl;
+    sp2_iter_log* dlog;  // [kMaxLog] records written by the device control (graph mode)
 };
+
+constexpr int kMaxLog = 10002;  // n_max <= 10000, plus the stop record
 
 void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, int tape_steps, Sp2Ws& w,
                int precision = 0) {
@@ -382,6 +364,7 @@ void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, 
     w.bound = c.take<double>(N);
     w.bound2 = c.take<double>(N);
     w.ctl = c.take<Sp2Ctl>(1);
+    w.dlog = c.take<sp2_iter_log>(kMaxLog);
     w.x32 = precision ? c.take<float>((size_t)cap * b * b) : nullptr;
 }
 
@@ -696,6 +679,8 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
     if (have_gap && !(p->homo < p->lumo)) return fail(SPAMM_EINVAL, "need homo < lumo");
     if (!(p->eps > 0.0)) return fail(SPAMM_EINVAL, "eps must be > 0");
     if (p->precision != 0 && p->precision != 1) return fail(SPAMM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 tier)");
+    if (p->graph_steps < 0) return fail(SPAMM_EINVAL, "graph_steps must be >= 0");
+    if (p->graph_steps > 0 && p->keep_tape) return fail(SPAMM_EINVAL, "graph mode needs keep_tape = 0");
     if (p->precision == 1 && F->b > 64) return fail(SPAMM_ENOTSUP, "the FP32 tier supports leaf 32 and 64");
     if (p->precision == 1 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
         return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
@@ -743,6 +728,7 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
     memset(&hc, 0, sizeof(hc));
     fill_i32(w.mw.ovf, 1, 0, s);
     fill_i32(w.sw.ovf, 1, 0, s);
+    fill_i64(w.tstats, 4, 0, s);  // stays 0 when no step truncates (Algorithm 4)
 
     // X_0 and its first truncation
     MatView Fv = view(F);
@@ -773,115 +759,205 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
         HIP_TRY(hipMemcpyAsync(t.sqlo, X0.sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
     }
 
-    std::vector<double> e_hist;
-    int cur = 0;
-    int nlog = 0;
-    int status = SPAMM_OK;
     const double tb_scale = p->variant == 0 ? 0.5 : 1.0;
-    for (int it = 1;; ++it) {
-        spamm_bsm* Xc = tape_steps > 0 ? &w.tape[it - 1] : &w.X[cur];
-        spamm_bsm* Xn = tape_steps > 0 ? (it <= tape_steps ? &w.tape[it] : nullptr) : &w.X[1 - cur];
-        MatView xv = view(Xc);
-        launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp, w.trace_out,
-                      nullptr, s);
-        double tr[4];
-        int64_t msc[4], ts[2];
-        int32_t ovf[2];
-        Sp2Ctl cs;
-        HIP_TRY(hipMemcpyAsync(tr, w.trace_out, sizeof(tr), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(msc, w.mw.sc, sizeof(msc), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(ts, w.tstats, sizeof(ts), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&ovf[0], w.mw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&ovf[1], w.sw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(&cs, w.ctl, sizeof(cs), hipMemcpyDeviceToHost, s));
-        int32_t nsl = 0;
-        HIP_TRY(hipMemcpyAsync(&nsl, xv.nslot, sizeof(nsl), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (ovf[0] || ovf[1]) {
-            status = fail(SPAMM_ECAPACITY, "capacity exceeded in iteration %d (flags %d/%d; pairs %lld of %lld)",
-                          it - 1, ovf[0], ovf[1], (long long)msc[0], (long long)max_pairs);
-            break;
-        }
-        if (nlog > 0) {
-            sp2_iter_log& L = log[nlog - 1];
-            L.idx = cs.idx;
-            L.tau = cs.tau;
-            L.npairs = msc[0];
-            L.nout = msc[1];
-            L.nslot_hat = msc[2];
-            L.removed_units = ts[0];
-            L.removed_fro2 = (double)ts[1] * trunc_quantum(L.delta * tb_scale);
-            L.nslot_kept = nsl;
-            L.npairs_low = tiered ? msc[3] : 0;
-            L.sigma = cs.sigma;
-            L.sidx = cs.sidx;
-            float ms = 0;
-            hipEventElapsedTime(&ms, ev[0], ev[1]); L.ms_sweep = ms;
-            hipEventElapsedTime(&ms, ev[1], ev[2]); L.ms_pairs = ms;
-            hipEventElapsedTime(&ms, ev[2], ev[3]); L.ms_gemm = ms;
-            hipEventElapsedTime(&ms, ev[3], ev[4]); L.ms_norms = ms;
-            hipEventElapsedTime(&ms, ev[4], ev[5]); L.ms_trunc = ms;
-            hipEventElapsedTime(&ms, ev[0], ev[5]); L.ms_total = ms;
-        }
-        const double t1 = tr[0], t2 = tr[2];
-        const double e = dd_diff(tr[0], tr[1], tr[2], tr[3]);
-        e_hist.push_back(e);
-        sp2_iter_log& L = log[nlog++];
-        memset(&L, 0, sizeof(L));
-        L.i = it;
-        L.t1 = t1;
-        L.t2 = t2;
-        L.e = e;
-        L.branch = -1;
-        const bool stop = should_stop(e_hist, p->e_tol);
-        if (stop || it > p->n_max || Xn == nullptr) {
-            L.stop = stop ? 1 : 2;
-            if (!stop) status = SPAMM_WNOCONV;
-            break;
-        }
-        const int br = choose_branch(t1, t2, p->n_occ);
-        if (have_gap) {
-            xh = map_gap(xh, br);
-            xl = map_gap(xl, br);
-        }
-        const double delta = step_delta(p, xh - xl);
-        L.branch = br;
-        L.delta = delta;
-        hc.branch = br;
-        hc.delta = delta;
-        hc.budget = p->variant == 0 ? delta / 2.0 : delta;
-        hc.budget_skip = tiered ? p->tier_split * hc.budget : hc.budget;
-        hc.tau = 0.0;
-        hc.idx = p->N;
-        hc.sigma = 0.0;
-        hc.sidx = p->N;
-        HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
-        MatView nv = view(Xn);
-        HIP_TRY(hipEventRecord(ev[0], s));
+    // One purification step on the device, X~_{i-1} (xv) -> X~_i (nv), with
+    // every decision read from the control block: the threshold sweep (and
+    // the low-precision limit), kept pairs and output pattern, the leaf
+    // products with the combine fused, block norms, truncation.  done: the
+    // device stop flag (graph mode), null in the host loop.  evs: phase
+    // events (host loop only).
+    auto enqueue_step = [&](const MatView& xv, const MatView& nv, const int32_t* done, hipEvent_t* evs,
+                            hipStream_t st) -> int {
+        if (evs) HIP_TRY(hipEventRecord(evs[0], st));
         if (p->variant != 2)
             run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
-                      &w.ctl->tau, w.sw, nullptr, s);
+                      &w.ctl->tau, w.sw, done, st);
         if (tiered) {
             // largest low-precision limit whose bound (skipped p plus c_low p for the low
             // tier) stays below the whole product budget
             run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2, &w.ctl->sidx,
-                      &w.ctl->sigma, w.sw, nullptr, s);
-            launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, nullptr, s);
+                      &w.ctl->sigma, w.sw, done, st);
+            launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, st);
         }
-        HIP_TRY(hipEventRecord(ev[1], s));
+        if (evs) HIP_TRY(hipEventRecord(evs[1], st));
         // kept pairs, output pattern and the leaf products (combined with X)
         run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
-                  &w.ctl->branch, nullptr, s);
-        // ev[2]/ev[3] bracket the product kernel alone
-        run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, nullptr, s, tiered ? w.x32 : nullptr,
-                 tiered ? w.x32 : nullptr, ev[2], ev[3]);
-        launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, s);
-        HIP_TRY(hipEventRecord(ev[4], s));
+                  &w.ctl->branch, done, st);
+        // evs[2]/evs[3] bracket the product kernel alone
+        run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, done, st,
+                 tiered ? w.x32 : nullptr, tiered ? w.x32 : nullptr, evs ? evs[2] : nullptr, evs ? evs[3] : nullptr);
+        launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, st, done);
+        if (evs) HIP_TRY(hipEventRecord(evs[4], st));
         if (p->variant != 1)
-            launch_truncate(nv, &w.ctl->delta, 0.0, tb_scale, w.trunc_tmp, cap, w.tstats, w.mw.ovf, nullptr, s);
-        HIP_TRY(hipEventRecord(ev[5], s));
+            launch_truncate(nv, &w.ctl->delta, 0.0, tb_scale, w.trunc_tmp, cap, w.tstats, w.mw.ovf, done, st);
+        if (evs) HIP_TRY(hipEventRecord(evs[5], st));
         HIP_TRY(hipGetLastError());
-        cur = 1 - cur;
+        return SPAMM_OK;
+    };
+
+    int cur = 0;
+    int nlog = 0;
+    int status = SPAMM_OK;
+    if (p->graph_steps > 0) {
+        // ---- device-driven loop: two steps (X0 -> X1 -> X0) captured once,
+        // replayed until the control kernel sets done ----
+        hc.eps = p->eps;
+        hc.homo = p->homo;
+        hc.lumo = p->lumo;
+        hc.delta_const = p->delta_const;
+        hc.e_tol = p->e_tol;
+        hc.n_occ = p->n_occ;
+        hc.n_max = p->n_max;
+        hc.variant = p->variant;
+        hc.N = p->N;
+        hc.xh = xh;
+        hc.xl = xl;
+        hc.n_e = 0;
+        hc.done = 0;
+        hc.nlog = 0;
+        hc.status = SPAMM_OK;
+        hc.tiered = tiered ? 1 : 0;
+        hc.have_gap = have_gap ? 1 : 0;
+        hc.tier_split = p->tier_split;
+        hc.trunc_scale = tb_scale;
+        HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+        (void)num_cus();  // device properties are read once, outside the capture
+        struct GraphGuard {
+            hipStream_t cs = nullptr;
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            ~GraphGuard() {
+                if (ge) hipGraphExecDestroy(ge);
+                if (g) hipGraphDestroy(g);
+                if (cs) hipStreamDestroy(cs);
+            }
+        } gg;
+        HIP_TRY(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+        HIP_TRY(hipEventRecord(ev[6], s));
+        HIP_TRY(hipStreamWaitEvent(gg.cs, ev[6], 0));
+        HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
+        int rc_cap = SPAMM_OK;
+        for (int q = 0; q < 2 && rc_cap == SPAMM_OK; ++q) {
+            MatView xv = view(&w.X[q]);
+            MatView nv = view(&w.X[1 - q]);
+            launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
+                          w.trace_out, &w.ctl->done, gg.cs);
+            launch_sp2_control(w.ctl, w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, xv.nslot, w.dlog, kMaxLog,
+                               gg.cs);
+            rc_cap = enqueue_step(xv, nv, &w.ctl->done, nullptr, gg.cs);
+        }
+        hipError_t ec = hipStreamEndCapture(gg.cs, &gg.g);
+        if (rc_cap != SPAMM_OK) return rc_cap;
+        if (ec != hipSuccess) return fail(SPAMM_EHIP, "graph capture: %s", hipGetErrorString(ec));
+        HIP_TRY(hipGraphInstantiate(&gg.ge, gg.g, nullptr, nullptr, 0));
+        const int per_poll = std::max(1, (p->graph_steps + 1) / 2);
+        const int max_replays = p->n_max / 2 + 2;  // n_max + 4 control steps: the stop always fires
+        int32_t done = 0;
+        for (int r = 0; r < max_replays && !done;) {
+            for (int q = 0; q < per_poll && r < max_replays; ++q, ++r) HIP_TRY(hipGraphLaunch(gg.ge, gg.cs));
+            HIP_TRY(hipMemcpyAsync(&done, &w.ctl->done, sizeof(done), hipMemcpyDeviceToHost, gg.cs));
+            HIP_TRY(hipStreamSynchronize(gg.cs));
+        }
+        Sp2Ctl cs;
+        int64_t msc[4];
+        HIP_TRY(hipMemcpyAsync(&cs, w.ctl, sizeof(cs), hipMemcpyDeviceToHost, gg.cs));
+        HIP_TRY(hipMemcpyAsync(msc, w.mw.sc, sizeof(msc), hipMemcpyDeviceToHost, gg.cs));
+        HIP_TRY(hipStreamSynchronize(gg.cs));
+        if (!done) return fail(SPAMM_EHIP, "device loop did not reach its stop");
+        nlog = cs.nlog;
+        if (nlog > 0)
+            HIP_TRY(hipMemcpy(log, w.dlog, sizeof(sp2_iter_log) * (size_t)nlog, hipMemcpyDeviceToHost));
+        if (cs.status == SPAMM_ECAPACITY) {
+            status = fail(SPAMM_ECAPACITY, "capacity exceeded in iteration %d (pairs %lld of %lld)", nlog,
+                          (long long)msc[0], (long long)max_pairs);
+        } else {
+            status = cs.status;
+        }
+        cur = (nlog - 1) & 1;
+    } else {
+        std::vector<double> e_hist;
+        for (int it = 1;; ++it) {
+            spamm_bsm* Xc = tape_steps > 0 ? &w.tape[it - 1] : &w.X[cur];
+            spamm_bsm* Xn = tape_steps > 0 ? (it <= tape_steps ? &w.tape[it] : nullptr) : &w.X[1 - cur];
+            MatView xv = view(Xc);
+            launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
+                          w.trace_out, nullptr, s);
+            double tr[4];
+            int64_t msc[4], ts[2];
+            int32_t ovf[2];
+            Sp2Ctl cs;
+            HIP_TRY(hipMemcpyAsync(tr, w.trace_out, sizeof(tr), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(msc, w.mw.sc, sizeof(msc), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(ts, w.tstats, sizeof(ts), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&ovf[0], w.mw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&ovf[1], w.sw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&cs, w.ctl, sizeof(cs), hipMemcpyDeviceToHost, s));
+            int32_t nsl = 0;
+            HIP_TRY(hipMemcpyAsync(&nsl, xv.nslot, sizeof(nsl), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (ovf[0] || ovf[1]) {
+                status = fail(SPAMM_ECAPACITY, "capacity exceeded in iteration %d (flags %d/%d; pairs %lld of %lld)",
+                              it - 1, ovf[0], ovf[1], (long long)msc[0], (long long)max_pairs);
+                break;
+            }
+            if (nlog > 0) {
+                sp2_iter_log& L = log[nlog - 1];
+                L.idx = cs.idx;
+                L.tau = cs.tau;
+                L.npairs = msc[0];
+                L.nout = msc[1];
+                L.nslot_hat = msc[2];
+                L.removed_units = ts[0];
+                L.removed_fro2 = (double)ts[1] * trunc_quantum(L.delta * tb_scale);
+                L.nslot_kept = nsl;
+                L.npairs_low = tiered ? msc[3] : 0;
+                L.sigma = cs.sigma;
+                L.sidx = cs.sidx;
+                float ms = 0;
+                hipEventElapsedTime(&ms, ev[0], ev[1]); L.ms_sweep = ms;
+                hipEventElapsedTime(&ms, ev[1], ev[2]); L.ms_pairs = ms;
+                hipEventElapsedTime(&ms, ev[2], ev[3]); L.ms_gemm = ms;
+                hipEventElapsedTime(&ms, ev[3], ev[4]); L.ms_norms = ms;
+                hipEventElapsedTime(&ms, ev[4], ev[5]); L.ms_trunc = ms;
+                hipEventElapsedTime(&ms, ev[0], ev[5]); L.ms_total = ms;
+            }
+            const double t1 = tr[0], t2 = tr[2];
+            const double e = dd_diff(tr[0], tr[1], tr[2], tr[3]);
+            e_hist.push_back(e);
+            sp2_iter_log& L = log[nlog++];
+            memset(&L, 0, sizeof(L));
+            L.i = it;
+            L.t1 = t1;
+            L.t2 = t2;
+            L.e = e;
+            L.branch = -1;
+            const bool stop = should_stop(e_hist, p->e_tol);
+            if (stop || it > p->n_max || Xn == nullptr) {
+                L.stop = stop ? 1 : 2;
+                if (!stop) status = SPAMM_WNOCONV;
+                break;
+            }
+            const int br = choose_branch(t1, t2, p->n_occ);
+            if (have_gap) {
+                xh = map_gap(xh, br);
+                xl = map_gap(xl, br);
+            }
+            const double delta = step_delta(p, xh - xl);
+            L.branch = br;
+            L.delta = delta;
+            hc.branch = br;
+            hc.delta = delta;
+            hc.budget = p->variant == 0 ? delta / 2.0 : delta;
+            hc.budget_skip = tiered ? p->tier_split * hc.budget : hc.budget;
+            hc.tau = 0.0;
+            hc.idx = p->N;
+            hc.sigma = 0.0;
+            hc.sidx = p->N;
+            HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+            const int rc_step = enqueue_step(xv, view(Xn), nullptr, ev, s);
+            if (rc_step != SPAMM_OK) return rc_step;
+            cur = 1 - cur;
+        }
     }
     // final: copy the last iterate into D
     if (status >= 0) {

@@ -3,6 +3,7 @@
 // include/spamm.h.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -130,7 +131,53 @@ struct Sp2Ctl {
     // precision tiers: low-precision limit sigma and its candidate index
     double sigma, budget_skip;
     int32_t sidx, pad5;
+    // device-driven loop: inputs of the decision rules and the run's status
+    double tier_split, trunc_scale;
+    int32_t tiered, have_gap, nlog, status;
 };
+
+// ---------------------------------------------------------------------------
+// Decision rules of the purification loop, shared by the host loop and the
+// device control kernel so both take identical decisions (double precision,
+// one rounding per operation, no contraction).
+// ---------------------------------------------------------------------------
+// delta_i = eps * g / (4 n_max) from the mapped gap g, or the given constant
+SPAMM_HD double sp2_step_delta(double eps, int n_max, double delta_const, double gap) {
+    if (!(delta_const != delta_const)) return delta_const;  // not NaN: explicit delta
+    return eps * gap / (4.0 * (double)n_max);
+}
+// SP2: x^2 (0) when its trace lands closer to n_occ, else 2x - x^2 (1)
+SPAMM_HD int sp2_choose_branch(double t1, double t2, int64_t n_occ) {
+    const double no = (double)n_occ;
+    return fabs(t2 - no) <= fabs((2.0 * t1 - t2) - no) ? 0 : 1;
+}
+SPAMM_HD double sp2_map_gap(double x, int br) { return br == 0 ? x * x : 2.0 * x - x * x; }
+// stop when |e_i| <= e_tol, or at the noise floor: |e_i| >= |e_{i-2}| once
+// |e_{i-2}| < 1e-3.  e: the last n_e values, most recent first (n_e <= 3).
+SPAMM_HD bool sp2_should_stop(const double* e, int n_e, double e_tol) {
+    if (n_e < 1) return false;
+    if (fabs(e[0]) <= e_tol) return true;
+    if (n_e >= 3 && fabs(e[2]) < 1e-3 && fabs(e[0]) >= fabs(e[2])) return true;
+    return false;
+}
+// RN(a - b) for double-doubles a = ahi + alo, b = bhi + blo
+SPAMM_HD double dd_diff(double ahi, double alo, double bhi, double blo) {
+    double s = ahi - bhi;
+    double bb = s - ahi;
+    double e = (ahi - (s - bb)) + (-bhi - bb);
+    e = e + (alo - blo);
+    return s + e;
+}
+// quantum of the truncation keys: 2^(floor(log2 RN(delta^2)) - 40)
+SPAMM_HD double sp2_trunc_quantum(double delta) {
+    const double T = delta * delta;
+    if (!(T > 0.0) || !(T <= 1.7976931348623157e308)) return 0.0;
+    int e;
+    frexp(T, &e);
+    int eq = e - 1 - 40;
+    if (eq < -1000) eq = -1000;
+    return ldexp(1.0, eq);
+}
 
 // flags in Sp2Ctl::overflow
 constexpr int kOvfPairs = 1, kOvfOut = 2, kOvfSlots = 4, kOvfCubes = 8, kOvfCand = 16;

@@ -2,6 +2,8 @@
 #pragma once
 #include "common.hpp"
 
+struct sp2_iter_log;  // include/spamm.h
+
 namespace spamm {
 
 // A block-sparse matrix as the kernels see it (see spamm_bsm in spamm.h).
@@ -21,7 +23,7 @@ struct MatView {
 
 // norms.hip
 void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, double* sq,
-                  double* sqlo, double* nrm, hipStream_t s);
+                  double* sqlo, double* nrm, hipStream_t s, const int32_t* done = nullptr);
 size_t traces_temp_bytes();
 void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
                    const double* val, const double* sq, const double* sqlo, double* temp, double* out,
@@ -118,6 +120,11 @@ void launch_adj_pairs(int nb, int nw, int64_t cap_out, const int64_t* nout, cons
                       int64_t cap_pairs, int2* pairs, int32_t* ovf, void* scan_tmp, hipStream_t s);
 void launch_adj_fbar(const MatView& F, const int32_t* map0, const double* g0, const double* lam, double* fbar,
                      hipStream_t s);
+
+// control.hip
+void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
+                        const int32_t* ovf_sweep, const int32_t* nslot_cur, ::sp2_iter_log* logs, int max_records,
+                        hipStream_t s);
 
 // trunc.hip
 size_t trunc_temp_bytes(int64_t cap);

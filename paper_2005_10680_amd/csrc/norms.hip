@@ -108,8 +108,9 @@ template <int B>
 __global__ __launch_bounds__(256) void k_norms(const int32_t* __restrict__ nslot_p, int64_t cap,
                                               const int32_t* __restrict__ brow, const double* __restrict__ val,
                                               double* __restrict__ sq, double* __restrict__ sqlo,
-                                              double* __restrict__ nrm) {
+                                              double* __restrict__ nrm, const int32_t* __restrict__ done) {
     __shared__ uint32_t slow[4][kLimbs];
+    if (done && *done) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int64_t nslot = *nslot_p;
     if (nslot > cap) nslot = cap;
@@ -170,12 +171,12 @@ __global__ __launch_bounds__(256) void k_norms(const int32_t* __restrict__ nslot
 }
 
 void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, double* sq,
-                  double* sqlo, double* nrm, hipStream_t s) {
+                  double* sqlo, double* nrm, hipStream_t s, const int32_t* done) {
     int grid = grid_for(cap, 4, 8192);
     switch (b) {
-        case 32: hipLaunchKernelGGL(k_norms<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm); break;
-        case 64: hipLaunchKernelGGL(k_norms<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm); break;
-        case 128: hipLaunchKernelGGL(k_norms<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm); break;
+        case 32: hipLaunchKernelGGL(k_norms<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done); break;
+        case 64: hipLaunchKernelGGL(k_norms<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done); break;
+        case 128: hipLaunchKernelGGL(k_norms<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done); break;
     }
 }
 
