@@ -51,6 +51,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verify", action="store_true", help="check ||D - D~||_F with a dense eigensolver")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision purification")
+    ap.add_argument("--graph", type=int, default=8,
+                    help="also time the graph-captured loop, polling every K iterations (0: skip)")
+    ap.add_argument("--adjoint", action="store_true", help="also time the reverse mode (tape + adjoint)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -77,9 +80,9 @@ def main():
     max_pairs = nb * nb * (nb + 1) // 2
     eps = 1e-6
 
-    def run_once(precision="fp64"):
-        return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap, max_pairs=max_pairs,
-                        precision=precision)
+    def run_once(precision="fp64", graph_steps=0, keep_tape=False, cap_=None):
+        return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap_ or cap,
+                        max_pairs=max_pairs, precision=precision, graph_steps=graph_steps, keep_tape=keep_tape)
 
     log(f"input ready: n={n} leaf={b} blocks={Fh.nblk}")
     for w in range(args.warmup):
@@ -135,6 +138,46 @@ def main():
                      "avg_launch_ms": round(avg_gemm_ms, 4),
                      "flops_per_launch": gemm_flops / ngemm},
     }
+
+    # the same purification as a replayed graph with decisions on the device
+    if args.graph > 0:
+        run_once(graph_steps=args.graph)
+        gtimes = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rg = run_once(graph_steps=args.graph)
+            torch.cuda.synchronize()
+            gtimes.append(time.perf_counter() - t0)
+        gsteps = [l for l in rg.logs if l["branch"] >= 0]
+        same = sum(l["npairs"] for l in gsteps) == sum(l["npairs"] for l in steps) and len(gsteps) == len(steps)
+        log(f"graph loop: {float(np.median(gtimes)):.3f} s, {len(gsteps)} iterations")
+        out["graph_loop"] = {"poll_every": args.graph, "sp2_time_s": round(float(np.median(gtimes)), 4),
+                             "kept_TFLOP_per_s": round(flops / args.steps / float(np.median(gtimes)) / 1e12, 4),
+                             "speedup_vs_host_loop": round(float(np.median(times)) / float(np.median(gtimes)), 4),
+                             "same_decisions": bool(same)}
+
+    # reverse mode: forward with a tape, then the adjoint of a random loss
+    if args.adjoint:
+        live_max = max(l["nslot_hat"] for l in steps) + nb
+        capt = int(min(cap, live_max * 1.1 + 64))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rt = run_once(keep_tape=True, cap_=capt)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        g = torch.Generator(device=dev).manual_seed(0)
+        dbar = torch.randn(capt * b * b, dtype=torch.float64, device=dev, generator=g)
+        P.purify_adjoint(rt, F, dbar)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.purify_adjoint(rt, F, dbar)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        log(f"adjoint: forward with tape {t_fwd:.3f} s, adjoint {t_adj:.3f} s")
+        out["adjoint"] = {"forward_with_tape_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
+                          "tape_entries": rt.nlog, "cap_blocks": capt}
+        del rt, dbar
 
     # mixed precision (FP32 leaf-product tier) on the same workload
     res_mixed = None

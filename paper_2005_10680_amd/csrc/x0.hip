@@ -9,15 +9,24 @@
 
 namespace spamm {
 
-// per-row disc: centre f_rr, radius RN(sum_{c != r} |f_rc|) (double-double sum)
-__global__ void k_gersch_rows(MatView F, double* __restrict__ lo, double* __restrict__ hi) {
+// per-row disc: centre f_rr, radius RN(sum_{c != r} |f_rc|) (double-double
+// sum).  One workgroup per block row I; thread t takes row r = t % b of the
+// block row and the block columns J = t / b, t / b + P, ... (P = 256 / b),
+// so each wave reads whole block columns (coalesced) and looks the block up
+// once; the P partial sums of a row are combined in a fixed order.
+__global__ __launch_bounds__(256) void k_gersch_rows(MatView F, double* __restrict__ lo, double* __restrict__ hi) {
+    __shared__ double shi[256], slo[256], scen[256];
+    __shared__ int shas[256];
     const int64_t n = F.n;
     const int b = F.b, nb = F.nb;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
-        const int I = (int)(g / b), r = (int)(g % b);
+    const int P = 256 / b;
+    const int r = threadIdx.x % b, part = threadIdx.x / b;
+    for (int I = blockIdx.x; I < nb; I += gridDim.x) {
+        const int64_t g = (int64_t)I * b + r;
         dd rad = {0.0, 0.0};
         double cen = 0.0;
-        for (int J = 0; J < nb; ++J) {
+        bool has_cen = false;
+        for (int J = part; J < nb; J += P) {
             const int s = F.map[(size_t)I * nb + J];
             if (s < 0) continue;
             const double* v = F.val + (size_t)s * b * b;
@@ -25,13 +34,30 @@ __global__ void k_gersch_rows(MatView F, double* __restrict__ lo, double* __rest
                 const int64_t gj = (int64_t)J * b + c;
                 if (gj >= n) break;
                 const double x = v[(size_t)c * b + r];
-                if (gj == g) cen = x;
-                else rad = dd_add(rad, dd{fabs(x), 0.0});
+                if (gj == g) {
+                    cen = x;
+                    has_cen = true;
+                } else {
+                    rad = dd_add(rad, dd{fabs(x), 0.0});
+                }
             }
         }
-        const double R = rad.hi;
-        lo[g] = cen - R;
-        hi[g] = cen + R;
+        shi[threadIdx.x] = rad.hi;
+        slo[threadIdx.x] = rad.lo;
+        scen[threadIdx.x] = cen;
+        shas[threadIdx.x] = has_cen ? 1 : 0;
+        __syncthreads();
+        if (part == 0 && g < n) {
+            dd acc = {shi[r], slo[r]};
+            double c0 = shas[r] ? scen[r] : 0.0;
+            for (int q = 1; q < P; ++q) {
+                acc = dd_add(acc, dd{shi[q * b + r], slo[q * b + r]});
+                if (shas[q * b + r]) c0 = scen[q * b + r];  // the part that met column g
+            }
+            lo[g] = c0 - acc.hi;
+            hi[g] = c0 + acc.hi;
+        }
+        __syncthreads();
     }
 }
 
@@ -60,7 +86,7 @@ __global__ __launch_bounds__(1024) void k_gersch_final(const double* __restrict_
 }
 
 void launch_gersch(const MatView& F, double* rowtmp, double* lam, hipStream_t s) {
-    hipLaunchKernelGGL(k_gersch_rows, dim3(grid_for(F.n, 256, 4096)), dim3(256), 0, s, F, rowtmp, rowtmp + F.n);
+    hipLaunchKernelGGL(k_gersch_rows, dim3(grid_for(F.nb, 1, 4096)), dim3(256), 0, s, F, rowtmp, rowtmp + F.n);
     hipLaunchKernelGGL(k_gersch_final, dim3(1), dim3(1024), 0, s, rowtmp, rowtmp + F.n, F.n, lam);
 }
 
