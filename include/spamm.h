@@ -275,6 +275,31 @@ int purify_sp2_adjoint(const spamm_bsm* F, const spamm_bsm* tape, int32_t ntape,
                        int32_t nlog, const double* dbar_val, double* fbar_val, void* ws, size_t ws_bytes,
                        spamm_stream_t stream);
 
+/*
+ * Batched purification of nsys independent systems (not in the paper; each
+ * system is Algorithm 5/4/1 exactly as purify_sp2 runs it).  The step of
+ * every system is captured once in a HIP graph with the decisions on the
+ * device (as purify_sp2 with graph_steps > 0) and replayed until every
+ * system has stopped; systems that stop early drop out of the later steps.
+ * Per step there is ONE persistent launch of the leaf-product kernel for
+ * all systems of a leaf size and tier: it walks the concatenation of their
+ * output lists, balanced by kept-pair count over the 8 XCDs.  Each system's
+ * result, records and status are bit-identical to its own purify_sp2 run.
+ *   F, p, D    : host arrays [nsys] (same contracts as purify_sp2; keep_tape
+ *                must be 0; capacities D[q].cap).
+ *   max_pairs  : host [nsys] kept-pair capacity per system.
+ *   log        : host [nsys * log_stride], log_stride >= n_max + 2 of every
+ *                system; nlog_out, status_out: host [nsys].
+ *   graph_steps: the largest of the systems' values is the poll interval.
+ * Returns the worst status (negative if any system failed; the others
+ * still carry their results).  Synchronises the stream.
+ */
+size_t purify_sp2_batched_workspace_bytes(int32_t nsys, const spamm_bsm* F, const sp2_params* p,
+                                          const int64_t* cap_blocks, const int64_t* max_pairs);
+int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, spamm_bsm* D,
+                       const int64_t* max_pairs, sp2_iter_log* log, int32_t log_stride, int32_t* nlog_out,
+                       int32_t* status_out, void* ws, size_t ws_bytes, spamm_stream_t stream);
+
 const char* spamm_status_str(int code);
 const char* spamm_last_error(void);
 int spamm_version(void);

@@ -109,6 +109,10 @@ def lib() -> ctypes.CDLL:
     L.purify_sp2_adjoint_workspace_bytes.argtypes = [i32, i32, i64, i64]
     L.purify_sp2_adjoint_workspace_bytes.restype = sz
     L.purify_sp2_adjoint.argtypes = [B, B, i32, ctypes.POINTER(sp2_iter_log), i32, P, P, P, sz, P]
+    L.purify_sp2_batched_workspace_bytes.argtypes = [i32, B, ctypes.POINTER(sp2_params), P, P]
+    L.purify_sp2_batched_workspace_bytes.restype = sz
+    L.purify_sp2_batched.argtypes = [i32, B, ctypes.POINTER(sp2_params), B, P, ctypes.POINTER(sp2_iter_log), i32,
+                                     P, P, P, sz, P]
     L.spamm_status_str.argtypes = [ctypes.c_int]
     L.spamm_status_str.restype = ctypes.c_char_p
     L.spamm_last_error.restype = ctypes.c_char_p
@@ -417,6 +421,57 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
     out = [{k: getattr(logs[i], k) for k, _ in sp2_iter_log._fields_} for i in range(nlog.value)]
     targs = (nb, b, N, int(cap), int(mp), tape_steps) if keep_tape else None
     return PurifyResult(D, out, rc, ws, targs, logs, nlog.value)
+
+
+@dataclass
+class BatchResult:
+    D: list        # BlockSparse per system
+    logs: list     # per system: list of record dicts
+    status: list   # per system
+    rc: int        # worst status
+
+
+def purify_batched(Fs, n_occ, eps, taus, homo, lumo, variant="hybrid", n_max=60, delta_const=float("nan"),
+                   e_tol=0.0, caps=None, max_pairs=None, precision="fp64", tier_split=0.5, graph_steps=8,
+                   raise_on_error=True) -> BatchResult:
+    """Purify independent systems together (purify_sp2_batched): per step one
+    persistent product launch for all systems of a leaf size and tier.
+    Per-system arguments (n_occ, homo, lumo, taus, variant, precision,
+    caps, max_pairs) are lists or one value for all."""
+    ns = len(Fs)
+
+    def per(v):
+        return list(v) if isinstance(v, (list, tuple)) else [v] * ns
+    n_occ, homo, lumo, variant, precision = per(n_occ), per(homo), per(lumo), per(variant), per(precision)
+    taus_l = taus if isinstance(taus, (list, tuple)) else [taus] * ns
+    dev = Fs[0].device
+    tt = [torch.as_tensor(t, dtype=torch.float64, device=dev).contiguous() for t in taus_l]
+    caps = per(caps) if caps is not None else [F.nb * F.nb for F in Fs]
+    mps = per(max_pairs) if max_pairs is not None else [max(1, F.nb * F.nb * (F.nb + 1) // 2) for F in Fs]
+    Fa = (spamm_bsm * ns)(*[F.struct() for F in Fs])
+    Ds = [BlockSparse(F.n, F.b, int(cp), dev) for F, cp in zip(Fs, caps)]
+    Da = (spamm_bsm * ns)(*[D.struct() for D in Ds])
+    pa = (sp2_params * ns)()
+    for q in range(ns):
+        pa[q] = sp2_params(int(n_occ[q]), float(eps), int(n_max), VARIANTS[variant[q]], tt[q].data_ptr(),
+                           int(tt[q].shape[0]), float(homo[q]), float(lumo[q]), float(delta_const), float(e_tol), 0,
+                           {"fp64": 0, "fp32": 1}[precision[q]], float(tier_split), int(graph_steps), 0)
+    capa = (ctypes.c_int64 * ns)(*[int(c) for c in caps])
+    mpa = (ctypes.c_int64 * ns)(*[int(m) for m in mps])
+    need = lib().purify_sp2_batched_workspace_bytes(ns, Fa, pa, capa, mpa)
+    if need == 0:
+        raise ValueError("bad batch arguments")
+    ws = _ws(need, dev)
+    stride = n_max + 2
+    logs = (sp2_iter_log * (ns * stride))()
+    nlog = (ctypes.c_int32 * ns)()
+    st = (ctypes.c_int32 * ns)()
+    rc = lib().purify_sp2_batched(ns, Fa, pa, Da, mpa, logs, stride, nlog, st, _ptr(ws), ws.numel(), _stream())
+    if rc < 0 and raise_on_error:
+        _check(rc)
+    out = [[{k: getattr(logs[q * stride + i], k) for k, _ in sp2_iter_log._fields_} for i in range(nlog[q])]
+           for q in range(ns)]
+    return BatchResult(Ds, out, [int(x) for x in st], int(rc))
 
 
 def adjoint_step(X: BlockSparse, G: BlockSparse, tau: float, branch: int, max_pairs=None):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "../../include/spamm.h"
@@ -368,6 +369,30 @@ void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, 
     w.x32 = precision ? c.take<float>((size_t)cap * b * b) : nullptr;
 }
 
+// argument checks shared by the single and the batched purification
+int check_sp2(const spamm_bsm* F, const sp2_params* p, const spamm_bsm* D) {
+    int rc = check_bsm(F, "F", false);
+    if (!rc) rc = check_bsm(D, "D", true);
+    if (rc) return rc;
+    if (!p) return fail(SPAMM_EINVAL, "NULL parameters");
+    if (D->nb != F->nb || D->b != F->b || D->n != F->n) return fail(SPAMM_EINVAL, "D must match F");
+    if (p->n_max < 1 || p->n_max > 10000) return fail(SPAMM_EINVAL, "n_max out of range");
+    if (p->variant < 0 || p->variant > 2) return fail(SPAMM_EINVAL, "variant must be 0, 1 or 2");
+    if (p->N < 1 || p->N > 1024 || !p->tau) return fail(SPAMM_EINVAL, "bad candidate list");
+    if (p->n_occ < 0 || p->n_occ > F->n) return fail(SPAMM_EINVAL, "n_occ out of range");
+    const bool have_gap = !isnan(p->homo) && !isnan(p->lumo);
+    if (!have_gap && isnan(p->delta_const)) return fail(SPAMM_EINVAL, "need homo/lumo or delta_const");
+    if (have_gap && !(p->homo < p->lumo)) return fail(SPAMM_EINVAL, "need homo < lumo");
+    if (!(p->eps > 0.0)) return fail(SPAMM_EINVAL, "eps must be > 0");
+    if (p->precision != 0 && p->precision != 1) return fail(SPAMM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 tier)");
+    if (p->graph_steps < 0) return fail(SPAMM_EINVAL, "graph_steps must be >= 0");
+    if (p->graph_steps > 0 && p->keep_tape) return fail(SPAMM_EINVAL, "graph mode needs keep_tape = 0");
+    if (p->precision == 1 && F->b > 64) return fail(SPAMM_ENOTSUP, "the FP32 tier supports leaf 32 and 64");
+    if (p->precision == 1 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
+        return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
+    return SPAMM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // adjoint workspace: one reverse step (pair list on the pattern of X)
 // ---------------------------------------------------------------------------
@@ -665,25 +690,10 @@ int purify_sp2_tape_view(void* ws, int32_t nb, int32_t b, int32_t N, int64_t cap
 
 int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out, void* ws,
                size_t ws_bytes, spamm_stream_t stream) {
-    int rc = check_bsm(F, "F", false);
-    if (!rc) rc = check_bsm(D, "D", true);
+    if (!log || !nlog_out) return fail(SPAMM_EINVAL, "NULL argument");
+    int rc = check_sp2(F, p, D);
     if (rc) return rc;
-    if (!p || !log || !nlog_out) return fail(SPAMM_EINVAL, "NULL argument");
-    if (D->nb != F->nb || D->b != F->b || D->n != F->n) return fail(SPAMM_EINVAL, "D must match F");
-    if (p->n_max < 1 || p->n_max > 10000) return fail(SPAMM_EINVAL, "n_max out of range");
-    if (p->variant < 0 || p->variant > 2) return fail(SPAMM_EINVAL, "variant must be 0, 1 or 2");
-    if (p->N < 1 || p->N > 1024 || !p->tau) return fail(SPAMM_EINVAL, "bad candidate list");
-    if (p->n_occ < 0 || p->n_occ > F->n) return fail(SPAMM_EINVAL, "n_occ out of range");
     const bool have_gap = !isnan(p->homo) && !isnan(p->lumo);
-    if (!have_gap && isnan(p->delta_const)) return fail(SPAMM_EINVAL, "need homo/lumo or delta_const");
-    if (have_gap && !(p->homo < p->lumo)) return fail(SPAMM_EINVAL, "need homo < lumo");
-    if (!(p->eps > 0.0)) return fail(SPAMM_EINVAL, "eps must be > 0");
-    if (p->precision != 0 && p->precision != 1) return fail(SPAMM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 tier)");
-    if (p->graph_steps < 0) return fail(SPAMM_EINVAL, "graph_steps must be >= 0");
-    if (p->graph_steps > 0 && p->keep_tape) return fail(SPAMM_EINVAL, "graph mode needs keep_tape = 0");
-    if (p->precision == 1 && F->b > 64) return fail(SPAMM_ENOTSUP, "the FP32 tier supports leaf 32 and 64");
-    if (p->precision == 1 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
-        return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
     const bool tiered = p->precision == 1;
     const double c_low = tier_constant(p->precision, F->b);
     const int nb = F->nb, b = F->b;
@@ -713,7 +723,8 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
         HIP_TRY(hipStreamSynchronize(s));
         nf = t;
     }
-    if (nf + nb > cap) return fail(SPAMM_ECAPACITY, "D->cap must be at least nslot(F) + nb");
+    if (nf + nb > cap && cap < (int64_t)nb * nb)
+        return fail(SPAMM_ECAPACITY, "D->cap must be at least min(nslot(F) + nb, nb^2)");
 
     hipEvent_t ev[8];
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
@@ -1082,6 +1093,308 @@ int purify_sp2_adjoint(const spamm_bsm* F, const spamm_bsm* tape, int32_t ntape,
     HIP_TRY(hipGetLastError());
     if (ovf) return fail(SPAMM_ECAPACITY, "adjoint pair list exceeded %lld pairs", (long long)max_pairs);
     return SPAMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched purification of independent systems
+// ---------------------------------------------------------------------------
+size_t purify_sp2_batched_workspace_bytes(int32_t nsys, const spamm_bsm* F, const sp2_params* p,
+                                          const int64_t* cap_blocks, const int64_t* max_pairs) {
+    if (nsys < 1 || nsys > 4096 || !F || !p || !cap_blocks || !max_pairs) return 0;
+    Carver c(nullptr);
+    for (int q = 0; q < nsys; ++q) {
+        if (F[q].nb < 1 || p[q].N < 1 || cap_blocks[q] < 1 || max_pairs[q] < 0) return 0;
+        Sp2Ws w;
+        carve_sp2(c, F[q].nb, F[q].b, p[q].N, cap_blocks[q], max_pairs[q], 0, w, p[q].precision);
+    }
+    c.take<GemmArgs>(2 * (size_t)nsys);        // descriptors, two parities
+    c.take<int64_t>(2 * (size_t)(nsys + 1) * 5);  // out_off / pair_off per group (<= 5 groups)
+    c.take<int32_t>(16 * 5);                     // work counters per group
+    c.take<Sp2Ctl*>(nsys);
+    c.take<int32_t>(4);
+    return c.off + 256;
+}
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_all_done(Sp2Ctl* const* __restrict__ ctls, int nsys, int32_t* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int all = 1;
+    for (int q = 0; q < nsys; ++q) all &= ctls[q]->done ? 1 : 0;
+    *out = all;
+}
+
+}  // namespace
+
+extern "C" {
+
+int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, spamm_bsm* D,
+                       const int64_t* max_pairs, sp2_iter_log* log, int32_t log_stride, int32_t* nlog_out,
+                       int32_t* status_out, void* ws, size_t ws_bytes, spamm_stream_t stream) {
+    if (nsys < 1 || nsys > 4096) return fail(SPAMM_EINVAL, "nsys must be in 1..4096");
+    if (!F || !p || !D || !max_pairs || !log || !nlog_out || !status_out) return fail(SPAMM_EINVAL, "NULL argument");
+    std::vector<int64_t> caps(nsys);
+    for (int q = 0; q < nsys; ++q) {
+        int rc = check_sp2(&F[q], &p[q], &D[q]);
+        if (rc) return fail(rc, "system %d: %s", q, std::string(g_err).c_str());
+        if (p[q].keep_tape) return fail(SPAMM_EINVAL, "system %d: the batched loop keeps no tape", q);
+        if (log_stride < p[q].n_max + 2) return fail(SPAMM_EINVAL, "log_stride must be at least n_max + 2");
+        if (max_pairs[q] < 1 || max_pairs[q] >= ((int64_t)1 << 31))
+            return fail(SPAMM_EINVAL, "system %d: max_pairs out of range", q);
+        caps[q] = D[q].cap;
+    }
+    const size_t need = purify_sp2_batched_workspace_bytes(nsys, F, p, caps.data(), max_pairs);
+    if (!ws || ws_bytes < need) return fail(SPAMM_EWORKSPACE, "batched purification needs %zu workspace bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    Carver c(ws);
+    std::vector<Sp2Ws> W(nsys);
+    for (int q = 0; q < nsys; ++q) carve_sp2(c, F[q].nb, F[q].b, p[q].N, caps[q], max_pairs[q], 0, W[q], p[q].precision);
+    GemmArgs* descs_dev = c.take<GemmArgs>(2 * (size_t)nsys);
+    int64_t* offs = c.take<int64_t>(2 * (size_t)(nsys + 1) * 5);
+    int32_t* counters = c.take<int32_t>(16 * 5);
+    Sp2Ctl** ctls_dev = c.take<Sp2Ctl*>(nsys);
+    int32_t* all_done = c.take<int32_t>(4);
+    if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
+
+    // groups of systems sharing one product launch: same leaf size and tier
+    struct Group {
+        int b;
+        bool low;
+        std::vector<int> sys;
+    };
+    std::vector<Group> groups;
+    for (int q = 0; q < nsys; ++q) {
+        const bool low = p[q].precision == 1;
+        int gi = -1;
+        for (size_t k = 0; k < groups.size(); ++k)
+            if (groups[k].b == F[q].b && groups[k].low == low) gi = (int)k;
+        if (gi < 0) {
+            groups.push_back({F[q].b, low, {}});
+            gi = (int)groups.size() - 1;
+        }
+        groups[gi].sys.push_back(q);
+    }
+
+    // prologue of every system: X_0, its norms, the Gerschgorin bounds
+    std::vector<int32_t> nf(nsys);
+    std::vector<double> lam(2 * (size_t)nsys);
+    for (int q = 0; q < nsys; ++q) {
+        Sp2Ws& w = W[q];
+        fill_i32(w.mw.ovf, 1, 0, s);
+        fill_i32(w.sw.ovf, 1, 0, s);
+        fill_i64(w.tstats, 4, 0, s);
+        MatView Fv = view(&F[q]);
+        MatView X0 = view(&w.X[0]);
+        launch_gersch(Fv, w.rowtmp, w.lam, s);
+        launch_x0(Fv, w.lam, X0, w.dflag, w.dpos, w.mw.scan_tmp, w.dcount, s);
+        launch_norms(F[q].b, X0.nslot, X0.cap, X0.brow, X0.val, X0.sq, X0.sqlo, X0.norm, s);
+        HIP_TRY(hipMemcpyAsync(&lam[2 * q], w.lam, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&nf[q], F[q].nslot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<Sp2Ctl*> ctl_ptrs(nsys);
+    for (int q = 0; q < nsys; ++q) {
+        const sp2_params* pq = &p[q];
+        Sp2Ws& w = W[q];
+        if (nf[q] + F[q].nb > caps[q] && caps[q] < (int64_t)F[q].nb * F[q].nb)
+            return fail(SPAMM_ECAPACITY, "system %d: D->cap must be at least min(nslot(F) + nb, nb^2)", q);
+        const bool have_gap = !isnan(pq->homo) && !isnan(pq->lumo);
+        const double Wd = lam[2 * q + 1] - lam[2 * q];
+        const double xh = have_gap ? (lam[2 * q + 1] - pq->homo) / Wd : NAN;
+        const double xl = have_gap ? (lam[2 * q + 1] - pq->lumo) / Wd : NAN;
+        Sp2Ctl hc;
+        memset(&hc, 0, sizeof(hc));
+        hc.delta = step_delta(pq, xh - xl);
+        hc.eps = pq->eps;
+        hc.homo = pq->homo;
+        hc.lumo = pq->lumo;
+        hc.delta_const = pq->delta_const;
+        hc.e_tol = pq->e_tol;
+        hc.n_occ = pq->n_occ;
+        hc.n_max = pq->n_max;
+        hc.variant = pq->variant;
+        hc.N = pq->N;
+        hc.xh = xh;
+        hc.xl = xl;
+        hc.tiered = pq->precision == 1 ? 1 : 0;
+        hc.have_gap = have_gap ? 1 : 0;
+        hc.tier_split = pq->tier_split;
+        hc.trunc_scale = pq->variant == 0 ? 0.5 : 1.0;
+        hc.status = SPAMM_OK;
+        HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+        if (pq->variant != 1)
+            launch_truncate(view(&w.X[0]), &w.ctl->delta, 0.0, 1.0, w.trunc_tmp, caps[q], w.tstats, w.mw.ovf, nullptr,
+                            s);
+        ctl_ptrs[q] = w.ctl;
+    }
+    HIP_TRY(hipMemcpyAsync(ctls_dev, ctl_ptrs.data(), sizeof(Sp2Ctl*) * nsys, hipMemcpyHostToDevice, s));
+
+    // product descriptors: parity q reads X[q] and writes X[1 - q]; one
+    // contiguous run of descriptors per group
+    std::vector<GemmArgs> hd(2 * (size_t)nsys);
+    std::vector<int> gstart(groups.size());
+    {
+        int pos = 0;
+        for (size_t k = 0; k < groups.size(); ++k) {
+            gstart[k] = pos;
+            pos += (int)groups[k].sys.size();
+        }
+        for (int par = 0; par < 2; ++par)
+            for (size_t k = 0; k < groups.size(); ++k)
+                for (size_t t = 0; t < groups[k].sys.size(); ++t) {
+                    const int q = groups[k].sys[t];
+                    Sp2Ws& w = W[q];
+                    const bool low = p[q].precision == 1;
+                    GemmArgs g;
+                    g.b = F[q].b;
+                    g.nb = F[q].nb;
+                    g.oi = w.mw.oi;
+                    g.oj = w.mw.oj;
+                    g.optr = w.mw.optr;
+                    g.pairs = w.mw.pairs;
+                    g.nout = &w.mw.sc[1];
+                    g.npairs = &w.mw.sc[0];
+                    g.valA = w.X[par].val;
+                    g.valB = w.X[par].val;
+                    g.btrans = 1;
+                    g.sym = 1;
+                    g.map_out = w.X[1 - par].map;
+                    g.val_out = w.X[1 - par].val;
+                    g.mapX = w.X[par].map;
+                    g.valX = w.X[par].val;
+                    g.branch = &w.ctl->branch;
+                    g.counters = w.mw.counters;
+                    g.ovf = w.mw.ovf;
+                    g.done = &w.ctl->done;
+                    g.valA32 = low ? w.x32 : nullptr;
+                    g.valB32 = low ? w.x32 : nullptr;
+                    g.olow = low ? w.mw.olow : nullptr;
+                    hd[(size_t)par * nsys + gstart[k] + t] = g;
+                }
+    }
+    HIP_TRY(hipMemcpyAsync(descs_dev, hd.data(), sizeof(GemmArgs) * hd.size(), hipMemcpyHostToDevice, s));
+    (void)num_cus();
+
+    struct GraphGuard {
+        hipStream_t cs = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        hipEvent_t e = nullptr;
+        ~GraphGuard() {
+            if (ge) hipGraphExecDestroy(ge);
+            if (g) hipGraphDestroy(g);
+            if (cs) hipStreamDestroy(cs);
+            if (e) hipEventDestroy(e);
+        }
+    } gg;
+    HIP_TRY(hipEventCreate(&gg.e));
+    HIP_TRY(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+    HIP_TRY(hipEventRecord(gg.e, s));
+    HIP_TRY(hipStreamWaitEvent(gg.cs, gg.e, 0));
+    HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
+    for (int par = 0; par < 2; ++par) {
+        // decisions of every system from the traces of its current iterate
+        for (int q = 0; q < nsys; ++q) {
+            Sp2Ws& w = W[q];
+            MatView xv = view(&w.X[par]);
+            launch_traces(xv.nslot, xv.cap, F[q].b, F[q].n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
+                          w.trace_out, &w.ctl->done, gg.cs);
+            launch_sp2_control(w.ctl, w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, xv.nslot, w.dlog, kMaxLog,
+                               gg.cs);
+        }
+        // sweeps, kept pairs and output patterns, system by system
+        for (int q = 0; q < nsys; ++q) {
+            Sp2Ws& w = W[q];
+            const sp2_params* pq = &p[q];
+            const bool tiered = pq->precision == 1;
+            const int32_t* done = &w.ctl->done;
+            MatView xv = view(&w.X[par]);
+            MatView nv = view(&w.X[1 - par]);
+            if (pq->variant != 2)
+                run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
+                          &w.ctl->tau, w.sw, done, gg.cs);
+            if (tiered) {
+                run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau,
+                          tier_constant(pq->precision, F[q].b), w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done,
+                          gg.cs);
+                launch_to_f32(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, gg.cs);
+            }
+            run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
+                      &w.ctl->branch, done, gg.cs);
+        }
+        // one persistent product launch per group over all its systems
+        for (size_t k = 0; k < groups.size(); ++k) {
+            const size_t ng = groups[k].sys.size();
+            int64_t* out_off = offs + (size_t)k * 2 * (nsys + 1);
+            int64_t* pair_off = out_off + (nsys + 1);
+            launch_gemm_batch(groups[k].b, groups[k].low, descs_dev + (size_t)par * nsys + gstart[k], (int)ng, out_off,
+                              pair_off, counters + 16 * k, num_cus(), gg.cs);
+        }
+        // pass-through blocks, norms and truncation of every system
+        for (int q = 0; q < nsys; ++q) {
+            Sp2Ws& w = W[q];
+            const sp2_params* pq = &p[q];
+            const int32_t* done = &w.ctl->done;
+            MatView xv = view(&w.X[par]);
+            MatView nv = view(&w.X[1 - par]);
+            launch_rest(F[q].b, nv.nslot, nv.cap, nv.brow, nv.bcol, w.fromc, F[q].nb, xv.map, xv.val, nv.val,
+                        &w.ctl->branch, done, gg.cs);
+            launch_norms(F[q].b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, gg.cs, done);
+            if (pq->variant != 1)
+                launch_truncate(nv, &w.ctl->delta, 0.0, pq->variant == 0 ? 0.5 : 1.0, w.trunc_tmp, caps[q], w.tstats,
+                                w.mw.ovf, done, gg.cs);
+        }
+    }
+    hipLaunchKernelGGL(k_all_done, dim3(1), dim3(64), 0, gg.cs, ctls_dev, nsys, all_done);
+    hipError_t ec = hipStreamEndCapture(gg.cs, &gg.g);
+    if (ec != hipSuccess) return fail(SPAMM_EHIP, "graph capture: %s", hipGetErrorString(ec));
+    HIP_TRY(hipGraphInstantiate(&gg.ge, gg.g, nullptr, nullptr, 0));
+    int n_max = 1, poll = 1;
+    for (int q = 0; q < nsys; ++q) {
+        n_max = std::max(n_max, p[q].n_max);
+        poll = std::max(poll, p[q].graph_steps);
+    }
+    const int per_poll = std::max(1, (poll + 1) / 2);
+    const int max_replays = n_max / 2 + 2;
+    int32_t done = 0;
+    for (int r = 0; r < max_replays && !done;) {
+        for (int k = 0; k < per_poll && r < max_replays; ++k, ++r) HIP_TRY(hipGraphLaunch(gg.ge, gg.cs));
+        HIP_TRY(hipMemcpyAsync(&done, all_done, sizeof(done), hipMemcpyDeviceToHost, gg.cs));
+        HIP_TRY(hipStreamSynchronize(gg.cs));
+    }
+    if (!done) return fail(SPAMM_EHIP, "batched loop did not reach its stop");
+    int worst = SPAMM_OK;
+    for (int q = 0; q < nsys; ++q) {
+        Sp2Ws& w = W[q];
+        Sp2Ctl cs;
+        HIP_TRY(hipMemcpy(&cs, w.ctl, sizeof(cs), hipMemcpyDeviceToHost));
+        const int nl = cs.nlog;
+        if (nl > 0) HIP_TRY(hipMemcpy(log + (size_t)q * log_stride, w.dlog, sizeof(sp2_iter_log) * nl,
+                                      hipMemcpyDeviceToHost));
+        nlog_out[q] = nl;
+        status_out[q] = cs.status;
+        if (cs.status < 0) {
+            worst = cs.status;
+            continue;
+        }
+        if (cs.status > 0 && worst == SPAMM_OK) worst = cs.status;
+        spamm_bsm* Xf = &w.X[(nl - 1) & 1];
+        const int64_t cap = caps[q];
+        const int b = F[q].b, nb = F[q].nb;
+        HIP_TRY(hipMemcpyAsync(D[q].nslot, Xf->nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D[q].brow, Xf->brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D[q].bcol, Xf->bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D[q].map, Xf->map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D[q].val, Xf->val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D[q].norm, Xf->norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D[q].sq, Xf->sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(D[q].sqlo, Xf->sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (worst < 0) return fail(worst, "a system of the batch failed (see status_out)");
+    return worst;
 }
 
 }  // extern "C"

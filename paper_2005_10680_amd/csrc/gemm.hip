@@ -413,15 +413,33 @@ struct RingSlot {
     }
 };
 
+// persistent grid of the ring kernels: workgroups per CU by leaf size, a
+// multiple of 8 so every XCD gets the same count
+inline int ring_grid(int b, int num_cu) {
+    const int per_cu = b == 64 ? 3 : (b == 32 ? 4 : 2);
+    return (num_cu * per_cu + 7) / 8 * 8;
+}
+
 template <int B, int LOWT>
 struct RingCtx {
     using R = RingCfg<B>;
-    const GemmArgs& g;
+    // operands of the current output (wave-uniform)
+    const int2* pairs;
+    const double* valA;
+    const double* valB;
+    const float* valA32;
+    const float* valB32;
     int p0, nlow, nst_low, nst;
     d4 acc[R::TM][R::TN];
     f4 acc32[R::TM][R::TN];
 
-    SPAMM_DEV RingCtx(const GemmArgs& g_) : g(g_) {}
+    SPAMM_DEV void bind(const GemmArgs& g) {
+        pairs = g.pairs;
+        valA = g.valA;
+        valB = g.valB;
+        valA32 = g.valA32;
+        valB32 = g.valB32;
+    }
 
     template <int SLOT>
     SPAMM_DEV void issue(int st) {
@@ -436,20 +454,20 @@ struct RingCtx {
         }
         // the pair list is read-only during the launch: read it through the
         // constant address space (scalar loads, counted apart from the copies)
-        const int2 pr = const_ld(g.pairs, p0 + pr_i);
+        const int2 pr = const_ld(pairs, p0 + pr_i);
         const char* a0;
         const char* b0;
         if (low) {
-            a0 = reinterpret_cast<const char*>(g.valA32 + (size_t)pr.x * B * B + (size_t)chunk * R::KC32 * B);
-            b0 = reinterpret_cast<const char*>(g.valB32 + (size_t)pr.y * B * B + (size_t)chunk * R::KC32 * B);
+            a0 = reinterpret_cast<const char*>(valA32 + (size_t)pr.x * B * B + (size_t)chunk * R::KC32 * B);
+            b0 = reinterpret_cast<const char*>(valB32 + (size_t)pr.y * B * B + (size_t)chunk * R::KC32 * B);
         } else if (pr.x >= 0) {
-            a0 = reinterpret_cast<const char*>(g.valA + (size_t)pr.x * B * B + (size_t)chunk * R::KC64 * B);
-            b0 = reinterpret_cast<const char*>(g.valB + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
+            a0 = reinterpret_cast<const char*>(valA + (size_t)pr.x * B * B + (size_t)chunk * R::KC64 * B);
+            b0 = reinterpret_cast<const char*>(valB + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
         } else {
             // a pair of the second kind (one's complement first slot): the
             // first operand comes from the B pool, the second from the A pool
-            a0 = reinterpret_cast<const char*>(g.valB + (size_t)(~pr.x) * B * B + (size_t)chunk * R::KC64 * B);
-            b0 = reinterpret_cast<const char*>(g.valA + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
+            a0 = reinterpret_cast<const char*>(valB + (size_t)(~pr.x) * B * B + (size_t)chunk * R::KC64 * B);
+            b0 = reinterpret_cast<const char*>(valA + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
         }
         dma_chunk<B>(a0, dst);
         dma_chunk<B>(b0, dst + R::OPB);
@@ -528,41 +546,120 @@ struct RingCtx {
     }
 };
 
+// Multiply one output block (i, j) from its pairs p0 .. p1 (the first nlow of
+// them FP32-tier) and write it (and its mirror) through the epilogue tile:
+// the combine 2X - C when beta.  d names the output's matrices.
+template <int B, int LOWT>
+SPAMM_DEV void ring_output(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int j, int p0, int p1, int nlow,
+                           bool beta, double* ldsd) {
+    using R = RingCfg<B>;
+    constexpr int PC = 8;  // epilogue columns per pass
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    cx.p0 = p0;
+    cx.nlow = LOWT ? nlow : 0;
+    cx.nst_low = cx.nlow * R::CH32;
+    cx.nst = cx.nst_low + (p1 - p0 - cx.nlow) * R::CH64;
+    const int nst = cx.nst;
+#pragma unroll
+    for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+        for (int b = 0; b < R::TN; ++b) {
+            cx.acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (LOWT != 0) cx.acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    wait_vmcnt<0>();  // nothing of the previous output stays in flight
+    if (0 < nst) cx.template issue<0>(0);
+    if (R::NS > 2 && 1 < nst) cx.template issue<1 % R::NS>(1);
+    if (R::NS > 3 && 2 < nst) cx.template issue<2 % R::NS>(2);
+    for (int st = 0; st < nst; st += R::NS) {
+        cx.template step<0>(st);
+        if (st + 1 < nst) cx.template step<1 % R::NS>(st + 1);
+        if (R::NS > 2 && st + 2 < nst) cx.template step<2 % R::NS>(st + 2);
+        if (R::NS > 3 && st + 3 < nst) cx.template step<3 % R::NS>(st + 3);
+    }
+    wait_vmcnt<0>();
+    __syncthreads();
+
+    // ---------------- epilogue through the LDS tile ----------------
+    const int sh = d.map_out[(size_t)i * d.nb + j];
+    const int sht = (d.sym && i != j) ? d.map_out[(size_t)j * d.nb + i] : -1;
+    const int sx = beta ? d.mapX[(size_t)i * d.nb + j] : -1;
+    double* dst = sh >= 0 ? d.val_out + (size_t)sh * B * B : nullptr;
+    double* dstt = sht >= 0 ? d.val_out + (size_t)sht * B * B : nullptr;
+    const double* xs = sx >= 0 ? d.valX + (size_t)sx * B * B : nullptr;
+    for (int pass = 0; pass < B / PC; ++pass) {
+        const int c0 = pass * PC;
+#pragma unroll
+        for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+            for (int b = 0; b < R::TN; ++b) {
+                const int col = wn * R::TN * 16 + b * 16 + (lane & 15);
+                if (col < c0 || col >= c0 + PC) continue;
+                const int rowb = wm * R::TM * 16 + a * 16 + (lane >> 4);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ldsd[(col - c0) * R::LDT + rowb + 4 * r] = cx.acc[a][b][r];
+            }
+        __syncthreads();
+        for (int e = tid; e < PC * B; e += 256) {
+            const int cl = e / B, row = e % B;
+            double v = ldsd[cl * R::LDT + row];
+            if (beta) {
+                const double x = xs ? xs[(size_t)(c0 + cl) * B + row] : 0.0;
+                v = 2.0 * x - v;
+                ldsd[cl * R::LDT + row] = v;
+            }
+            if (dst) dst[(size_t)(c0 + cl) * B + row] = v;
+        }
+        if (dstt) {
+            __syncthreads();
+            for (int e = tid; e < PC * B; e += 256) {
+                const int cp = e / PC, rp = e % PC;
+                dstt[(size_t)cp * B + c0 + rp] = ldsd[rp * R::LDT + cp];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// First output of XCD range xcd (0..8): outputs are cut where the running
+// pair count first reaches np * xcd / 8; pair_before(o) = pairs of the
+// outputs before o (monotone, pair_before(nout) = np).
+template <typename PB>
+SPAMM_DEV int64_t xcd_cut(int64_t nout, int64_t np, int xcd, PB&& pair_before) {
+    if (xcd >= 8) return nout;
+    const int64_t t = np * xcd / 8;
+    int64_t lo = 0, hi = nout;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pair_before(mid) < t) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
 template <int B, int LOWT>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void k_gemm_ring(GemmArgs g) {
     using R = RingCfg<B>;
     static_assert(R::NS >= 2 && R::NS <= 4, "ring depth");
-    constexpr int PC = 8;  // epilogue columns per pass, in a tile of its own
-    __shared__ double ldsd[PC * R::LDT];
+    __shared__ double ldsd[8 * R::LDT];
     __shared__ int s_o, s_lo, s_hi;
     if (g.done && *g.done) return;
     if (g.ovf && *g.ovf) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
+    const int tid = threadIdx.x;
     const int64_t nout = *g.nout;
     const int xcd = blockIdx.x % 8;
     if (tid == 0) {
         const int64_t np = g.optr[nout];
-        const int64_t t_lo = np * xcd / 8, t_hi = np * (xcd + 1) / 8;
-        int64_t lo = 0, hi = nout;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if (g.optr[mid] < t_lo) lo = mid + 1; else hi = mid;
-        }
-        s_lo = (int)lo;
-        int64_t l2 = 0, h2 = nout;
-        while (l2 < h2) {
-            int64_t mid = (l2 + h2) >> 1;
-            if (g.optr[mid] < t_hi) l2 = mid + 1; else h2 = mid;
-        }
-        s_hi = xcd == 7 ? (int)nout : (int)l2;
+        auto pb = [&](int64_t o) -> int64_t { return g.optr[o]; };
+        s_lo = (int)xcd_cut(nout, np, xcd, pb);
+        s_hi = (int)xcd_cut(nout, np, xcd + 1, pb);
     }
     __syncthreads();
     const int lo = __builtin_amdgcn_readfirstlane(s_lo), hi = __builtin_amdgcn_readfirstlane(s_hi);
     const bool beta = g.mapX && g.branch && (*g.branch == 1);
-    RingCtx<B, LOWT> cx(g);
-
+    RingCtx<B, LOWT> cx;
+    cx.bind(g);
     while (true) {
         if (tid == 0) s_o = lo + atomicAdd(&g.counters[xcd], 1);
         __syncthreads();
@@ -572,73 +669,84 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
         __syncthreads();
         if (o >= hi) break;
         const int i = const_ld(g.oi, o), j = const_ld(g.oj, o);
-        const int p0 = const_ld(g.optr, o);
-        const int p1 = const_ld(g.optr, o + 1);
-        cx.p0 = p0;
-        cx.nlow = LOWT ? const_ld(g.olow, o) : 0;
-        cx.nst_low = cx.nlow * R::CH32;
-        cx.nst = cx.nst_low + (p1 - p0 - cx.nlow) * R::CH64;
-        const int nst = cx.nst;
-#pragma unroll
-        for (int a = 0; a < R::TM; ++a)
-#pragma unroll
-            for (int b = 0; b < R::TN; ++b) {
-                cx.acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-                if constexpr (LOWT != 0) cx.acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-            }
-        wait_vmcnt<0>();  // nothing of the previous output stays in flight
-        if (0 < nst) cx.template issue<0>(0);
-        if (R::NS > 2 && 1 < nst) cx.template issue<1 % R::NS>(1);
-        if (R::NS > 3 && 2 < nst) cx.template issue<2 % R::NS>(2);
-        for (int st = 0; st < nst; st += R::NS) {
-            cx.template step<0>(st);
-            if (st + 1 < nst) cx.template step<1 % R::NS>(st + 1);
-            if (R::NS > 2 && st + 2 < nst) cx.template step<2 % R::NS>(st + 2);
-            if (R::NS > 3 && st + 3 < nst) cx.template step<3 % R::NS>(st + 3);
-        }
-        wait_vmcnt<0>();
-        __syncthreads();
+        const int p0 = const_ld(g.optr, o), p1 = const_ld(g.optr, o + 1);
+        const int nlow = LOWT ? const_ld(g.olow, o) : 0;
+        ring_output<B, LOWT>(cx, g, i, j, p0, p1, nlow, beta, ldsd);
+    }
+}
 
-        // ---------------- epilogue through the LDS tile ----------------
-        const int sh = g.map_out[(size_t)i * g.nb + j];
-        const int sht = (g.sym && i != j) ? g.map_out[(size_t)j * g.nb + i] : -1;
-        const int sx = beta ? g.mapX[(size_t)i * g.nb + j] : -1;
-        double* dst = sh >= 0 ? g.val_out + (size_t)sh * B * B : nullptr;
-        double* dstt = sht >= 0 ? g.val_out + (size_t)sht * B * B : nullptr;
-        const double* xs = sx >= 0 ? g.valX + (size_t)sx * B * B : nullptr;
-        for (int pass = 0; pass < B / PC; ++pass) {
-            const int c0 = pass * PC;
-#pragma unroll
-            for (int a = 0; a < R::TM; ++a)
-#pragma unroll
-                for (int b = 0; b < R::TN; ++b) {
-                    const int col = wn * R::TN * 16 + b * 16 + (lane & 15);
-                    if (col < c0 || col >= c0 + PC) continue;
-                    const int rowb = wm * R::TM * 16 + a * 16 + (lane >> 4);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) ldsd[(col - c0) * R::LDT + rowb + 4 * r] = cx.acc[a][b][r];
-                }
-            __syncthreads();
-            for (int e = tid; e < PC * B; e += 256) {
-                const int cl = e / B, row = e % B;
-                double v = ldsd[cl * R::LDT + row];
-                if (beta) {
-                    const double x = xs ? xs[(size_t)(c0 + cl) * B + row] : 0.0;
-                    v = 2.0 * x - v;
-                    ldsd[cl * R::LDT + row] = v;
-                }
-                if (dst) dst[(size_t)(c0 + cl) * B + row] = v;
-            }
-            if (dstt) {
-                __syncthreads();
-                for (int e = tid; e < PC * B; e += 256) {
-                    const int cp = e / PC, rp = e % PC;
-                    dstt[(size_t)cp * B + c0 + rp] = ldsd[rp * R::LDT + cp];
-                }
-            }
-            __syncthreads();
+// Several independent products in one persistent launch: system s owns the
+// global outputs out_off[s] .. out_off[s+1] and the pairs pair_off[s] ..
+// pair_off[s+1] (exclusive prefix sums over the systems, k_batch_prefix);
+// descs[s] holds its matrices and lists.
+template <int B, int LOWT>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void k_gemm_ring_batch(
+    const GemmArgs* __restrict__ descs, int nsys, const int64_t* __restrict__ out_off,
+    const int64_t* __restrict__ pair_off, int32_t* __restrict__ counters) {
+    using R = RingCfg<B>;
+    __shared__ double ldsd[8 * R::LDT];
+    __shared__ int s_o, s_lo, s_hi;
+    const int tid = threadIdx.x;
+    const int64_t nout = out_off[nsys];
+    const int xcd = blockIdx.x % 8;
+    auto sys_of = [&](int64_t o) -> int {
+        int a = 0, z = nsys - 1;  // last s with out_off[s] <= o
+        while (a < z) {
+            const int m = (a + z + 1) >> 1;
+            if (out_off[m] <= o) a = m; else z = m - 1;
+        }
+        return a;
+    };
+    if (tid == 0) {
+        const int64_t np = pair_off[nsys];
+        auto pb = [&](int64_t o) -> int64_t {
+            if (o >= nout) return np;
+            const int sy = sys_of(o);
+            return pair_off[sy] + descs[sy].optr[o - out_off[sy]];
+        };
+        s_lo = (int)xcd_cut(nout, np, xcd, pb);
+        s_hi = (int)xcd_cut(nout, np, xcd + 1, pb);
+    }
+    __syncthreads();
+    const int lo = __builtin_amdgcn_readfirstlane(s_lo), hi = __builtin_amdgcn_readfirstlane(s_hi);
+    RingCtx<B, LOWT> cx;
+    while (true) {
+        if (tid == 0) s_o = lo + atomicAdd(&counters[xcd], 1);
+        __syncthreads();
+        const int o = __builtin_amdgcn_readfirstlane(s_o);
+        __syncthreads();
+        if (o >= hi) break;
+        const int sy = __builtin_amdgcn_readfirstlane(sys_of(o));
+        const GemmArgs& d = descs[sy];
+        const int ol = o - (int)out_off[sy];
+        const int i = const_ld(d.oi, ol), j = const_ld(d.oj, ol);
+        const int p0 = const_ld(d.optr, ol), p1 = const_ld(d.optr, ol + 1);
+        const int nlow = LOWT ? const_ld(d.olow, ol) : 0;
+        const bool beta = d.mapX && d.branch && (*d.branch == 1);
+        cx.bind(d);
+        ring_output<B, LOWT>(cx, d, i, j, p0, p1, nlow, beta, ldsd);
+    }
+}
+
+// out_off / pair_off over the systems whose step runs (not done, no overflow)
+__global__ void k_batch_prefix(const GemmArgs* __restrict__ descs, int nsys, int64_t* __restrict__ out_off,
+                               int64_t* __restrict__ pair_off) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t ao = 0, ap = 0;
+    for (int s = 0; s < nsys; ++s) {
+        out_off[s] = ao;
+        pair_off[s] = ap;
+        const GemmArgs& d = descs[s];
+        const bool skip = (d.done && *d.done) || (d.ovf && *d.ovf);
+        if (!skip) {
+            const int64_t n = *d.nout;
+            ao += n;
+            ap += d.optr[n];
         }
     }
+    out_off[nsys] = ao;
+    pair_off[nsys] = ap;
 }
 
 __global__ void k_reset_counters(int32_t* c) {
@@ -660,8 +768,7 @@ void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev
         case 128: SPAMM_G(128, T_, 0); break; /* no FP32 tier at leaf 128 */ \
     }
     if (g.btrans) {
-        const int per_cu_ring = g.b == 64 ? 3 : (g.b == 32 ? 4 : 2);
-        int gr = (num_cu * per_cu_ring + 7) / 8 * 8;
+        const int gr = ring_grid(g.b, num_cu);
         switch (g.b) {
             case 32: if (low) hipLaunchKernelGGL((k_gemm_ring<32, 1>), dim3(gr), dim3(256), 0, s, g);
                      else hipLaunchKernelGGL((k_gemm_ring<32, 0>), dim3(gr), dim3(256), 0, s, g); break;
@@ -675,6 +782,22 @@ void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev
     if (ev_end) (void)hipEventRecord(ev_end, s);
 #undef SPAMM_GB
 #undef SPAMM_G
+}
+
+void launch_gemm_batch(int b, bool low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
+                       int32_t* counters, int num_cu, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(64), 0, s, descs_dev, nsys, out_off, pair_off);
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);
+    const int gr = ring_grid(b, num_cu);
+#define SPAMM_GBT(B_, L_)                                                                                       \
+    hipLaunchKernelGGL((k_gemm_ring_batch<B_, L_>), dim3(gr), dim3(256), 0, s, descs_dev, nsys, out_off, pair_off, \
+                       counters)
+    switch (b) {
+        case 32: if (low) SPAMM_GBT(32, 1); else SPAMM_GBT(32, 0); break;
+        case 64: if (low) SPAMM_GBT(64, 1); else SPAMM_GBT(64, 0); break;
+        case 128: SPAMM_GBT(128, 0); break;
+    }
+#undef SPAMM_GBT
 }
 
 // FP32 copies of the live blocks (round to nearest), for the low tier.

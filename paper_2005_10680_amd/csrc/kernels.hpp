@@ -107,6 +107,10 @@ struct GemmArgs {
 // ev_start/ev_end (optional) are recorded right around the product kernel.
 void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start = nullptr,
                      hipEvent_t ev_end = nullptr);
+// several products in one launch: descs_dev[nsys] on the device, out_off and
+// pair_off [nsys + 1] scratch, counters [16]
+void launch_gemm_batch(int b, bool low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
+                       int32_t* counters, int num_cu, hipStream_t s);
 void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
                    const int32_t* done, hipStream_t s);
 
