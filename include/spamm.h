@@ -300,6 +300,44 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                        const int64_t* max_pairs, sp2_iter_log* log, int32_t log_stride, int32_t* nlog_out,
                        int32_t* status_out, void* ws, size_t ws_bytes, spamm_stream_t stream);
 
+/*
+ * Re-blocking (not in the paper): Y = X on another leaf size (Y->b any of
+ * 32, 64, 128; Y->n == X->n).  A block of Y is present when a block of X it
+ * overlaps is present; values are copied (0 where X has no block or past
+ * n); slots of Y in 2D Morton order; norms of Y computed.  Y->cap must hold
+ * the blocks (SPAMM_ECAPACITY otherwise; nb_Y^2 always suffices).
+ * Workspace: spamm_reblock_workspace_bytes(Y->nb).  Synchronises.
+ */
+size_t spamm_reblock_workspace_bytes(int32_t nb_to);
+int spamm_reblock(const spamm_bsm* X, spamm_bsm* Y, void* ws, size_t ws_bytes, spamm_stream_t stream);
+
+/*
+ * Schedule of the leaf-product kernels: workgroups per CU of the persistent
+ * grid for leaf size b (0 restores the default: 4, 3, 2 for b = 32, 64,
+ * 128).  Process-wide; results do not depend on it (every output block is
+ * computed by one workgroup in the same order whatever the grid).
+ * spamm_get_gemm_schedule returns the current value.
+ */
+int spamm_set_gemm_schedule(int32_t b, int32_t workgroups_per_cu);
+int spamm_get_gemm_schedule(int32_t b);
+
+/*
+ * Leaf-size and schedule autotuner (not in the paper).  For each leaf size
+ * (32, 64, 128; 32 and 64 with the FP32 tier) F is re-blocked and the first
+ * trial_steps steps of its purification with parameters p are timed (the
+ * delta schedule is the one of the full run); the mean time of the steps
+ * after the first decides the leaf size.  Then every workgroups-per-CU
+ * setting up to the default is timed on the leaf products of the chosen
+ * size, and the fastest is installed (spamm_set_gemm_schedule).
+ *   best_b, best_per_cu : outputs; ms_per_step: host [3] mean step times for
+ *   b = 32, 64, 128 (-1 where not tried).
+ * Workspace: purify_sp2_autotune_workspace_bytes(F->n, p->N, p->precision).
+ * Synchronises.
+ */
+size_t purify_sp2_autotune_workspace_bytes(int64_t n, int32_t N, int32_t precision);
+int purify_sp2_autotune(const spamm_bsm* F, const sp2_params* p, int32_t trial_steps, int32_t* best_b,
+                        int32_t* best_per_cu, float* ms_per_step, void* ws, size_t ws_bytes, spamm_stream_t stream);
+
 const char* spamm_status_str(int code);
 const char* spamm_last_error(void);
 int spamm_version(void);

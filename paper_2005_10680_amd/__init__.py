@@ -113,6 +113,14 @@ def lib() -> ctypes.CDLL:
     L.purify_sp2_batched_workspace_bytes.restype = sz
     L.purify_sp2_batched.argtypes = [i32, B, ctypes.POINTER(sp2_params), B, P, ctypes.POINTER(sp2_iter_log), i32,
                                      P, P, P, sz, P]
+    L.spamm_reblock_workspace_bytes.argtypes = [i32]
+    L.spamm_reblock_workspace_bytes.restype = sz
+    L.spamm_reblock.argtypes = [B, B, P, sz, P]
+    L.spamm_set_gemm_schedule.argtypes = [i32, i32]
+    L.spamm_get_gemm_schedule.argtypes = [i32]
+    L.purify_sp2_autotune_workspace_bytes.argtypes = [i64, i32, i32]
+    L.purify_sp2_autotune_workspace_bytes.restype = sz
+    L.purify_sp2_autotune.argtypes = [B, ctypes.POINTER(sp2_params), i32, P, P, P, P, sz, P]
     L.spamm_status_str.argtypes = [ctypes.c_int]
     L.spamm_status_str.restype = ctypes.c_char_p
     L.spamm_last_error.restype = ctypes.c_char_p
@@ -472,6 +480,43 @@ def purify_batched(Fs, n_occ, eps, taus, homo, lumo, variant="hybrid", n_max=60,
     out = [[{k: getattr(logs[q * stride + i], k) for k, _ in sp2_iter_log._fields_} for i in range(nlog[q])]
            for q in range(ns)]
     return BatchResult(Ds, out, [int(x) for x in st], int(rc))
+
+
+def reblock(X: BlockSparse, b: int, cap=None) -> BlockSparse:
+    """The same matrix on leaf size b (spamm_reblock), norms included."""
+    nb = (X.n + b - 1) // b
+    Y = BlockSparse(X.n, b, int(cap) if cap is not None else nb * nb, X.device)
+    ws = _ws(lib().spamm_reblock_workspace_bytes(nb), X.device)
+    _check(lib().spamm_reblock(ctypes.byref(X.struct()), ctypes.byref(Y.struct()), _ptr(ws), ws.numel(), _stream()))
+    return Y
+
+
+def set_gemm_schedule(b: int, workgroups_per_cu: int) -> None:
+    _check(lib().spamm_set_gemm_schedule(int(b), int(workgroups_per_cu)))
+
+
+def get_gemm_schedule(b: int) -> int:
+    return _check(lib().spamm_get_gemm_schedule(int(b)))
+
+
+def autotune(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo=float("nan"), variant="hybrid",
+             n_max=60, delta_const=float("nan"), precision="fp64", tier_split=0.5, trial_steps=6):
+    """Leaf size and product schedule for this input (purify_sp2_autotune):
+    returns (best leaf size, workgroups per CU, {leaf: mean ms per step}).
+    The schedule is installed process-wide."""
+    dev = F.device
+    taus = torch.as_tensor(taus, dtype=torch.float64, device=dev).contiguous()
+    prec = {"fp64": 0, "fp32": 1}[precision]
+    p = sp2_params(int(n_occ), float(eps), int(n_max), VARIANTS[variant], taus.data_ptr(), int(taus.shape[0]),
+                   float(homo), float(lumo), float(delta_const), 0.0, 0, prec, float(tier_split), 0, 0)
+    ws = _ws(lib().purify_sp2_autotune_workspace_bytes(F.n, int(taus.shape[0]), prec), dev)
+    bb = ctypes.c_int32(0)
+    pc = ctypes.c_int32(0)
+    ms = (ctypes.c_float * 3)()
+    _check(lib().purify_sp2_autotune(ctypes.byref(F.struct()), ctypes.byref(p), int(trial_steps), ctypes.byref(bb),
+                                     ctypes.byref(pc), ms, _ptr(ws), ws.numel(), _stream()))
+    del ws
+    return int(bb.value), int(pc.value), {b: float(ms[q]) for q, b in enumerate((32, 64, 128)) if ms[q] >= 0}
 
 
 def adjoint_step(X: BlockSparse, G: BlockSparse, tau: float, branch: int, max_pairs=None):

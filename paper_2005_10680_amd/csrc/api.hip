@@ -688,8 +688,10 @@ int purify_sp2_tape_view(void* ws, int32_t nb, int32_t b, int32_t N, int64_t cap
     return SPAMM_OK;
 }
 
-int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out, void* ws,
-               size_t ws_bytes, spamm_stream_t stream) {
+// purify_sp2 with an extra limit: the host loop stops after max_steps
+// steps (status SPAMM_WNOCONV) while delta_i still follows p->n_max
+static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out,
+                      void* ws, size_t ws_bytes, spamm_stream_t stream, int max_steps) {
     if (!log || !nlog_out) return fail(SPAMM_EINVAL, "NULL argument");
     int rc = check_sp2(F, p, D);
     if (rc) return rc;
@@ -943,7 +945,7 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
             L.e = e;
             L.branch = -1;
             const bool stop = should_stop(e_hist, p->e_tol);
-            if (stop || it > p->n_max || Xn == nullptr) {
+            if (stop || it > p->n_max || Xn == nullptr || it > max_steps) {
                 L.stop = stop ? 1 : 2;
                 if (!stop) status = SPAMM_WNOCONV;
                 break;
@@ -985,6 +987,11 @@ int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_l
     }
     *nlog_out = nlog;
     return status;
+}
+
+int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out, void* ws,
+               size_t ws_bytes, spamm_stream_t stream) {
+    return purify_run(F, p, D, log, nlog_out, ws, ws_bytes, stream, 1 << 30);
 }
 
 size_t spamm_adjoint_step_workspace_bytes(int32_t nb, int64_t cap_blocks, int64_t max_pairs) {
@@ -1395,6 +1402,190 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
     HIP_TRY(hipStreamSynchronize(s));
     if (worst < 0) return fail(worst, "a system of the batch failed (see status_out)");
     return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Re-blocking, product schedule, leaf-size autotuner
+// ---------------------------------------------------------------------------
+static int reblock_grid_p(int nb) {
+    int P = 1;
+    while (P < nb) P <<= 1;
+    return P;
+}
+
+size_t spamm_reblock_workspace_bytes(int32_t nb_to) {
+    if (nb_to < 1) return 0;
+    const int64_t PP = (int64_t)reblock_grid_p(nb_to) * reblock_grid_p(nb_to);
+    Carver c(nullptr);
+    c.take<int32_t>(PP);
+    c.take<int32_t>(PP);
+    c.take<int64_t>(2);
+    c.take<int32_t>(2);
+    c.take<char>(scan_temp_bytes(PP));
+    return c.off + 256;
+}
+
+int spamm_reblock(const spamm_bsm* X, spamm_bsm* Y, void* ws, size_t ws_bytes, spamm_stream_t stream) {
+    int rc = check_bsm(X, "X", false);
+    if (!rc) rc = check_bsm(Y, "Y", true);
+    if (rc) return rc;
+    if (X->n != Y->n) return fail(SPAMM_EINVAL, "X and Y must have the same n");
+    const size_t need = spamm_reblock_workspace_bytes(Y->nb);
+    if (!ws || ws_bytes < need) return fail(SPAMM_EWORKSPACE, "reblock needs %zu workspace bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t PP = (int64_t)reblock_grid_p(Y->nb) * reblock_grid_p(Y->nb);
+    Carver c(ws);
+    int32_t* flag = c.take<int32_t>(PP);
+    int32_t* pos = c.take<int32_t>(PP);
+    int64_t* total = c.take<int64_t>(2);
+    int32_t* ovf = c.take<int32_t>(2);
+    void* tmp = c.take<char>(scan_temp_bytes(PP));
+    fill_i32(ovf, 1, 0, s);
+    launch_reblock(view(X), view(Y), flag, pos, total, tmp, ovf, s);
+    launch_norms(Y->b, Y->nslot, Y->cap, Y->brow, Y->val, Y->sq, Y->sqlo, Y->norm, s);
+    int32_t o = 0;
+    int64_t t = 0;
+    HIP_TRY(hipMemcpyAsync(&o, ovf, sizeof(o), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&t, total, sizeof(t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipGetLastError());
+    if (o) return fail(SPAMM_ECAPACITY, "Y needs %lld slots, has %lld", (long long)t, (long long)Y->cap);
+    return SPAMM_OK;
+}
+
+int spamm_set_gemm_schedule(int32_t b, int32_t workgroups_per_cu) {
+    if (b != 32 && b != 64 && b != 128) return fail(SPAMM_EINVAL, "leaf size must be 32, 64 or 128");
+    if (workgroups_per_cu == 0) workgroups_per_cu = b == 32 ? 4 : (b == 64 ? 3 : 2);
+    if (workgroups_per_cu < 1 || workgroups_per_cu > 8) return fail(SPAMM_EINVAL, "workgroups per CU in 1..8");
+    set_ring_per_cu(b, workgroups_per_cu);
+    return SPAMM_OK;
+}
+
+int spamm_get_gemm_schedule(int32_t b) {
+    if (b != 32 && b != 64 && b != 128) return fail(SPAMM_EINVAL, "leaf size must be 32, 64 or 128");
+    return get_ring_per_cu(b);
+}
+
+}  // extern "C"
+
+namespace {
+
+// sizes of one autotuner trial at leaf b
+struct TrialSize {
+    int nb;
+    int64_t cap, max_pairs;
+    size_t bytes;
+};
+
+TrialSize trial_size(int64_t n, int b, int N, int precision) {
+    TrialSize t;
+    t.nb = (int)((n + b - 1) / b);
+    t.cap = (int64_t)t.nb * t.nb;
+    t.max_pairs = t.cap * (t.nb + 1) / 2;
+    Carver c(nullptr);
+    spamm_bsm m;
+    carve_mat(c, n, b, t.cap, m);  // F at leaf b
+    carve_mat(c, n, b, t.cap, m);  // D at leaf b
+    c.take<char>(spamm_reblock_workspace_bytes(t.nb));
+    c.take<char>(purify_sp2_workspace_bytes(t.nb, b, N, t.cap, 0, 0, precision) + 8 * (size_t)t.max_pairs + 1024);
+    t.bytes = c.off + 256;
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t purify_sp2_autotune_workspace_bytes(int64_t n, int32_t N, int32_t precision) {
+    if (n < 1 || N < 1) return 0;
+    size_t m = 0;
+    for (int b : {32, 64, 128}) {
+        if (precision == 1 && b > 64) continue;
+        m = std::max(m, trial_size(n, b, N, precision).bytes);
+    }
+    return m;
+}
+
+int purify_sp2_autotune(const spamm_bsm* F, const sp2_params* p, int32_t trial_steps, int32_t* best_b,
+                        int32_t* best_per_cu, float* ms_per_step, void* ws, size_t ws_bytes, spamm_stream_t stream) {
+    int rc = check_bsm(F, "F", false);
+    if (rc) return rc;
+    if (!p || !best_b || !best_per_cu || !ms_per_step) return fail(SPAMM_EINVAL, "NULL argument");
+    if (trial_steps < 2 || trial_steps > 1000) return fail(SPAMM_EINVAL, "trial_steps must be in 2..1000");
+    const size_t need = purify_sp2_autotune_workspace_bytes(F->n, p->N, p->precision);
+    if (!ws || ws_bytes < need) return fail(SPAMM_EWORKSPACE, "autotune needs %zu workspace bytes", need);
+    hipStream_t s = (hipStream_t)stream;
+    sp2_params pt = *p;
+    pt.keep_tape = 0;
+    pt.graph_steps = 0;
+    std::vector<sp2_iter_log> logs(trial_steps + 2);
+    // mean time of the trial steps after the first, and of their products
+    auto trial = [&](int b, float* ms_step, float* ms_gemm) -> int {
+        const TrialSize t = trial_size(F->n, b, p->N, p->precision);
+        Carver c(ws);
+        spamm_bsm Fb, Db;
+        carve_mat(c, F->n, b, t.cap, Fb);
+        carve_mat(c, F->n, b, t.cap, Db);
+        const size_t rb = spamm_reblock_workspace_bytes(t.nb);
+        void* rws = c.take<char>(rb);
+        int r = spamm_reblock(F, &Fb, rws, rb, stream);
+        if (r) return r;
+        const size_t pb = purify_sp2_workspace_bytes(t.nb, b, p->N, t.cap, 0, 0, p->precision) +
+                          8 * (size_t)t.max_pairs + 1024;
+        void* pws = c.take<char>(pb);
+        int32_t nl = 0;
+        r = purify_run(&Fb, &pt, &Db, logs.data(), &nl, pws, pb, stream, trial_steps);
+        if (r < 0) return r;
+        double tot = 0.0, gem = 0.0;
+        int cnt = 0;
+        for (int k = 1; k < nl; ++k) {
+            if (logs[k].branch < 0) continue;
+            tot += logs[k].ms_total;
+            gem += logs[k].ms_gemm;
+            ++cnt;
+        }
+        *ms_step = cnt ? (float)(tot / cnt) : -1.0f;
+        *ms_gemm = cnt ? (float)(gem / cnt) : -1.0f;
+        return SPAMM_OK;
+    };
+    int bb = 0;
+    float best = 0.0f;
+    const int leaves[3] = {32, 64, 128};
+    for (int q = 0; q < 3; ++q) {
+        ms_per_step[q] = -1.0f;
+        if (p->precision == 1 && leaves[q] > 64) continue;
+        float st = 0.0f, gm = 0.0f;
+        rc = trial(leaves[q], &st, &gm);
+        if (rc) return rc;
+        ms_per_step[q] = st;
+        if (st > 0.0f && (bb == 0 || st < best)) {
+            bb = leaves[q];
+            best = st;
+        }
+    }
+    if (bb == 0) return fail(SPAMM_EINVAL, "the trials took no step (the input converged at once)");
+    // schedule of the chosen leaf: workgroups per CU of the product kernel
+    const int def = get_ring_per_cu(bb);
+    int best_pc = def;
+    float best_g = 0.0f;
+    for (int pc = 1; pc <= def; ++pc) {
+        set_ring_per_cu(bb, pc);
+        float st = 0.0f, gm = 0.0f;
+        rc = trial(bb, &st, &gm);
+        if (rc) {
+            set_ring_per_cu(bb, def);
+            return rc;
+        }
+        if (gm > 0.0f && (best_g == 0.0f || gm < best_g)) {
+            best_g = gm;
+            best_pc = pc;
+        }
+    }
+    set_ring_per_cu(bb, best_pc);
+    *best_b = bb;
+    *best_per_cu = best_pc;
+    (void)s;
+    return SPAMM_OK;
 }
 
 }  // extern "C"

@@ -413,10 +413,19 @@ struct RingSlot {
     }
 };
 
-// persistent grid of the ring kernels: workgroups per CU by leaf size, a
-// multiple of 8 so every XCD gets the same count
+// Schedule of the ring kernels: workgroups per CU of the persistent grid, by
+// leaf size (32, 64, 128).  Defaults: as many as the register and LDS
+// budgets keep resident; settable (the autotuner measures the choices).
+static int g_ring_per_cu[3] = {4, 3, 2};
+
+static int leaf_index(int b) { return b == 32 ? 0 : (b == 64 ? 1 : 2); }
+
+int get_ring_per_cu(int b) { return g_ring_per_cu[leaf_index(b)]; }
+void set_ring_per_cu(int b, int per_cu) { g_ring_per_cu[leaf_index(b)] = per_cu; }
+
+// persistent grid: a multiple of 8 so every XCD gets the same count
 inline int ring_grid(int b, int num_cu) {
-    const int per_cu = b == 64 ? 3 : (b == 32 ? 4 : 2);
+    const int per_cu = get_ring_per_cu(b);
     return (num_cu * per_cu + 7) / 8 * 8;
 }
 

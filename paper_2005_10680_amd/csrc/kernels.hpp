@@ -107,6 +107,9 @@ struct GemmArgs {
 // ev_start/ev_end (optional) are recorded right around the product kernel.
 void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start = nullptr,
                      hipEvent_t ev_end = nullptr);
+// workgroups per CU of the ring kernels' persistent grid, by leaf size
+int get_ring_per_cu(int b);
+void set_ring_per_cu(int b, int per_cu);
 // several products in one launch: descs_dev[nsys] on the device, out_off and
 // pair_off [nsys + 1] scratch, counters [16]
 void launch_gemm_batch(int b, bool low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
@@ -129,6 +132,11 @@ void launch_adj_fbar(const MatView& F, const int32_t* map0, const double* g0, co
 void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
                         const int32_t* ovf_sweep, const int32_t* nslot_cur, ::sp2_iter_log* logs, int max_records,
                         hipStream_t s);
+
+// reblock.hip: Y (leaf Y.b, same n) from X; flag/pos [P^2] with P the power
+// of two >= Y.nb, total: device int64, ovf: set when Y.cap is too small
+void launch_reblock(const MatView& X, const MatView& Y, int32_t* flag, int32_t* pos, int64_t* total, void* scan_tmp,
+                    int32_t* ovf, hipStream_t s);
 
 // trunc.hip
 size_t trunc_temp_bytes(int64_t cap);
