@@ -54,6 +54,9 @@ def main():
     ap.add_argument("--graph", type=int, default=8,
                     help="also time the graph-captured loop, polling every K iterations (0: skip)")
     ap.add_argument("--adjoint", action="store_true", help="also time the reverse mode (tape + adjoint)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="also time the batched workload: the first N of the 64 systems (sizes log-uniform in "
+                         "[2048, 32768], seed 4), leaf sizes by the autotuner")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -62,9 +65,13 @@ def main():
               "the multi-GPU sharding is a design, not a measured path.", file=sys.stderr)
         sys.exit(2)
 
+    import synth
+    batch_mats = None
+    if args.batch > 0:
+        # host-side generation first, before this process touches the GPU
+        batch_mats = generate_batch(args.batch, synth)
     import torch
     import paper_2005_10680_amd as P
-    import synth
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -237,6 +244,9 @@ def main():
         log(f"plain copy of {args.copy_mb} MiB done")
         del src, dst
 
+    if args.batch > 0:
+        out["batched"] = batch_leg(args, dev, P, synth, batch_mats)
+
     if not args.no_cpu:
         log("timing the oracle on a sample (cpu baseline)")
         out["cpu_baseline"] = cpu_baseline(res, Fh, taus, b, args.cpu_seconds)
@@ -277,6 +287,98 @@ def measured_traffic(n, b, seed):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def _gen_leaf32(arg):
+    n, seed = arg
+    import synth
+    return synth.sys3d(n, seed, 32)
+
+
+def generate_batch(count, synth):
+    """The first `count` systems of the batched workload at leaf 32 (process
+    pool; called before any GPU use)."""
+    from concurrent.futures import ProcessPoolExecutor
+    sizes = synth.batch_sizes(4, 64)[:count]
+    t0 = time.perf_counter()
+    workers = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 8))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        mats = list(ex.map(_gen_leaf32, sizes))
+    log(f"batch: generated {len(mats)} systems (sum n = {sum(n for n, _ in sizes)}) in {time.perf_counter() - t0:.1f} s")
+    return mats
+
+
+def batch_leg(args, dev, P, synth, mats):
+    """The batched workload: independent 3D systems (sizes log-uniform in
+    [2048, 32768], generator seed 4, system seeds 4000 + s), generated at
+    leaf 32, each re-blocked to the leaf size the autotuner picks for it,
+    then purified together (one product launch per leaf size and tier per
+    step, graph-captured loop) and, for comparison, one after another.
+    Without dense spectra at these sizes the per-step delta is a constant
+    (1e-9, the range the gap-based schedule gives for the n = 16384 system)."""
+    import torch
+    taus = synth.tau_log(32)
+    eps, dconst = 1e-6, 1e-9
+    saved = {b: P.get_gemm_schedule(b) for b in (32, 64, 128)}
+    Fs, leaves = [], []
+    t0 = time.perf_counter()
+    for m in mats:
+        F32 = P.BlockSparse.from_host(m)
+        b, _, _ = P.autotune(F32, m.n // 2, eps, taus, delta_const=dconst, trial_steps=6)
+        for bb, v in saved.items():
+            P.set_gemm_schedule(bb, v)
+        Fs.append(F32 if b == 32 else P.reblock(F32, b))
+        leaves.append(b)
+        del F32
+        torch.cuda.empty_cache()
+    log(f"batch: autotuned leaf sizes {dict((b, leaves.count(b)) for b in sorted(set(leaves)))} "
+        f"in {time.perf_counter() - t0:.1f} s")
+    del mats
+    res_all = {}
+    caps_used = None
+    for prec in ("fp64", "fp32"):
+        if prec == "fp32" and any(b > 64 for b in leaves):
+            continue
+        # one after another (graph loop each, capacity nb^2): the comparison,
+        # and the peak block count of every system (runs are deterministic,
+        # so the batched run needs exactly these capacities)
+        peaks = []
+        for F in Fs:
+            r1 = P.purify(F, F.n // 2, eps, taus, delta_const=dconst, precision=prec, graph_steps=8)
+            nf = int(F.live()[0].shape[0])
+            peaks.append(max([nf + F.nb] + [int(l["nslot_hat"]) for l in r1.logs]))
+            del r1
+        torch.cuda.empty_cache()
+        caps = [min(F.nb * F.nb, pk) for F, pk in zip(Fs, peaks)]
+        caps_used = caps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for F, cp in zip(Fs, caps):
+            P.purify(F, F.n // 2, eps, taus, delta_const=dconst, precision=prec, cap=cp, graph_steps=8)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        torch.cuda.empty_cache()
+        kw = dict(delta_const=dconst, precision=prec, caps=caps, graph_steps=8, raise_on_error=False)
+        r = P.purify_batched(Fs, [F.n // 2 for F in Fs], eps, taus, float("nan"), float("nan"), **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = P.purify_batched(Fs, [F.n // 2 for F in Fs], eps, taus, float("nan"), float("nan"), **kw)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        ok = sum(1 for st in r.status if st >= 0)
+        flops = sum(sum(l["npairs"] for l in lg if l["branch"] >= 0) * 2.0 * F.b ** 3 for lg, F in zip(r.logs, Fs))
+        iters = [sum(1 for l in lg if l["branch"] >= 0) for lg in r.logs]
+        del r
+        torch.cuda.empty_cache()
+        log(f"batch {prec}: {tb:.3f} s together, {ts:.3f} s one by one, {ok}/{len(Fs)} systems ok")
+        res_all[prec] = {"time_s": round(tb, 4), "kept_TFLOP_per_s": round(flops / tb / 1e12, 4),
+                         "sequential_time_s": round(ts, 4), "speedup_vs_sequential": round(ts / tb, 4),
+                         "systems_ok": ok, "iterations_min_max": [min(iters), max(iters)]}
+    dense = sum(F.nb * F.nb for F in Fs)
+    return {"systems": len(Fs), "sum_n": int(sum(F.n for F in Fs)),
+            "leaf_counts": {str(b): leaves.count(b) for b in sorted(set(leaves))},
+            "capacity_fraction_of_dense": round(sum(caps_used) / dense, 4) if caps_used else None,
+            "delta_const": dconst, **res_all}
 
 
 def cpu_baseline(res, Fh, taus, b, seconds):
