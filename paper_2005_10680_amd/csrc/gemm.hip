@@ -401,6 +401,64 @@ SPAMM_DEV int2 const_ld(const int2* p, int idx) {
     return make_int2((int32_t)(v & 0xffffffff), (int32_t)(v >> 32));
 }
 
+// 32-bit LDS address of a pointer into LDS
+SPAMM_DEV uint32_t lds_addr(const char* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char*)p;
+}
+
+// The FP64 operand reads of one k-step: T doubles of A at a, a + 128, ...
+// and T of B at b, b + 128, ... (byte addresses in LDS), waited for inside
+// the same block.  Written out so that the compiler's memory model does not
+// see LDS reads here: it cannot tell which ring slot the copies in flight
+// fill once they cross the stage loop's back edge, and would drain every
+// copy before the first read of each loop iteration.  The stage's own
+// vmcnt wait and barrier order these reads after the copies of their slot,
+// and the barrier of the next stage orders them before the slot's refill.
+template <int T>
+SPAMM_DEV void lds_read_tiles(uint32_t a, uint32_t b, double* av, double* bv);
+
+template <>
+SPAMM_DEV void lds_read_tiles<1>(uint32_t a, uint32_t b, double* av, double* bv) {
+    double x, y;
+    asm volatile("ds_read_b64 %0, %2\n\tds_read_b64 %1, %3\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(x), "=&v"(y)
+                 : "v"(a), "v"(b));
+    av[0] = x;
+    bv[0] = y;
+}
+
+template <>
+SPAMM_DEV void lds_read_tiles<2>(uint32_t a, uint32_t b, double* av, double* bv) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 x, y;
+    asm volatile("ds_read2_b64 %0, %2 offset1:16\n\tds_read2_b64 %1, %3 offset1:16\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&v"(x), "=&v"(y)
+                 : "v"(a), "v"(b));
+    av[0] = x[0];
+    av[1] = x[1];
+    bv[0] = y[0];
+    bv[1] = y[1];
+}
+
+template <>
+SPAMM_DEV void lds_read_tiles<4>(uint32_t a, uint32_t b, double* av, double* bv) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 x0, x1, y0, y1;
+    asm volatile(
+        "ds_read2_b64 %0, %4 offset1:16\n\tds_read2_b64 %1, %4 offset0:32 offset1:48\n\t"
+        "ds_read2_b64 %2, %5 offset1:16\n\tds_read2_b64 %3, %5 offset0:32 offset1:48\n\ts_waitcnt lgkmcnt(0)"
+        : "=&v"(x0), "=&v"(x1), "=&v"(y0), "=&v"(y1)
+        : "v"(a), "v"(b));
+    av[0] = x0[0];
+    av[1] = x0[1];
+    av[2] = x1[0];
+    av[3] = x1[1];
+    bv[0] = y0[0];
+    bv[1] = y0[1];
+    bv[2] = y1[0];
+    bv[3] = y1[1];
+}
+
 // One LDS object per ring slot, and the stage loop unrolled by NS so every
 // access names its slot statically: the compiler can then see that the
 // copies in flight (other slots) never alias the slot being read, and only
@@ -522,16 +580,14 @@ struct RingCtx {
                     }
             }
         } else {
-            const double* As = reinterpret_cast<const double*>(sl);
-            const double* Bs = reinterpret_cast<const double*>(sl + R::OPB);
+            // LDS byte addresses of this lane's first A and B element
+            const uint32_t lbase = lds_addr(sl);
+            const uint32_t a0 = lbase + 8u * (uint32_t)((lane >> 4) * B + wm * R::TM * 16 + (lane & 15));
+            const uint32_t b0 = lbase + R::OPB + 8u * (uint32_t)((lane >> 4) * B + wn * R::TN * 16 + (lane & 15));
 #pragma unroll
             for (int ks = 0; ks < R::KC64 / 4; ++ks) {
-                const int kr = ks * 4 + (lane >> 4);
                 double av[R::TM], bv[R::TN];
-#pragma unroll
-                for (int a = 0; a < R::TM; ++a) av[a] = As[kr * B + wm * R::TM * 16 + a * 16 + (lane & 15)];
-#pragma unroll
-                for (int b = 0; b < R::TN; ++b) bv[b] = Bs[kr * B + wn * R::TN * 16 + b * 16 + (lane & 15)];
+                lds_read_tiles<R::TM>(a0 + (uint32_t)(ks * 4 * B * 8), b0 + (uint32_t)(ks * 4 * B * 8), av, bv);
 #pragma unroll
                 for (int a = 0; a < R::TM; ++a)
 #pragma unroll
