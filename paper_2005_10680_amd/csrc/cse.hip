@@ -74,12 +74,13 @@ void launch_cube_list(int T, const int32_t* flag, const int32_t* idx, uint32_t* 
                        ovf, done);
 }
 
-// Error of the subtree rooted at level LEV, node (i0, k0, j0) inside the cube.
+// Error of the subtree rooted at level LEV, node (i0, k0, j0) inside the
+// cube; P holds the cube's leaf products p = RN(nu(A_ik) nu(B_kj)) at
+// (i * S + k) * S + j.
 template <int LEV, int S, int MODE>
-SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double cl, const double (*nA)[S],
-                           const double (*nB)[S]) {
+SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double cl, const double* P) {
     if constexpr (LEV == 0) {
-        double p = nA[i0][k0] * nB[k0][j0];
+        const double p = P[(i0 * S + k0) * S + j0];
         if constexpr (MODE == 0) {
             return p < tm ? p : 0.0;
         } else {
@@ -94,8 +95,8 @@ SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double 
         for (int a = 0; a < 2; ++a)
 #pragma unroll(LEV == 1 ? 2 : 1)
             for (int c = 0; c < 2; ++c) {
-                double e1 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0, 2 * j0 + c, tm, t0, cl, nA, nB);
-                double e2 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0 + 1, 2 * j0 + c, tm, t0, cl, nA, nB);
+                double e1 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0, 2 * j0 + c, tm, t0, cl, P);
+                double e2 = cube_node<LEV - 1, S, MODE>(2 * i0 + a, 2 * k0 + 1, 2 * j0 + c, tm, t0, cl, P);
                 double t = e1 + e2;
                 double t2 = t * t;
                 acc = acc + t2;
@@ -104,45 +105,68 @@ SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double 
     }
 }
 
+// LDS for the leaf products of the cubes of one workgroup (doubles)
+constexpr int kCubeLds = 4096;
+
+// Workgroups of 256 threads take `cpw` cubes at a time, `lpc` threads per
+// cube (candidates m = lane, lane + lpc, ...): the leaf norms of the cubes
+// go to LDS, then their S^3 leaf products (computed once, shared by every
+// candidate), then each thread evaluates Algorithm 3 over its cube for its
+// candidates.
 template <int L0, int MODE>
 __global__ __launch_bounds__(256) void k_cube_eval(int nb, const uint32_t* __restrict__ keys,
                                                   const int64_t* __restrict__ ncubes_p, int64_t cap,
                                                   const int32_t* __restrict__ mapA, const double* __restrict__ normA,
                                                   const int32_t* __restrict__ mapB, const double* __restrict__ normB,
                                                   int btrans, const double* __restrict__ tau, int N,
-                                                  const double* __restrict__ tau0_p, double c_low,
+                                                  const double* __restrict__ tau0_p, double c_low, int cpw, int lpc,
                                                   double* __restrict__ vals, const int32_t* __restrict__ done) {
     constexpr int S = 1 << L0;
-    __shared__ double nA[S][S];
-    __shared__ double nB[S][S];
+    constexpr int S2 = S * S, S3 = S * S * S;
+    __shared__ double nA[kCubeLds / 4];
+    __shared__ double nB[kCubeLds / 4];
+    __shared__ double P[kCubeLds];
     if (done && *done) return;
     int64_t ncubes = *ncubes_p;
     if (ncubes > cap) ncubes = cap;
     const double t0 = (MODE == 1 && tau0_p) ? *tau0_p : 0.0;
-    for (int64_t cube = blockIdx.x; cube < ncubes; cube += gridDim.x) {
-        uint32_t I, K, J;
-        demorton3(keys[cube], I, K, J);
+    const int tid = threadIdx.x;
+    for (int64_t g = blockIdx.x; g * cpw < ncubes; g += gridDim.x) {
+        const int64_t c0 = g * cpw;
         __syncthreads();
-        for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
-            int a = t / S, q = t % S;
-            int i = (int)I * S + a, k = (int)K * S + q;  // A_ik
-            double va = 0.0;
-            if (i < nb && k < nb) {
-                int sa = mapA[(size_t)i * nb + k];
-                if (sa >= 0) va = normA[sa];
+        for (int t = tid; t < cpw * S2; t += 256) {
+            const int c = t / S2, r = t % S2;
+            const int a = r / S, q = r % S;
+            double va = 0.0, vb = 0.0;
+            if (c0 + c < ncubes) {
+                uint32_t I, K, J;
+                demorton3(keys[c0 + c], I, K, J);
+                const int i = (int)I * S + a, k = (int)K * S + q;  // A_ik
+                if (i < nb && k < nb) {
+                    const int sa = mapA[(size_t)i * nb + k];
+                    if (sa >= 0) va = normA[sa];
+                }
+                const int kk = (int)K * S + a, j = (int)J * S + q;  // B_kj
+                if (kk < nb && j < nb) {
+                    const int sb = btrans ? mapB[(size_t)j * nb + kk] : mapB[(size_t)kk * nb + j];
+                    if (sb >= 0) vb = normB[sb];
+                }
             }
-            nA[a][q] = va;
-            int kk = (int)K * S + a, j = (int)J * S + q;  // B_kj
-            double vb = 0.0;
-            if (kk < nb && j < nb) {
-                int sb = btrans ? mapB[(size_t)j * nb + kk] : mapB[(size_t)kk * nb + j];
-                if (sb >= 0) vb = normB[sb];
-            }
-            nB[a][q] = vb;
+            nA[t] = va;
+            nB[t] = vb;
         }
         __syncthreads();
-        for (int m = threadIdx.x; m < N; m += blockDim.x)
-            vals[(size_t)cube * N + m] = cube_node<L0, S, MODE>(0, 0, 0, tau[m], t0, c_low, nA, nB);
+        for (int t = tid; t < cpw * S3; t += 256) {
+            const int c = t / S3, r = t % S3;
+            const int i = r / S2, k = (r / S) % S, j = r % S;
+            P[t] = nA[c * S2 + i * S + k] * nB[c * S2 + k * S + j];
+        }
+        __syncthreads();
+        const int c = tid / lpc;
+        if (c < cpw && c0 + c < ncubes) {
+            for (int m = tid % lpc; m < N; m += lpc)
+                vals[(size_t)(c0 + c) * N + m] = cube_node<L0, S, MODE>(0, 0, 0, tau[m], t0, c_low, P + c * S3);
+        }
     }
 }
 
@@ -150,11 +174,17 @@ void launch_cube_eval(int mode, int l0, int nb, const uint32_t* keys, const int6
                       const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB, int btrans,
                       const double* tau, int N, const double* tau0, double c_low, double* vals, const int32_t* done,
                       hipStream_t s) {
-    int grid = grid_for(cap, 1, 4096);
-    int threads = N >= 256 ? 256 : ((N + 63) / 64) * 64;
-#define SPAMM_CUBE(L0_, M_)                                                                                       \
-    hipLaunchKernelGGL((k_cube_eval<L0_, M_>), dim3(grid), dim3(threads), 0, s, nb, keys, ncubes, cap, mapA, normA, \
-                       mapB, normB, btrans, tau, N, tau0, c_low, vals, done)
+    // threads per cube: the candidate count rounded up to a power of two
+    // (at most 256), cubes per workgroup: what 256 threads and the LDS hold
+    int lpc = 1;
+    while (lpc < N && lpc < 256) lpc <<= 1;
+    const int s3 = 1 << (3 * l0);
+    int cpw = 256 / lpc;
+    while (cpw > 1 && cpw * s3 > kCubeLds) cpw >>= 1;
+    const int grid = grid_for((cap + cpw - 1) / cpw, 1, 4096);
+#define SPAMM_CUBE(L0_, M_)                                                                                      \
+    hipLaunchKernelGGL((k_cube_eval<L0_, M_>), dim3(grid), dim3(256), 0, s, nb, keys, ncubes, cap, mapA, normA, \
+                       mapB, normB, btrans, tau, N, tau0, c_low, cpw, lpc, vals, done)
     if (mode == 0) {
         switch (l0) {
             case 0: SPAMM_CUBE(0, 0); break;
