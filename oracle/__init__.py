@@ -414,19 +414,38 @@ def combine(X: BSM, C: BSM, branch: int) -> BSM:
 
 
 def tier_constant(precision: int, b: int) -> float:
-    """Per-pair rounding factor of the FP32 leaf-product tier (not in the
-    paper): inputs rounded to FP32 (unit roundoff u = 2^-24 each) and b-term
-    products accumulated in FP32 with an assumed unit roundoff of 2u give
-    |fl(AB) - AB| <= (2u + u^2 + gamma_b(2u) (1+u)^2) |A||B| entrywise,
-    gamma_m(x) = m x / (1 - m x), hence ||fl(AB) - AB||_F <= c ||A||_F ||B||_F
-    (Cauchy-Schwarz per entry).  Rounded up by a factor 1 + 2^-40."""
-    if precision != 1:
-        return 0.0
-    u = 2.0 ** -24
-    ue = 2.0 * u
+    """Per-pair rounding factor c of a low-precision leaf-product tier (not in
+    the paper): ||fl(AB) - AB||_F <= c ||A||_F ||B||_F for one b x b pair.
+
+    precision 1, FP32: operands rounded to FP32 (unit roundoff u = 2^-24
+    each), b products accumulated in FP32 with an assumed unit roundoff of
+    2u: |fl(AB) - AB| <= (2u + u^2 + gamma_b(2u) (1+u)^2) |A||B| entrywise,
+    gamma_m(x) = m x / (1 - m x), then Cauchy-Schwarz per entry.
+
+    precision 2, split BF16: each block scaled by a power of two (max entry
+    in [1, 2)), split x = hi + lo + e with hi = RN_bf16(x), lo = RN_bf16(x -
+    hi) (unit roundoff u = 2^-8): |lo| <= u (1+u) |x|, |e| <= u^2 (1+u) |x|;
+    the three products hi*hi + hi*lo + lo*hi are exact in FP32 and their 3b
+    terms are accumulated in FP32 (unit roundoff 2 * 2^-24 assumed).  The
+    dropped terms lo*lo, e*(hi + lo), (hi + lo)*e', e*e' give
+    kappa = u^2 ((1+u)^2 + 2 (1+u)^3 + u^2 (1+u)^2), the accumulation
+    gamma_3b(2^-23) (1 + 2u)(1+u)^2, and 2^-100 covers entries below the
+    BF16 normal range (relative to the scaled blocks, whose norms are >= 1).
+
+    Both rounded up by a factor 1 + 2^-40."""
     m = float(b)
-    gam = m * ue / (1.0 - m * ue)
-    return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 2.0 ** -40)
+    if precision == 1:
+        u = 2.0 ** -24
+        ue = 2.0 * u
+        gam = m * ue / (1.0 - m * ue)
+        return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 2.0 ** -40)
+    if precision == 2:
+        u = 2.0 ** -8
+        ue = 2.0 * 2.0 ** -24
+        kappa = u * u * ((1.0 + u) ** 2 + 2.0 * (1.0 + u) ** 3 + u * u * (1.0 + u) ** 2)
+        gam = 3.0 * m * ue / (1.0 - 3.0 * m * ue)
+        return (kappa + gam * (1.0 + 2.0 * u) * (1.0 + u) ** 2 + 2.0 ** -100) * (1.0 + 2.0 ** -40)
+    return 0.0
 
 
 @dataclass
@@ -440,7 +459,7 @@ class SP2Params:
     variant: str = "hybrid"       # "hybrid" (Alg. 5), "spamm" (Alg. 4), "truncmul" (Alg. 1)
     delta_const: float = float("nan")  # explicit per-step delta when no gap is given
     e_tol: float = 0.0
-    precision: int = 0            # 1: FP32 tier for tau <= p < sigma (rounding folded into the bound)
+    precision: int = 0            # 1: FP32 tier, 2: split-BF16 tier, for tau <= p < sigma (rounding folded into the bound)
     tier_split: float = 0.5       # share of the product budget given to skipping when tiered
 
 

@@ -331,3 +331,56 @@ def test_fp32_tier_constant_bounds_fp32_products(b):
         worst = max(worst, ratio)
         assert ratio <= c
     assert worst > 1e-9                             # the FP32 path really rounded
+
+
+def _rn_bf16(x):
+    """Round to the nearest BF16 value (8 significant bits, ties to even,
+    subnormal spacing 2^-133), exactly, in float64."""
+    x = np.asarray(x, dtype=np.float64)
+    _, e = np.frexp(x)                      # x = m 2^e, 0.5 <= |m| < 1
+    q = np.maximum(e - 8, -133).astype(np.float64)
+    return np.rint(np.ldexp(x, (-q).astype(np.int64))) * np.exp2(q)
+
+
+@pytest.mark.parametrize("b", [32, 64])
+def test_bf16x3_tier_constant_bounds_split_products(b):
+    """||2^(ea+eb) (hi_a hi_b + hi_a lo_b + lo_a hi_b) (FP32) - AB||_F <=
+    c_bf16 ||A||_F ||B||_F, with each block scaled by a power of two to a
+    maximum in [1, 2) and split hi = RN_bf16(x), lo = RN_bf16(x - hi)."""
+    rng = np.random.default_rng(100 + b)
+    c = oracle.tier_constant(2, b)
+    assert c > oracle.tier_constant(1, b) and c < 1e-4
+    worst = 0.0
+    for t in range(200):
+        A = rng.standard_normal((b, b)) * np.exp(rng.uniform(-20, 5))
+        B = rng.standard_normal((b, b)) * np.exp(rng.uniform(-20, 5))
+        if t % 3 == 0:
+            A = np.abs(A); B = np.abs(B)                        # no cancellation
+        if t % 5 == 0:                                          # entries far below the BF16 range
+            A[rng.random((b, b)) < 0.3] *= 1e-45
+        parts = []
+        for M in (A, B):
+            e = np.frexp(np.max(np.abs(M)))[1]
+            Ms = np.ldexp(M, 1 - e)                             # max in [1, 2)
+            hi = _rn_bf16(Ms)
+            lo = _rn_bf16(Ms - hi)
+            parts.append((hi.astype(np.float32), lo.astype(np.float32), e - 1))
+        (ah, al, ea), (bh, bl, eb) = parts
+        S = (ah @ bh) + (ah @ bl) + (al @ bh)                   # FP32 arithmetic
+        P = np.ldexp(S.astype(np.float64), ea + eb)
+        err = np.linalg.norm(P - A @ B)
+        ratio = err / (np.linalg.norm(A) * np.linalg.norm(B))
+        worst = max(worst, ratio)
+        assert ratio <= c
+    assert worst > 1e-7                                         # the split really rounded
+
+
+def test_bf16_rounding_helper():
+    # exact values, ties to even, subnormal spacing
+    assert _rn_bf16(1.0) == 1.0
+    assert _rn_bf16(1.0 + 2.0 ** -9) == 1.0                     # below half a spacing (2^-7)
+    assert _rn_bf16(1.0 + 2.0 ** -8) == 1.0                     # tie -> even (down)
+    assert _rn_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6     # tie -> even (up)
+    assert _rn_bf16(-(1.0 + 3 * 2.0 ** -8)) == -(1.0 + 2.0 ** -6)
+    assert _rn_bf16(3 * 2.0 ** -134) == 2.0 ** -132             # subnormal spacing 2^-133, tie to even
+    assert _rn_bf16(2.0 ** -140) == 0.0

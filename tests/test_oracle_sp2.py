@@ -106,16 +106,18 @@ def test_other_variants_step_conditions(variant):
     assert np.linalg.norm(X.to_dense() - Dref) < 1e-6
 
 
-def test_fp32_tier_selection_converges():
+@pytest.mark.parametrize("precision", [1, 2])
+def test_tier_selection_converges(precision):
     """The tiered selection (tau from half the budget, then the largest sigma
-    whose Algorithm 3 bound with folded c_32 p terms fits the budget) keeps
-    every step within delta/2 (the oracle's products are FP64, so this checks
-    the budget split) and converges."""
+    whose Algorithm 3 bound with folded c p terms fits the budget; c of the
+    FP32 or the split-BF16 tier) keeps every step within delta/2 (the
+    oracle's products are FP64, so this checks the budget split) and
+    converges."""
     n = 768
     F = oracle.BSM.of(synth.sys3d(n, 7, 32))
     Dref, w = eigh_density(F, n // 2)
     p = oracle.SP2Params(n_occ=n // 2, eps=1e-6, taus=synth.tau_log(32), homo=w[n // 2 - 1], lumo=w[n // 2],
-                         precision=1)
+                         precision=precision)
     D, logs, info = oracle.sp2(F, p)
     steps = [l for l in logs if l.branch >= 0]
     assert any(l.npairs_low > 0 for l in steps)
