@@ -53,6 +53,8 @@ extern "C" {
 #define SPAMM_SYMMETRIC 1u   /* A = B = X symmetric: outputs i <= j, C_ji = C_ij^T */
 #define SPAMM_B_TRANSPOSED 2u /* B is given as its transpose Bt (Bt_jk = B_kj^T) */
 #define SPAMM_SYNC 4u        /* synchronise the stream before returning */
+#define SPAMM_TIER_BF16 8u   /* spamm_multiply_tiered: low-tier pairs as split-BF16 products (needs
+                                SPAMM_B_TRANSPOSED); default: FP32 products */
 
 typedef void* spamm_stream_t; /* hipStream_t */
 
@@ -134,20 +136,27 @@ int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev
  * Workspace: spamm_truncate_workspace_bytes(cap).
  */
 /*
- * SpAMM product with an FP32 precision tier (mixed-precision leaf products;
- * not in the paper): kept pairs with tau <= p < sigma use FP32 copies of the
- * blocks on FP32 MFMA, each pair's FP32 product added into the FP64
- * accumulator, so ||fl(A_ik B_kj) - A_ik B_kj||_F <= c_32 p with
- * c_32 = 2u + u^2 + gamma_b(2u)(1+u)^2, u = 2^-24 (spamm_tier_constant).
- * Pairs with p >= sigma are FP64.  Leaf 32 or 64.  kept_out: device [3] =
- * {kept pairs, output blocks, low-tier pairs}; may be NULL.
+ * SpAMM product with a low-precision tier (mixed-precision leaf products;
+ * not in the paper): kept pairs with tau <= p < sigma run in low precision,
+ * each pair's product added into the FP64 accumulator, with
+ * ||fl(A_ik B_kj) - A_ik B_kj||_F <= c_t p (spamm_tier_constant):
+ *   FP32 tier (default): FP32 copies on the FP32 MFMA,
+ *     c_32 = 2u + u^2 + gamma_b(2u)(1+u)^2, u = 2^-24;
+ *   split-BF16 tier (SPAMM_TIER_BF16, needs SPAMM_B_TRANSPOSED): each block
+ *     scaled by a power of two and split x = hi + lo (BF16), the products
+ *     hi*hi + hi*lo + lo*hi on the BF16 MFMA with FP32 accumulation, rescaled
+ *     exactly; c_bf16 = kappa + gamma_3b(2^-23)(1 + 2u)(1+u)^2 + 2^-100,
+ *     kappa = u^2 ((1+u)^2 + 2(1+u)^3 + u^2 (1+u)^2), u = 2^-8.
+ * Both rounded up by 1 + 2^-40.  Pairs with p >= sigma are FP64.  Leaf 32 or
+ * 64.  kept_out: device [3] = {kept pairs, output blocks, low-tier pairs};
+ * may be NULL.
  * Workspace: spamm_multiply_tiered_workspace_bytes(nb, capA, capB, b, max_pairs).
  */
 size_t spamm_multiply_tiered_workspace_bytes(int32_t nb, int64_t capA, int64_t capB, int32_t b, int64_t max_pairs);
 int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev, const double* sigma_dev,
                           uint32_t flags, spamm_bsm* C, int64_t* kept_out, void* ws, size_t ws_bytes,
                           spamm_stream_t stream);
-/* c_t of a precision tier (1 = FP32) for leaf size b: the per-pair factor of
+/* c_t of a precision tier (1 = FP32, 2 = split BF16) for leaf size b: the per-pair factor of
  * the rounding bound ||fl(A B) - A B||_F <= c_t ||A||_F ||B||_F. */
 double spamm_tier_constant(int32_t precision, int32_t b);
 
@@ -167,7 +176,8 @@ typedef struct sp2_params {
     double delta_const;  /* explicit per-step delta when homo/lumo are NaN (else NaN) */
     double e_tol;        /* stop when |tr X - ||X||_F^2| <= e_tol (0: noise-floor rule only) */
     int32_t keep_tape;   /* nonzero: keep every X~_i in the workspace (adjoint, inspection) */
-    int32_t precision;   /* 0 FP64 leaf products; 1 FP32 tier for pairs with tau <= p < sigma (leaf 32/64) */
+    int32_t precision;   /* 0 FP64 leaf products; for pairs with tau <= p < sigma (leaf 32/64):
+                            1 FP32 tier, 2 split-BF16 tier (hi*hi + hi*lo + lo*hi on the BF16 MFMA) */
     double tier_split;   /* share of the product budget given to skipping when precision != 0 (e.g. 0.5) */
     int32_t graph_steps; /* 0: host-driven loop (per-iteration phase timings); K > 0: the step is
                             captured once as a HIP graph with its decisions taken on the device

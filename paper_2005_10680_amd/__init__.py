@@ -32,8 +32,10 @@ SPAMM_WTAUFALLBACK = 2
 SYMMETRIC = 1
 B_TRANSPOSED = 2
 SYNC = 4
+TIER_BF16 = 8
 
 VARIANTS = {"hybrid": 0, "spamm": 1, "truncmul": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 
 class SpammError(RuntimeError):
@@ -341,9 +343,9 @@ def multiply(A: BlockSparse, B: BlockSparse, tau, symmetric=False, b_transposed=
 
 
 def multiply_tiered(A: BlockSparse, B: BlockSparse, tau, sigma, symmetric=False, b_transposed=False, cap=None,
-                    max_pairs=None):
-    """SpAMM with an FP32 tier for pairs with tau <= p < sigma.  Returns
-    (C, kept[3] = pairs, outputs, low-tier pairs)."""
+                    max_pairs=None, tier="fp32"):
+    """SpAMM with a low-precision tier ("fp32" or "bf16x3") for pairs with
+    tau <= p < sigma.  Returns (C, kept[3] = pairs, outputs, low-tier pairs)."""
     dev = A.device
     nb = A.nb
     if cap is None:
@@ -356,7 +358,8 @@ def multiply_tiered(A: BlockSparse, B: BlockSparse, tau, sigma, symmetric=False,
     kept = torch.zeros(3, dtype=torch.int64, device=dev)
     base = lib().spamm_multiply_tiered_workspace_bytes(nb, A.cap, B.cap, A.b, 0)
     ws = _ws(base + 8 * int(max_pairs) + 1024, dev)
-    flags = (SYMMETRIC if symmetric else 0) | (B_TRANSPOSED if b_transposed else 0)
+    flags = (SYMMETRIC if symmetric else 0) | (B_TRANSPOSED if b_transposed else 0) | \
+        ({"fp32": 0, "bf16x3": TIER_BF16}[tier])
     _check(lib().spamm_multiply_tiered(ctypes.byref(A.struct()), ctypes.byref(B.struct()), _ptr(tau_t), _ptr(sig_t),
                                        flags, ctypes.byref(C.struct()), _ptr(kept), _ptr(ws), ws.numel(), _stream()))
     return C, kept
@@ -413,7 +416,7 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
     if max_pairs is None:
         max_pairs = max(1, nb * nb * (nb + 1) // 2)
     tape_steps = n_max if keep_tape else 0
-    prec = {"fp64": 0, "fp32": 1}[precision]
+    prec = PRECISIONS[precision]
     base = lib().purify_sp2_workspace_bytes(nb, b, N, int(cap), 0, tape_steps, prec)
     ws = _ws(base + 8 * int(max_pairs) + 1024, dev)
     mp = (ws.numel() - base - 512) // 8   # the pair capacity the library derives
@@ -463,7 +466,7 @@ def purify_batched(Fs, n_occ, eps, taus, homo, lumo, variant="hybrid", n_max=60,
     for q in range(ns):
         pa[q] = sp2_params(int(n_occ[q]), float(eps), int(n_max), VARIANTS[variant[q]], tt[q].data_ptr(),
                            int(tt[q].shape[0]), float(homo[q]), float(lumo[q]), float(delta_const), float(e_tol), 0,
-                           {"fp64": 0, "fp32": 1}[precision[q]], float(tier_split), int(graph_steps), 0)
+                           PRECISIONS[precision[q]], float(tier_split), int(graph_steps), 0)
     capa = (ctypes.c_int64 * ns)(*[int(c) for c in caps])
     mpa = (ctypes.c_int64 * ns)(*[int(m) for m in mps])
     need = lib().purify_sp2_batched_workspace_bytes(ns, Fa, pa, capa, mpa)
@@ -506,7 +509,7 @@ def autotune(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lu
     The schedule is installed process-wide."""
     dev = F.device
     taus = torch.as_tensor(taus, dtype=torch.float64, device=dev).contiguous()
-    prec = {"fp64": 0, "fp32": 1}[precision]
+    prec = PRECISIONS[precision]
     p = sp2_params(int(n_occ), float(eps), int(n_max), VARIANTS[variant], taus.data_ptr(), int(taus.shape[0]),
                    float(homo), float(lumo), float(delta_const), 0.0, 0, prec, float(tier_split), 0, 0)
     ws = _ws(lib().purify_sp2_autotune_workspace_bytes(F.n, int(taus.shape[0]), prec), dev)

@@ -228,7 +228,8 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
 void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatView& C, const uint8_t* fromc,
               MulWs& w, const int32_t* mapX, const double* valX, const int32_t* branch_dev, const int32_t* done,
               hipStream_t s, const float* valA32 = nullptr, const float* valB32 = nullptr,
-              hipEvent_t ev_start = nullptr, hipEvent_t ev_end = nullptr) {
+              hipEvent_t ev_start = nullptr, hipEvent_t ev_end = nullptr, const uint16_t* valA16 = nullptr,
+              const uint16_t* valB16 = nullptr, const int32_t* expA = nullptr, const int32_t* expB = nullptr) {
     const int nb = A.nb;
     GemmArgs g;
     g.b = A.b;
@@ -253,7 +254,11 @@ void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const Mat
     g.done = done;
     g.valA32 = valA32;
     g.valB32 = valB32;
-    g.olow = valA32 ? w.olow : nullptr;
+    g.valA16 = valA16;
+    g.valB16 = valB16;
+    g.expA = expA;
+    g.expB = expB;
+    g.olow = (valA32 || valA16) ? w.olow : nullptr;
     launch_gemm_f64(g, num_cus(), s, ev_start, ev_end);
     if (mapX) launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s);
 }
@@ -280,10 +285,24 @@ bool should_stop(const std::vector<double>& eh, double e_tol) {
 // |fl(AB) - AB| <= (2u + u^2 + gamma_b(2u)(1+u)^2) |A||B| entrywise and
 // ||fl(AB) - AB||_F <= c ||A||_F ||B||_F.  Rounded up by 2^-40.
 double tier_constant(int precision, int b) {
-    if (precision != 1) return 0.0;
-    const double u = 0x1p-24, ue = 2.0 * u, m = (double)b;
-    const double gam = m * ue / (1.0 - m * ue);
-    return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 0x1p-40);
+    const double m = (double)b;
+    if (precision == 1) {
+        const double u = 0x1p-24, ue = 2.0 * u;
+        const double gam = m * ue / (1.0 - m * ue);
+        return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 0x1p-40);
+    }
+    if (precision == 2) {
+        // split BF16: x = hi + lo + e after a power-of-two block scaling,
+        // |lo| <= u (1+u) |x|, |e| <= u^2 (1+u) |x| (u = 2^-8); dropped terms
+        // lo lo', e (hi' + lo'), (hi + lo) e', e e'; the three products exact
+        // in FP32, 3b terms accumulated in FP32 (unit roundoff 2^-23 assumed);
+        // 2^-100 covers entries below the BF16 normal range
+        const double u = 0x1p-8, ue = 2.0 * 0x1p-24;
+        const double kappa = u * u * (pow(1.0 + u, 2.0) + 2.0 * pow(1.0 + u, 3.0) + u * u * pow(1.0 + u, 2.0));
+        const double gam = 3.0 * m * ue / (1.0 - 3.0 * m * ue);
+        return (kappa + gam * (1.0 + 2.0 * u) * pow(1.0 + u, 2.0) + 0x1p-100) * (1.0 + 0x1p-40);
+    }
+    return 0.0;
 }
 
 double trunc_quantum(double delta) { return sp2_trunc_quantum(delta); }
@@ -336,7 +355,8 @@ struct Sp2Ws {
     int64_t* dcount;
     double* bound;  // [N]
     double* bound2; // [N] sweep over the low-precision limit
-    float* x32;     // FP32 copy of the current iterate (precision tier)
+    float* x32;     // FP32 copy of the current iterate (FP32 tier), or its split-BF16 parts
+    int32_t* xexp;  // per-slot exponents of the split-BF16 parts
     Sp2Ctl* ctl;
     sp2_iter_log* dlog;  // [kMaxLog] records written by the device control (graph mode)
 };
@@ -367,6 +387,7 @@ void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, 
     w.ctl = c.take<Sp2Ctl>(1);
     w.dlog = c.take<sp2_iter_log>(kMaxLog);
     w.x32 = precision ? c.take<float>((size_t)cap * b * b) : nullptr;
+    w.xexp = precision == 2 ? c.take<int32_t>(cap) : nullptr;
 }
 
 // argument checks shared by the single and the batched purification
@@ -384,11 +405,12 @@ int check_sp2(const spamm_bsm* F, const sp2_params* p, const spamm_bsm* D) {
     if (!have_gap && isnan(p->delta_const)) return fail(SPAMM_EINVAL, "need homo/lumo or delta_const");
     if (have_gap && !(p->homo < p->lumo)) return fail(SPAMM_EINVAL, "need homo < lumo");
     if (!(p->eps > 0.0)) return fail(SPAMM_EINVAL, "eps must be > 0");
-    if (p->precision != 0 && p->precision != 1) return fail(SPAMM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 tier)");
+    if (p->precision < 0 || p->precision > 2)
+        return fail(SPAMM_EINVAL, "precision must be 0 (FP64), 1 (FP32 tier) or 2 (split-BF16 tier)");
     if (p->graph_steps < 0) return fail(SPAMM_EINVAL, "graph_steps must be >= 0");
     if (p->graph_steps > 0 && p->keep_tape) return fail(SPAMM_EINVAL, "graph mode needs keep_tape = 0");
-    if (p->precision == 1 && F->b > 64) return fail(SPAMM_ENOTSUP, "the FP32 tier supports leaf 32 and 64");
-    if (p->precision == 1 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
+    if (p->precision != 0 && F->b > 64) return fail(SPAMM_ENOTSUP, "the precision tiers support leaf 32 and 64");
+    if (p->precision != 0 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
         return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
     return SPAMM_OK;
 }
@@ -598,6 +620,8 @@ size_t spamm_multiply_tiered_workspace_bytes(int32_t nb, int64_t capA, int64_t c
     Carver c(nullptr);
     c.take<float>((size_t)capA * b * b);
     c.take<float>((size_t)capB * b * b);
+    c.take<int32_t>(capA);
+    c.take<int32_t>(capB);
     MulWs w;
     carve_mul(c, nb, max_pairs, w);
     return c.off + 256;
@@ -612,10 +636,12 @@ int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* 
     if (rc) return rc;
     if (A->nb != B->nb || A->b != B->b || C->nb != A->nb || C->b != A->b)
         return fail(SPAMM_EINVAL, "A, B and C must share n and leaf size");
-    if (A->b > 64) return fail(SPAMM_ENOTSUP, "the FP32 tier supports leaf 32 and 64");
+    if (A->b > 64) return fail(SPAMM_ENOTSUP, "the precision tiers support leaf 32 and 64");
     if (!tau_dev || !sigma_dev) return fail(SPAMM_EINVAL, "tau_dev and sigma_dev are required");
     const int sym = (flags & SPAMM_SYMMETRIC) ? 1 : 0;
     const int btrans = (flags & SPAMM_B_TRANSPOSED) ? 1 : 0;
+    const bool bf16 = (flags & SPAMM_TIER_BF16) != 0;
+    if (bf16 && !btrans) return fail(SPAMM_ENOTSUP, "the split-BF16 tier needs SPAMM_B_TRANSPOSED");
     const size_t base = spamm_multiply_tiered_workspace_bytes(A->nb, A->cap, B->cap, A->b, 0);
     if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "tiered multiply needs at least %zu bytes", base);
     const int64_t max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
@@ -623,14 +649,25 @@ int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* 
     Carver c(ws);
     float* a32 = c.take<float>((size_t)A->cap * A->b * A->b);
     float* b32 = c.take<float>((size_t)B->cap * B->b * B->b);
+    int32_t* ea = c.take<int32_t>(A->cap);
+    int32_t* eb = c.take<int32_t>(B->cap);
     MulWs w;
     carve_mul(c, A->nb, max_pairs, w);
     if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
     fill_i32(w.ovf, 1, 0, s);
-    launch_to_f32(A->b, A->nslot, A->cap, A->brow, A->val, a32, nullptr, s);
-    launch_to_f32(B->b, B->nslot, B->cap, B->brow, B->val, b32, nullptr, s);
+    uint16_t* a16 = reinterpret_cast<uint16_t*>(a32);
+    uint16_t* b16 = reinterpret_cast<uint16_t*>(b32);
+    if (bf16) {
+        launch_to_bf16x2(A->b, A->nslot, A->cap, A->brow, A->val, a16, ea, nullptr, s);
+        launch_to_bf16x2(B->b, B->nslot, B->cap, B->brow, B->val, b16, eb, nullptr, s);
+    } else {
+        launch_to_f32(A->b, A->nslot, A->cap, A->brow, A->val, a32, nullptr, s);
+        launch_to_f32(B->b, B->nslot, B->cap, B->brow, B->val, b32, nullptr, s);
+    }
     run_pairs(view(A), view(B), btrans, sym, tau_dev, sigma_dev, view(C), nullptr, w, nullptr, nullptr, nullptr, s);
-    run_gemm(view(A), view(B), btrans, sym, view(C), nullptr, w, nullptr, nullptr, nullptr, nullptr, s, a32, b32);
+    run_gemm(view(A), view(B), btrans, sym, view(C), nullptr, w, nullptr, nullptr, nullptr, nullptr, s,
+             bf16 ? nullptr : a32, bf16 ? nullptr : b32, nullptr, nullptr, bf16 ? a16 : nullptr, bf16 ? b16 : nullptr,
+             bf16 ? ea : nullptr, bf16 ? eb : nullptr);
     HIP_TRY(hipGetLastError());
     int64_t sc[4];
     int32_t ovf = 0;
@@ -696,7 +733,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     int rc = check_sp2(F, p, D);
     if (rc) return rc;
     const bool have_gap = !isnan(p->homo) && !isnan(p->lumo);
-    const bool tiered = p->precision == 1;
+    const bool tiered = p->precision != 0;
     const double c_low = tier_constant(p->precision, F->b);
     const int nb = F->nb, b = F->b;
     const int tape_steps = p->keep_tape ? p->n_max : 0;
@@ -790,7 +827,11 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             // tier) stays below the whole product budget
             run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2, &w.ctl->sidx,
                       &w.ctl->sigma, w.sw, done, st);
-            launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, st);
+            if (p->precision == 2)
+                launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp,
+                                 done, st);
+            else
+                launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, st);
         }
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));
         // kept pairs, output pattern and the leaf products (combined with X)
@@ -798,7 +839,10 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                   &w.ctl->branch, done, st);
         // evs[2]/evs[3] bracket the product kernel alone
         run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, done, st,
-                 tiered ? w.x32 : nullptr, tiered ? w.x32 : nullptr, evs ? evs[2] : nullptr, evs ? evs[3] : nullptr);
+                 p->precision == 1 ? w.x32 : nullptr, p->precision == 1 ? w.x32 : nullptr, evs ? evs[2] : nullptr,
+                 evs ? evs[3] : nullptr, p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr,
+                 p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr,
+                 p->precision == 2 ? w.xexp : nullptr, p->precision == 2 ? w.xexp : nullptr);
         launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, st, done);
         if (evs) HIP_TRY(hipEventRecord(evs[4], st));
         if (p->variant != 1)
@@ -1168,12 +1212,12 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
     // groups of systems sharing one product launch: same leaf size and tier
     struct Group {
         int b;
-        bool low;
+        int low;  // tier: 0 FP64, 1 FP32, 2 split BF16
         std::vector<int> sys;
     };
     std::vector<Group> groups;
     for (int q = 0; q < nsys; ++q) {
-        const bool low = p[q].precision == 1;
+        const int low = p[q].precision;
         int gi = -1;
         for (size_t k = 0; k < groups.size(); ++k)
             if (groups[k].b == F[q].b && groups[k].low == low) gi = (int)k;
@@ -1225,7 +1269,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
         hc.N = pq->N;
         hc.xh = xh;
         hc.xl = xl;
-        hc.tiered = pq->precision == 1 ? 1 : 0;
+        hc.tiered = pq->precision != 0 ? 1 : 0;
         hc.have_gap = have_gap ? 1 : 0;
         hc.tier_split = pq->tier_split;
         hc.trunc_scale = pq->variant == 0 ? 0.5 : 1.0;
@@ -1253,7 +1297,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                 for (size_t t = 0; t < groups[k].sys.size(); ++t) {
                     const int q = groups[k].sys[t];
                     Sp2Ws& w = W[q];
-                    const bool low = p[q].precision == 1;
+                    const int low = p[q].precision;
                     GemmArgs g;
                     g.b = F[q].b;
                     g.nb = F[q].nb;
@@ -1275,8 +1319,12 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                     g.counters = w.mw.counters;
                     g.ovf = w.mw.ovf;
                     g.done = &w.ctl->done;
-                    g.valA32 = low ? w.x32 : nullptr;
-                    g.valB32 = low ? w.x32 : nullptr;
+                    g.valA32 = low == 1 ? w.x32 : nullptr;
+                    g.valB32 = low == 1 ? w.x32 : nullptr;
+                    g.valA16 = low == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr;
+                    g.valB16 = low == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr;
+                    g.expA = low == 2 ? w.xexp : nullptr;
+                    g.expB = low == 2 ? w.xexp : nullptr;
                     g.olow = low ? w.mw.olow : nullptr;
                     hd[(size_t)par * nsys + gstart[k] + t] = g;
                 }
@@ -1315,7 +1363,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
         for (int q = 0; q < nsys; ++q) {
             Sp2Ws& w = W[q];
             const sp2_params* pq = &p[q];
-            const bool tiered = pq->precision == 1;
+            const bool tiered = pq->precision != 0;
             const int32_t* done = &w.ctl->done;
             MatView xv = view(&w.X[par]);
             MatView nv = view(&w.X[1 - par]);
@@ -1326,7 +1374,11 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                 run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau,
                           tier_constant(pq->precision, F[q].b), w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done,
                           gg.cs);
-                launch_to_f32(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, gg.cs);
+                if (pq->precision == 2)
+                    launch_to_bf16x2(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32),
+                                     w.xexp, done, gg.cs);
+                else
+                    launch_to_f32(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, gg.cs);
             }
             run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
                       &w.ctl->branch, done, gg.cs);

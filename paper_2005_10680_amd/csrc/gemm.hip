@@ -388,6 +388,33 @@ SPAMM_DEV void dma_chunk(const char* __restrict__ src, char* lds_dst) {
     }
 }
 
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Copy inner indices 32c .. 32c+31 of one split-BF16 block (hi part, then lo
+// part, each b rows of b bf16, row-major) into LDS: per part b rows of four
+// 16 B groups (8 inner indices each).  Group g of row r sits at position
+// (g + r/4) mod 4 of its row, so the 16 rows one MFMA operand read touches
+// fall in 16 different bank quads.  Every 1 KB piece is 64 lane-contiguous
+// 16 B copies, as the direct-to-LDS copy requires; each lane picks the
+// global source of its LDS position.
+template <int B>
+SPAMM_DEV void dma_bf16_chunk(const char* __restrict__ blk, int chunk, char* lds_dst) {
+    using R = RingCfg<B>;
+    constexpr int PPP = B / 16;  // 1 KB pieces per part
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < R::NI; ++q) {
+        const int piece = w + 4 * q;
+        const int part = piece / PPP, pp = piece % PPP;
+        const int pos = pp * 64 + lane;
+        const int row = pos >> 2, kg = ((pos & 3) - (row >> 2)) & 3;
+        const char* src = blk + (size_t)part * B * B * 2 + (size_t)row * B * 2 + chunk * 64 + kg * 16;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(lds_dst + piece * 1024), 16, 0,
+                                         0);
+    }
+}
+
 // Read-only (for the whole launch) data at a wave-uniform index, through the
 // constant address space: a scalar load, which never waits behind vector
 // memory operations in flight.
@@ -496,6 +523,10 @@ struct RingCtx {
     const double* valB;
     const float* valA32;
     const float* valB32;
+    const uint16_t* valA16;
+    const uint16_t* valB16;
+    const int32_t* expA;
+    const int32_t* expB;
     int p0, nlow, nst_low, nst;
     d4 acc[R::TM][R::TN];
     f4 acc32[R::TM][R::TN];
@@ -506,6 +537,10 @@ struct RingCtx {
         valB = g.valB;
         valA32 = g.valA32;
         valB32 = g.valB32;
+        valA16 = g.valA16;
+        valB16 = g.valB16;
+        expA = g.expA;
+        expB = g.expB;
     }
 
     template <int SLOT>
@@ -522,9 +557,17 @@ struct RingCtx {
         // the pair list is read-only during the launch: read it through the
         // constant address space (scalar loads, counted apart from the copies)
         const int2 pr = const_ld(pairs, p0 + pr_i);
+        if constexpr (LOWT == 2) {
+            if (low) {
+                dma_bf16_chunk<B>(reinterpret_cast<const char*>(valA16 + (size_t)pr.x * 2 * B * B), chunk, dst);
+                dma_bf16_chunk<B>(reinterpret_cast<const char*>(valB16 + (size_t)pr.y * 2 * B * B), chunk,
+                                  dst + R::OPB);
+                return;
+            }
+        }
         const char* a0;
         const char* b0;
-        if (low) {
+        if (LOWT == 1 && low) {
             a0 = reinterpret_cast<const char*>(valA32 + (size_t)pr.x * B * B + (size_t)chunk * R::KC32 * B);
             b0 = reinterpret_cast<const char*>(valB32 + (size_t)pr.y * B * B + (size_t)chunk * R::KC32 * B);
         } else if (pr.x >= 0) {
@@ -545,7 +588,54 @@ struct RingCtx {
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         const int wm = w >> 1, wn = w & 1;
         const char* sl = RingSlot<B, SLOT>::get();
-        if (LOWT && st < nst_low) {
+        if (LOWT == 2 && st < nst_low) {
+            // split-BF16 stage: 32 inner indices, parts hi and lo of A and B
+            // (swizzled rows of four 16 B groups, see dma_bf16_chunk); the A
+            // rows go in the order pi(m) = m/4 + 4(m%4) as in the FP32 tier
+            const int mrow = ((lane & 15) >> 2) + 4 * (lane & 3);
+            const int kg = lane >> 4;
+            auto rd = [&](const char* part, int row) -> bf8 {
+                const int pos = row * 4 + ((kg + (row >> 2)) & 3);
+                return *reinterpret_cast<const bf8*>(part + pos * 16);
+            };
+            const char* Ah = sl;
+            const char* Al = sl + B * 64;
+            const char* Bh = sl + R::OPB;
+            const char* Bl = sl + R::OPB + B * 64;
+            bf8 ah[R::TM], al[R::TM], bh[R::TN], bl[R::TN];
+#pragma unroll
+            for (int a = 0; a < R::TM; ++a) {
+                ah[a] = rd(Ah, wm * R::TM * 16 + a * 16 + mrow);
+                al[a] = rd(Al, wm * R::TM * 16 + a * 16 + mrow);
+            }
+#pragma unroll
+            for (int b = 0; b < R::TN; ++b) {
+                bh[b] = rd(Bh, wn * R::TN * 16 + b * 16 + (lane & 15));
+                bl[b] = rd(Bl, wn * R::TN * 16 + b * 16 + (lane & 15));
+            }
+#pragma unroll
+            for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+                for (int b = 0; b < R::TN; ++b) {
+                    acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc32[a][b], 0, 0, 0);
+                    acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc32[a][b], 0, 0, 0);
+                    acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc32[a][b], 0, 0, 0);
+                }
+            if ((st % R::CH32) == R::CH32 - 1) {
+                // end of one pair: undo the two blocks' scalings (exact) and
+                // fold into FP64
+                const int2 pr = const_ld(pairs, p0 + st / R::CH32);
+                const int e = const_ld(expA, pr.x) + const_ld(expB, pr.y);
+#pragma unroll
+                for (int a = 0; a < R::TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < R::TN; ++b) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[a][b][r] = acc[a][b][r] + ldexp((double)acc32[a][b][r], e);
+                        acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+        } else if (LOWT == 1 && st < nst_low) {
             const float* As = reinterpret_cast<const float*>(sl);
             const float* Bs = reinterpret_cast<const float*>(sl + R::OPB);
             // The f32 16x16x4 result puts row 4(l>>4)+r in register r of lane
@@ -825,6 +915,7 @@ void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev
     int grid = num_cu * per_cu;
     grid = (grid + 7) / 8 * 8;
     const bool low = g.valA32 != nullptr;
+    const bool low16 = g.valA16 != nullptr;
 #define SPAMM_G(B_, T_, L_) hipLaunchKernelGGL((k_gemm<B_, T_, L_>), dim3(grid), dim3(256), 0, s, g)
 #define SPAMM_GB(T_)                                                     \
     switch (g.b) {                                                       \
@@ -835,9 +926,11 @@ void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev
     if (g.btrans) {
         const int gr = ring_grid(g.b, num_cu);
         switch (g.b) {
-            case 32: if (low) hipLaunchKernelGGL((k_gemm_ring<32, 1>), dim3(gr), dim3(256), 0, s, g);
+            case 32: if (low16) hipLaunchKernelGGL((k_gemm_ring<32, 2>), dim3(gr), dim3(256), 0, s, g);
+                     else if (low) hipLaunchKernelGGL((k_gemm_ring<32, 1>), dim3(gr), dim3(256), 0, s, g);
                      else hipLaunchKernelGGL((k_gemm_ring<32, 0>), dim3(gr), dim3(256), 0, s, g); break;
-            case 64: if (low) hipLaunchKernelGGL((k_gemm_ring<64, 1>), dim3(gr), dim3(256), 0, s, g);
+            case 64: if (low16) hipLaunchKernelGGL((k_gemm_ring<64, 2>), dim3(gr), dim3(256), 0, s, g);
+                     else if (low) hipLaunchKernelGGL((k_gemm_ring<64, 1>), dim3(gr), dim3(256), 0, s, g);
                      else hipLaunchKernelGGL((k_gemm_ring<64, 0>), dim3(gr), dim3(256), 0, s, g); break;
             case 128: hipLaunchKernelGGL((k_gemm_ring<128, 0>), dim3(gr), dim3(256), 0, s, g); break;
         }
@@ -849,7 +942,7 @@ void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev
 #undef SPAMM_G
 }
 
-void launch_gemm_batch(int b, bool low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
+void launch_gemm_batch(int b, int low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
                        int32_t* counters, int num_cu, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(64), 0, s, descs_dev, nsys, out_off, pair_off);
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counters);
@@ -858,11 +951,84 @@ void launch_gemm_batch(int b, bool low, const GemmArgs* descs_dev, int nsys, int
     hipLaunchKernelGGL((k_gemm_ring_batch<B_, L_>), dim3(gr), dim3(256), 0, s, descs_dev, nsys, out_off, pair_off, \
                        counters)
     switch (b) {
-        case 32: if (low) SPAMM_GBT(32, 1); else SPAMM_GBT(32, 0); break;
-        case 64: if (low) SPAMM_GBT(64, 1); else SPAMM_GBT(64, 0); break;
+        case 32: if (low == 2) SPAMM_GBT(32, 2); else if (low) SPAMM_GBT(32, 1); else SPAMM_GBT(32, 0); break;
+        case 64: if (low == 2) SPAMM_GBT(64, 2); else if (low) SPAMM_GBT(64, 1); else SPAMM_GBT(64, 0); break;
         case 128: SPAMM_GBT(128, 0); break;
     }
 #undef SPAMM_GBT
+}
+
+// Round to the nearest BF16 value (8 significant bits, ties to even, BF16
+// subnormal spacing 2^-133), in double arithmetic: every step is exact.
+SPAMM_DEV double rn_bf16(double x) {
+    if (x == 0.0) return x;
+    int e;
+    frexp(x, &e);
+    int q = e - 8;
+    if (q < -133) q = -133;
+    return ldexp(rint(ldexp(x, -q)), q);
+}
+
+// bits of a BF16 value held exactly in a double
+SPAMM_DEV uint16_t bf16_bits(double v) { return (uint16_t)(__float_as_uint((float)v) >> 16); }
+
+// Split-BF16 copies of the live blocks: the block is scaled by 2^-e so that
+// its largest |x| lies in [1, 2) (exact), then hi = RN_bf16(x'), lo =
+// RN_bf16(x' - hi); both parts row-major, hi then lo per slot; expo = e.
+// The block passes through a padded LDS tile so that the column-major read
+// and the row-major writes are both coalesced.
+template <int B>
+__global__ __launch_bounds__(256) void k_to_bf16x2(const int32_t* __restrict__ nslot_p, int64_t cap,
+                                                  const int32_t* __restrict__ brow, const double* __restrict__ val,
+                                                  uint16_t* __restrict__ out, int32_t* __restrict__ expo,
+                                                  const int32_t* __restrict__ done) {
+    __shared__ double t[B * (B + 1)];
+    __shared__ double red[256];
+    if (done && *done) return;
+    int64_t nslot = *nslot_p;
+    if (nslot > cap) nslot = cap;
+    const int tid = threadIdx.x;
+    for (int64_t s = blockIdx.x; s < nslot; s += gridDim.x) {
+        if (brow[s] < 0) continue;
+        const double* v = val + (size_t)s * B * B;
+        double m = 0.0;
+        for (int e = tid; e < B * B; e += 256) {
+            const int c = e / B, r = e % B;  // column-major source
+            const double x = v[e];
+            t[r * (B + 1) + c] = x;
+            m = fmax(m, fabs(x));
+        }
+        red[tid] = m;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st) red[tid] = fmax(red[tid], red[tid + st]);
+            __syncthreads();
+        }
+        int ex = 0;
+        if (red[0] > 0.0) frexp(red[0], &ex);
+        const int sc = 1 - ex;  // x' = x 2^sc has its largest |x'| in [1, 2)
+        uint16_t* hi = out + (size_t)s * 2 * B * B;
+        uint16_t* lo = hi + B * B;
+        for (int e = tid; e < B * B; e += 256) {
+            const int r = e / B, c = e % B;  // row-major destination
+            const double x = ldexp(t[r * (B + 1) + c], sc);
+            const double h = rn_bf16(x);
+            const double l = rn_bf16(x - h);
+            hi[e] = bf16_bits(h);
+            lo[e] = bf16_bits(l);
+        }
+        if (tid == 0) expo[s] = -sc;
+        __syncthreads();
+    }
+}
+
+void launch_to_bf16x2(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, uint16_t* out,
+                      int32_t* expo, const int32_t* done, hipStream_t s) {
+    const int grid = grid_for(cap, 1, 8192);
+    switch (b) {
+        case 32: hipLaunchKernelGGL((k_to_bf16x2<32>), dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, expo, done); break;
+        case 64: hipLaunchKernelGGL((k_to_bf16x2<64>), dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, expo, done); break;
+    }
 }
 
 // FP32 copies of the live blocks (round to nearest), for the low tier.

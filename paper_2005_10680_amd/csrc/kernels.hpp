@@ -103,6 +103,12 @@ struct GemmArgs {
     const float* valA32 = nullptr;
     const float* valB32 = nullptr;
     const int32_t* olow = nullptr;
+    // split-BF16 tier (null when off): per slot the hi part (b*b bf16,
+    // row-major) then the lo part, and the slot's power-of-two exponent
+    const uint16_t* valA16 = nullptr;
+    const uint16_t* valB16 = nullptr;
+    const int32_t* expA = nullptr;
+    const int32_t* expB = nullptr;
 };
 // ev_start/ev_end (optional) are recorded right around the product kernel.
 void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start = nullptr,
@@ -112,8 +118,12 @@ int get_ring_per_cu(int b);
 void set_ring_per_cu(int b, int per_cu);
 // several products in one launch: descs_dev[nsys] on the device, out_off and
 // pair_off [nsys + 1] scratch, counters [16]
-void launch_gemm_batch(int b, bool low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
+void launch_gemm_batch(int b, int low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
                        int32_t* counters, int num_cu, hipStream_t s);
+// split-BF16 copies of the live blocks: x = 2^e (hi + lo + err), max |x| 2^-e
+// in [1, 2), hi = RN_bf16, lo = RN_bf16(x 2^-e - hi); row-major per slot
+void launch_to_bf16x2(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, uint16_t* out,
+                      int32_t* expo, const int32_t* done, hipStream_t s);
 void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
                    const int32_t* done, hipStream_t s);
 

@@ -1,8 +1,9 @@
-"""GPU parity of the FP32 leaf-product tier (mixed precision, not in the
-paper): the kept set and the tier split are bit-exact against the oracle;
-the product differs from the oracle's FP64 product by no more than the
-Algorithm 3 bound over the folded rounding terms c_32 * p of the low-tier
-pairs; mixed purification still meets ||D~ - D||_F < 1e-6."""
+"""GPU parity of the low-precision leaf-product tiers (FP32 and split BF16;
+mixed precision, not in the paper): the kept set and the tier split are
+bit-exact against the oracle; the product differs from the oracle's FP64
+product by no more than the Algorithm 3 bound over the folded rounding
+terms c_t * p of the low-tier pairs; mixed purification still meets
+||D~ - D||_F < 1e-6 and takes the oracle's decisions step by step."""
 import numpy as np
 import pytest
 
@@ -29,13 +30,18 @@ def sym_x(n, b, seed):
     return oracle.x0(F, lmin, lmax)
 
 
+TIERS = {"fp32": 1, "bf16x3": 2}
+
+
 def test_tier_constant_matches_oracle():
-    for b in (32, 64):
-        assert P.tier_constant(1, b) == oracle.tier_constant(1, b)
+    for prec in (1, 2):
+        for b in (32, 64):
+            assert P.tier_constant(prec, b) == oracle.tier_constant(prec, b)
 
 
+@pytest.mark.parametrize("tier", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("n,b,seed", [(2000, 64, 2), (1024, 32, 5)])
-def test_multiply_tiered_within_folded_bound(n, b, seed):
+def test_multiply_tiered_within_folded_bound(n, b, seed, tier):
     X = sym_x(n, b, seed)
     # a squared iterate has the spread of norms the tier is meant for
     C0, _ = oracle.spamm(X, X, 0.0, sym=True)
@@ -45,7 +51,7 @@ def test_multiply_tiered_within_folded_bound(n, b, seed):
     sigma = float(np.quantile(nu, 0.6)) ** 2
     M = P.BlockSparse.from_host(X)
     P.build_norms(M)
-    C, kept = P.multiply_tiered(M, M, tau, sigma, symmetric=True, b_transposed=True)
+    C, kept = P.multiply_tiered(M, M, tau, sigma, symmetric=True, b_transposed=True, tier=tier)
     Co, Ko = oracle.spamm(X, X, tau, sym=True)
     kg = kept.cpu().numpy()
     assert int(kg[0]) == Ko.npairs
@@ -56,7 +62,7 @@ def test_multiply_tiered_within_folded_bound(n, b, seed):
     # Algorithm 3 over the rounding terms of the low tier only
     nb = X.nb
     mp = X.block_map()
-    c = oracle.tier_constant(1, b)
+    c = oracle.tier_constant(TIERS[tier], b)
     lv = np.zeros((nb, nb, nb))
     for i in range(nb):
         for k in range(nb):
@@ -75,7 +81,7 @@ def test_multiply_tiered_within_folded_bound(n, b, seed):
     ref = np.linalg.norm(Co.to_dense())
     # the bound runs over all triples, so it covers both mirrored triangles
     assert np.linalg.norm(diff) <= bound_sym * 1.0000001 + 1e-13 * ref
-    assert np.linalg.norm(diff) > 0.0          # the FP32 tier really ran
+    assert np.linalg.norm(diff) > 0.0          # the low tier really ran
 
 
 def test_purify_fp32_tier_chain():
@@ -101,7 +107,8 @@ def test_purify_fp32_tier_chain():
     assert np.array_equal(D64.keys(), Dm.keys()) and np.array_equal(D64.vals, Dm.vals)
 
 
-def test_purify_fp32_tier_teacher_forced():
+@pytest.mark.parametrize("tier", ["fp32", "bf16x3"])
+def test_purify_tier_teacher_forced(tier):
     n, b = 2048, 64
     Fm = synth.sys3d(n, 12, b)
     F = oracle.BSM.of(Fm)
@@ -109,9 +116,10 @@ def test_purify_fp32_tier_teacher_forced():
     n_occ = n // 2
     Dref = U[:, :n_occ] @ U[:, :n_occ].T
     taus = synth.tau_log(32)
-    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=taus, homo=w[n_occ - 1], lumo=w[n_occ], precision=1)
+    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=taus, homo=w[n_occ - 1], lumo=w[n_occ],
+                         precision=TIERS[tier])
     G = P.BlockSparse.from_host(Fm)
-    res = P.purify(G, n_occ, 1e-6, taus, homo=w[n_occ - 1], lumo=w[n_occ], keep_tape=True, precision="fp32")
+    res = P.purify(G, n_occ, 1e-6, taus, homo=w[n_occ - 1], lumo=w[n_occ], keep_tape=True, precision=tier)
     steps = [lg for lg in res.logs if lg["branch"] >= 0]
     _, _, st, _ = oracle.sp2_start(F, p)
     xh, xl, e_hist = st.xh, st.xl, []
