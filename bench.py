@@ -186,22 +186,25 @@ def main():
                           "tape_entries": rt.nlog, "cap_blocks": capt}
         del rt, dbar
 
-    # mixed precision (FP32 leaf-product tier) on the same workload
-    res_mixed = None
+    # mixed precision (FP32 and split-BF16 leaf-product tiers) on the same workload
+    res_mixed = {}
     if not args.no_mixed:
-        run_once("fp32")
-        mtimes = []
-        for _ in range(args.steps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            res_mixed = run_once("fp32")
-            torch.cuda.synchronize()
-            mtimes.append(time.perf_counter() - t0)
-        msteps = [l for l in res_mixed.logs if l["branch"] >= 0]
-        mpairs = sum(l["npairs"] for l in msteps)
-        mlow = sum(l["npairs_low"] for l in msteps)
-        log(f"mixed: {float(np.median(mtimes)):.3f} s, {len(msteps)} iterations, low-tier share {mlow / max(mpairs, 1):.3f}")
-        out["mixed"] = {"precision": "fp32 tier", "sp2_time_s": round(float(np.median(mtimes)), 4),
+        for tier, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3")):
+            run_once(tier)
+            mtimes = []
+            for _ in range(args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rm = run_once(tier)
+                torch.cuda.synchronize()
+                mtimes.append(time.perf_counter() - t0)
+            res_mixed[key] = rm
+            msteps = [l for l in rm.logs if l["branch"] >= 0]
+            mpairs = sum(l["npairs"] for l in msteps)
+            mlow = sum(l["npairs_low"] for l in msteps)
+            log(f"{tier} tier: {float(np.median(mtimes)):.3f} s, {len(msteps)} iterations, "
+                f"low-tier share {mlow / max(mpairs, 1):.3f}")
+            out[key] = {"precision": f"{tier} tier", "sp2_time_s": round(float(np.median(mtimes)), 4),
                         "iterations": len(msteps), "kept_pairs_per_run": int(mpairs),
                         "low_tier_pairs_per_run": int(mlow),
                         "kept_TFLOP_per_s": round(mpairs * 2.0 * b ** 3 / float(np.median(mtimes)) / 1e12, 4),
@@ -223,16 +226,16 @@ def main():
         Dref = Uo @ Uo.T
         err = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
         out["verify_fro_err"] = err
-        if res_mixed is not None:
-            Dm = res_mixed.D.to_host()
+        for key, rm in res_mixed.items():
+            Dm = rm.D.to_host()
             Dd[:] = 0.0
             for k in range(Dm.brow.shape[0]):
                 r, c = int(Dm.brow[k]), int(Dm.bcol[k])
                 blk = Dm.vals[k].T
                 rr, cc = min(b, n - r * b), min(b, n - c * b)
                 Dd[r * b:r * b + rr, c * b:c * b + cc] = blk[:rr, :cc]
-            out["mixed"]["verify_fro_err"] = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
-        log(f"verified: fp64 {err:.3e}" + (f", mixed {out['mixed']['verify_fro_err']:.3e}" if res_mixed else ""))
+            out[key]["verify_fro_err"] = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
+        log(f"verified: fp64 {err:.3e}" + "".join(f", {k} {out[k]['verify_fro_err']:.3e}" for k in res_mixed))
         del Fd, U, Uo, Dref
 
     if args.copy_mb:
