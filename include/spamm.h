@@ -175,7 +175,8 @@ typedef struct sp2_params {
     double homo, lumo;   /* eigenvalue bounds of F around the gap (homo < lumo), or NaN */
     double delta_const;  /* explicit per-step delta when homo/lumo are NaN (else NaN) */
     double e_tol;        /* stop when |tr X - ||X||_F^2| <= e_tol (0: noise-floor rule only) */
-    int32_t keep_tape;   /* nonzero: keep every X~_i in the workspace (adjoint, inspection) */
+    int32_t keep_tape;   /* 0: none; 1: keep every X~_i in the workspace; k > 1: keep X~_0, X~_k,
+                            X~_2k, ... (checkpoints for the adjoint) */
     int32_t precision;   /* 0 FP64 leaf products; for pairs with tau <= p < sigma (leaf 32/64):
                             1 FP32 tier, 2 split-BF16 tier (hi*hi + hi*lo + lo*hi on the BF16 MFMA) */
     double tier_split;   /* share of the product budget given to skipping when precision != 0 (e.g. 0.5) */
@@ -211,7 +212,8 @@ typedef struct sp2_iter_log {
  *   F     : symmetric input with norms NOT required (computed internally).
  *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise).
  *   log   : host [n_max + 2] records; nlog_out: records written.
- * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, keep_tape ? n_max : 0, precision).
+ * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, tape_steps, precision) with
+ * tape_steps = n_max (keep_tape = 1), n_max / keep_tape (keep_tape > 1) or 0.
  * Host-driven loop: reads scalars back every iteration (synchronises the
  * stream).  Graph mode (graph_steps > 0): same decisions, same kernels and
  * bit-identical results; the stream is synchronised once per graph_steps
@@ -266,24 +268,36 @@ int spamm_adjoint_step(const spamm_bsm* X, const spamm_bsm* G, double tau, int32
 /*
  * Gradient of a loss with respect to F through a whole recorded purification.
  *   F        : the input of the forward run (pattern arrays, n, b).
- *   tape     : host array of ntape handles X~_0 .. X~_{ntape-1}
- *              (purify_sp2_tape_view of a run with keep_tape); the last one
- *              is D~.  The forward workspace must be unchanged.
- *   log      : the forward run's records (nlog == ntape): record t-1 holds
- *              tau and the branch of step t; the last record is the stop.
- *   dbar_val : device [cap * b * b]: dL/dD~ in the slot layout of
- *              tape[ntape-1] (only its symmetric part is used).
+ *   p        : the forward run's parameters (variant, precision).
+ *   tape, ntape, tape_every : host array of handles (purify_sp2_tape_view
+ *              of a run with keep_tape = tape_every):
+ *              tape_every = 1: every iterate X~_0 .. X~_T (T = nlog - 1
+ *                steps), ntape = nlog;
+ *              tape_every = k > 1: checkpoints X~_0, X~_k, X~_2k, ...; each
+ *                segment is recomputed from its checkpoint with the recorded
+ *                thresholds, branches and deltas by the forward's own
+ *                kernels (bit-identical iterates), FP64 runs only.
+ *              The forward workspace must be unchanged.
+ *   D        : the run's result D~ = X~_T (required with checkpoints, may be
+ *              NULL with a full tape).
+ *   log      : the forward run's records: record t-1 holds tau, delta and
+ *              the branch of step t; the last record is the stop.
+ *   dbar_val : device [cap * b * b]: dL/dD~ in the slot layout of D~ (only
+ *              its symmetric part is used).
  *   fbar_val : output, device [F->cap * b * b] in F's slot layout:
  *              Fbar = -Xbar_0 / (lmax - lmin) on the blocks of F that the
  *              first truncation kept, zero on those it removed.
- * Workspace: purify_sp2_adjoint_workspace_bytes(nb, b, cap, max_pairs) with
- * cap the tape entries' capacity; SPAMM_ECAPACITY when a step's pair list
+ * Workspace: purify_sp2_adjoint_workspace_bytes(nb, b, cap, max_pairs,
+ * tape_every) with cap the tape entries' capacity; with checkpoints it also
+ * holds tape_every - 1 matrices of that capacity and the recomputation's
+ * own pair list (of the same max_pairs).  SPAMM_ECAPACITY when a pair list
  * needs more than max_pairs (a bound: nb^2 (nb + 1)).  Synchronises.
  */
-size_t purify_sp2_adjoint_workspace_bytes(int32_t nb, int32_t b, int64_t cap_blocks, int64_t max_pairs);
-int purify_sp2_adjoint(const spamm_bsm* F, const spamm_bsm* tape, int32_t ntape, const sp2_iter_log* log,
-                       int32_t nlog, const double* dbar_val, double* fbar_val, void* ws, size_t ws_bytes,
-                       spamm_stream_t stream);
+size_t purify_sp2_adjoint_workspace_bytes(int32_t nb, int32_t b, int64_t cap_blocks, int64_t max_pairs,
+                                          int32_t tape_every);
+int purify_sp2_adjoint(const spamm_bsm* F, const sp2_params* p, const spamm_bsm* tape, int32_t ntape,
+                       int32_t tape_every, const spamm_bsm* D, const sp2_iter_log* log, int32_t nlog,
+                       const double* dbar_val, double* fbar_val, void* ws, size_t ws_bytes, spamm_stream_t stream);
 
 /*
  * Batched purification of nsys independent systems (not in the paper; each

@@ -108,9 +108,10 @@ def lib() -> ctypes.CDLL:
     L.spamm_adjoint_step_workspace_bytes.argtypes = [i32, i64, i64]
     L.spamm_adjoint_step_workspace_bytes.restype = sz
     L.spamm_adjoint_step.argtypes = [B, B, d, i32, P, P, P, sz, P]
-    L.purify_sp2_adjoint_workspace_bytes.argtypes = [i32, i32, i64, i64]
+    L.purify_sp2_adjoint_workspace_bytes.argtypes = [i32, i32, i64, i64, i32]
     L.purify_sp2_adjoint_workspace_bytes.restype = sz
-    L.purify_sp2_adjoint.argtypes = [B, B, i32, ctypes.POINTER(sp2_iter_log), i32, P, P, P, sz, P]
+    L.purify_sp2_adjoint.argtypes = [B, ctypes.POINTER(sp2_params), B, i32, i32, B, ctypes.POINTER(sp2_iter_log),
+                                     i32, P, P, P, sz, P]
     L.purify_sp2_batched_workspace_bytes.argtypes = [i32, B, ctypes.POINTER(sp2_params), P, P]
     L.purify_sp2_batched_workspace_bytes.restype = sz
     L.purify_sp2_batched.argtypes = [i32, B, ctypes.POINTER(sp2_params), B, P, ctypes.POINTER(sp2_iter_log), i32,
@@ -390,6 +391,9 @@ class PurifyResult:
     tape_args: tuple | None
     raw_logs: object = None
     nlog: int = 0
+    tape_every: int = 0
+    params: object = None     # the sp2_params of the run (kept with its tau tensor)
+    taus: object = None
 
     def tape(self, step: int) -> BlockSparse:
         """X~_step of a run with keep_tape (a view into the workspace)."""
@@ -415,14 +419,15 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
         cap = nb * nb
     if max_pairs is None:
         max_pairs = max(1, nb * nb * (nb + 1) // 2)
-    tape_steps = n_max if keep_tape else 0
+    every = int(keep_tape)
+    tape_steps = n_max if every == 1 else (n_max // every if every > 1 else 0)
     prec = PRECISIONS[precision]
     base = lib().purify_sp2_workspace_bytes(nb, b, N, int(cap), 0, tape_steps, prec)
     ws = _ws(base + 8 * int(max_pairs) + 1024, dev)
     mp = (ws.numel() - base - 512) // 8   # the pair capacity the library derives
     D = BlockSparse(F.n, b, cap, dev)
     p = sp2_params(int(n_occ), float(eps), int(n_max), VARIANTS[variant], taus.data_ptr(), N, float(homo),
-                   float(lumo), float(delta_const), float(e_tol), 1 if keep_tape else 0, prec, float(tier_split),
+                   float(lumo), float(delta_const), float(e_tol), every, prec, float(tier_split),
                    int(graph_steps), 0)
     logs = (sp2_iter_log * (n_max + 2))()
     nlog = ctypes.c_int32(0)
@@ -430,8 +435,8 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
                           ctypes.byref(nlog), _ptr(ws), ws.numel(), _stream())
     _check(rc)
     out = [{k: getattr(logs[i], k) for k, _ in sp2_iter_log._fields_} for i in range(nlog.value)]
-    targs = (nb, b, N, int(cap), int(mp), tape_steps) if keep_tape else None
-    return PurifyResult(D, out, rc, ws, targs, logs, nlog.value)
+    targs = (nb, b, N, int(cap), int(mp), tape_steps) if every else None
+    return PurifyResult(D, out, rc, ws, targs, logs, nlog.value, every, p, taus)
 
 
 @dataclass
@@ -550,25 +555,29 @@ def with_values(M: BlockSparse, val: torch.Tensor) -> BlockSparse:
 def purify_adjoint(res: PurifyResult, F: BlockSparse, dbar: torch.Tensor, max_pairs=None) -> torch.Tensor:
     """dL/dF (values in F's slot layout) from dbar = dL/dD~ (values in the
     slot layout of res.D) through the recorded run res (purify with
-    keep_tape), decisions held fixed (purify_sp2_adjoint)."""
+    keep_tape = 1, or k > 1 for checkpoints every k iterates), decisions
+    held fixed (purify_sp2_adjoint)."""
     if res.tape_args is None:
         raise ValueError("purify was run without keep_tape")
     nb, b = F.nb, F.b
-    ntape = res.nlog
+    every = res.tape_every
+    steps = res.nlog - 1
+    ntape = res.nlog if every == 1 else steps // every + 1
     tape = (spamm_bsm * ntape)()
     for t in range(ntape):
         _check(lib().purify_sp2_tape_view(_ptr(res.ws), *res.tape_args, t, ctypes.byref(tape[t])))
     cap = res.tape_args[3]
     if max_pairs is None:
         max_pairs = max(1, nb * nb * (nb + 1))
-    base = lib().purify_sp2_adjoint_workspace_bytes(nb, b, cap, 0)
-    ws = _ws(base + 8 * int(max_pairs) + 1024, F.device)
+    base = lib().purify_sp2_adjoint_workspace_bytes(nb, b, cap, 0, every)
+    ws = _ws(base + (16 if every > 1 else 8) * int(max_pairs) + 1024, F.device)
     dbar = dbar.to(torch.float64).contiguous()
     if dbar.numel() < cap * b * b:
         raise ValueError("dbar must hold the slots of D")
     fbar = torch.zeros(F.cap * b * b, dtype=torch.float64, device=F.device)
-    _check(lib().purify_sp2_adjoint(ctypes.byref(F.struct()), tape, ntape, res.raw_logs, res.nlog,
-                                    dbar.data_ptr(), fbar.data_ptr(), _ptr(ws), ws.numel(), _stream()))
+    _check(lib().purify_sp2_adjoint(ctypes.byref(F.struct()), ctypes.byref(res.params), tape, ntape, every,
+                                    ctypes.byref(res.D.struct()), res.raw_logs, res.nlog, dbar.data_ptr(),
+                                    fbar.data_ptr(), _ptr(ws), ws.numel(), _stream()))
     return fbar
 
 
@@ -578,7 +587,9 @@ class _Purify(torch.autograd.Function):
     @staticmethod
     def forward(ctx, fval, F, kw, holder):
         Fv = with_values(F, fval.detach().contiguous())
-        res = purify(Fv, keep_tape=True, **kw)
+        kw = dict(kw)
+        every = int(kw.pop("checkpoint_every", 1))
+        res = purify(Fv, keep_tape=every, **kw)
         ctx.res, ctx.F = res, Fv
         holder["res"] = res
         return res.D.val
@@ -593,7 +604,8 @@ def purify_autograd(F: BlockSparse, fval: torch.Tensor, n_occ: int, eps: float, 
     values are in the slot layout of result.D.  Gradients flow to fval (F's
     value array, F's slot layout) for symmetric perturbations, with the
     run's decisions (kept sets, truncation patterns, branches, Gerschgorin
-    bounds) held fixed."""
+    bounds) held fixed.  checkpoint_every = k > 1 keeps every k-th iterate
+    and recomputes the others in the backward pass (FP64 runs)."""
     holder = {}
     dval = _Purify.apply(fval, F, dict(kw, n_occ=n_occ, eps=eps, taus=taus), holder)
     return dval, holder["res"]

@@ -338,6 +338,20 @@ void carve_mat(Carver& c, int64_t n, int b, int64_t cap, spamm_bsm& m) {
     m.sqlo = c.take<double>(cap);
 }
 
+// dst = src (pattern, values, norms); both with capacity cap
+int copy_mat(const spamm_bsm& dst, const spamm_bsm& src, int64_t cap, hipStream_t s) {
+    const int nb = src.nb, b = src.b;
+    HIP_TRY(hipMemcpyAsync(dst.nslot, src.nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dst.brow, src.brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dst.bcol, src.bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dst.map, src.map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dst.val, src.val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dst.norm, src.norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dst.sq, src.sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dst.sqlo, src.sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+    return SPAMM_OK;
+}
+
 struct Sp2Ws {
     spamm_bsm X[2];
     std::vector<spamm_bsm> tape;
@@ -409,6 +423,7 @@ int check_sp2(const spamm_bsm* F, const sp2_params* p, const spamm_bsm* D) {
         return fail(SPAMM_EINVAL, "precision must be 0 (FP64), 1 (FP32 tier) or 2 (split-BF16 tier)");
     if (p->graph_steps < 0) return fail(SPAMM_EINVAL, "graph_steps must be >= 0");
     if (p->graph_steps > 0 && p->keep_tape) return fail(SPAMM_EINVAL, "graph mode needs keep_tape = 0");
+    if (p->keep_tape < 0 || p->keep_tape > p->n_max) return fail(SPAMM_EINVAL, "keep_tape must be in 0..n_max");
     if (p->precision != 0 && F->b > 64) return fail(SPAMM_ENOTSUP, "the precision tiers support leaf 32 and 64");
     if (p->precision != 0 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
         return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
@@ -736,7 +751,9 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     const bool tiered = p->precision != 0;
     const double c_low = tier_constant(p->precision, F->b);
     const int nb = F->nb, b = F->b;
-    const int tape_steps = p->keep_tape ? p->n_max : 0;
+    // keep_tape: 0 none, 1 every iterate, k > 1 every k-th iterate (checkpoints)
+    const int every = p->keep_tape;
+    const int tape_steps = every == 1 ? p->n_max : (every > 1 ? p->n_max / every : 0);
     // internal capacity: whatever the workspace holds (the binding sizes it)
     int64_t cap = 0;
     {
@@ -796,17 +813,11 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     hc.delta = delta0;
     HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
     if (p->variant != 1) launch_truncate(X0, &w.ctl->delta, 0.0, 1.0, w.trunc_tmp, cap, w.tstats, w.mw.ovf, nullptr, s);
-    if (tape_steps > 0) {
+    const bool full_tape = every == 1;
+    if (every >= 1) {
         // tape[0] = X~_0
-        spamm_bsm& t = w.tape[0];
-        HIP_TRY(hipMemcpyAsync(t.nslot, X0.nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(t.brow, X0.brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(t.bcol, X0.bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(t.map, X0.map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(t.val, X0.val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(t.norm, X0.norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(t.sq, X0.sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(t.sqlo, X0.sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        const int rcc = copy_mat(w.tape[0], w.X[0], cap, s);
+        if (rcc) return rcc;
     }
 
     const double tb_scale = p->variant == 0 ? 0.5 : 1.0;
@@ -934,8 +945,8 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     } else {
         std::vector<double> e_hist;
         for (int it = 1;; ++it) {
-            spamm_bsm* Xc = tape_steps > 0 ? &w.tape[it - 1] : &w.X[cur];
-            spamm_bsm* Xn = tape_steps > 0 ? (it <= tape_steps ? &w.tape[it] : nullptr) : &w.X[1 - cur];
+            spamm_bsm* Xc = full_tape ? &w.tape[it - 1] : &w.X[cur];
+            spamm_bsm* Xn = full_tape ? (it <= tape_steps ? &w.tape[it] : nullptr) : &w.X[1 - cur];
             MatView xv = view(Xc);
             launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
                           w.trace_out, nullptr, s);
@@ -1013,20 +1024,18 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
             const int rc_step = enqueue_step(xv, view(Xn), nullptr, ev, s);
             if (rc_step != SPAMM_OK) return rc_step;
+            if (every > 1 && it % every == 0 && it / every <= tape_steps) {
+                const int rcc = copy_mat(w.tape[it / every], *Xn, cap, s);  // checkpoint X~_it
+                if (rcc) return rcc;
+            }
             cur = 1 - cur;
         }
     }
     // final: copy the last iterate into D
     if (status >= 0) {
-        spamm_bsm* Xf = tape_steps > 0 ? &w.tape[nlog - 1] : &w.X[cur];
-        HIP_TRY(hipMemcpyAsync(D->nslot, Xf->nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D->brow, Xf->brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D->bcol, Xf->bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D->map, Xf->map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D->val, Xf->val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D->norm, Xf->norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D->sq, Xf->sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D->sqlo, Xf->sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        spamm_bsm* Xf = full_tape ? &w.tape[nlog - 1] : &w.X[cur];
+        const int rcc = copy_mat(*D, *Xf, cap, s);
+        if (rcc) return rcc;
         HIP_TRY(hipStreamSynchronize(s));
     }
     *nlog_out = nlog;
@@ -1079,25 +1088,74 @@ int spamm_adjoint_step(const spamm_bsm* X, const spamm_bsm* G, double tau, int32
     return SPAMM_OK;
 }
 
-size_t purify_sp2_adjoint_workspace_bytes(int32_t nb, int32_t b, int64_t cap_blocks, int64_t max_pairs) {
-    if (nb < 1 || cap_blocks < 1 || max_pairs < 0) return 0;
+}  // extern "C"
+
+namespace {
+
+// workspace of the whole-run adjoint: two gradient buffers, the Gerschgorin
+// scratch, one reverse step, and with checkpoints (tape_every > 1) the
+// buffers and scratch of the forward recomputation of one segment
+struct AdjRunWs {
+    double* gbuf[2];
+    double* rowtmp;
+    double* lam;
+    AdjWs aw;
+    std::vector<spamm_bsm> seg;
+    MulWs mw;
+    uint8_t* fromc;
+    void* trunc_tmp;
+    int64_t* tstats;
+    Sp2Ctl* ctl;
+};
+
+void carve_adj_run(Carver& c, int nb, int b, int64_t cap, int64_t max_pairs, int every, AdjRunWs& w) {
+    w.gbuf[0] = c.take<double>((size_t)cap * b * b);
+    w.gbuf[1] = c.take<double>((size_t)cap * b * b);
+    w.rowtmp = c.take<double>(2 * (size_t)nb * b);
+    w.lam = c.take<double>(2);
+    carve_adj(c, nb, cap, max_pairs, w.aw);
+    w.seg.clear();
+    if (every > 1) {
+        w.seg.resize(every - 1);
+        for (auto& m : w.seg) carve_mat(c, (int64_t)nb * b, b, cap, m);
+        carve_mul(c, nb, max_pairs, w.mw);
+        w.fromc = c.take<uint8_t>(cap);
+        w.trunc_tmp = c.take<char>(trunc_temp_bytes(cap));
+        w.tstats = c.take<int64_t>(4);
+        w.ctl = c.take<Sp2Ctl>(1);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t purify_sp2_adjoint_workspace_bytes(int32_t nb, int32_t b, int64_t cap_blocks, int64_t max_pairs,
+                                          int32_t tape_every) {
+    if (nb < 1 || cap_blocks < 1 || max_pairs < 0 || tape_every < 1) return 0;
     Carver c(nullptr);
-    c.take<double>((size_t)cap_blocks * b * b);
-    c.take<double>((size_t)cap_blocks * b * b);
-    c.take<double>(2 * (size_t)nb * b);
-    c.take<double>(2);
-    AdjWs w;
-    carve_adj(c, nb, cap_blocks, max_pairs, w);
+    AdjRunWs w;
+    carve_adj_run(c, nb, b, cap_blocks, max_pairs, tape_every, w);
     return c.off + 256;
 }
 
-int purify_sp2_adjoint(const spamm_bsm* F, const spamm_bsm* tape, int32_t ntape, const sp2_iter_log* log,
-                       int32_t nlog, const double* dbar_val, double* fbar_val, void* ws, size_t ws_bytes,
-                       spamm_stream_t stream) {
+int purify_sp2_adjoint(const spamm_bsm* F, const sp2_params* p, const spamm_bsm* tape, int32_t ntape,
+                       int32_t tape_every, const spamm_bsm* D, const sp2_iter_log* log, int32_t nlog,
+                       const double* dbar_val, double* fbar_val, void* ws, size_t ws_bytes, spamm_stream_t stream) {
     int rc = check_bsm(F, "F", false);
     if (rc) return rc;
-    if (!tape || ntape < 1 || !log || !dbar_val || !fbar_val) return fail(SPAMM_EINVAL, "NULL or empty argument");
-    if (nlog != ntape) return fail(SPAMM_EINVAL, "a run with %d tape entries has %d log records, not %d", ntape, ntape, nlog);
+    if (!p || !tape || ntape < 1 || !log || nlog < 1 || !dbar_val || !fbar_val)
+        return fail(SPAMM_EINVAL, "NULL or empty argument");
+    if (tape_every < 1) return fail(SPAMM_EINVAL, "tape_every must be >= 1");
+    const int T = nlog - 1;  // steps of the recorded run
+    const int every = tape_every;
+    if (every == 1 && ntape != nlog)
+        return fail(SPAMM_EINVAL, "a full tape of a run with %d records has %d entries, not %d", nlog, nlog, ntape);
+    if (every > 1 && ntape < T / every + 1)
+        return fail(SPAMM_EINVAL, "%d checkpoints every %d steps do not cover %d steps", ntape, every, T);
+    if (every > 1 && !D) return fail(SPAMM_EINVAL, "D is required with checkpoints");
+    if (every > 1 && p->precision != 0)
+        return fail(SPAMM_ENOTSUP, "recomputation from checkpoints supports FP64 runs (use a full tape)");
     const int nb = F->nb, b = F->b;
     int64_t cap = 0;
     for (int t = 0; t < ntape; ++t) {
@@ -1107,42 +1165,90 @@ int purify_sp2_adjoint(const spamm_bsm* F, const spamm_bsm* tape, int32_t ntape,
         if (tape[t].nb != nb || tape[t].b != b) return fail(SPAMM_EINVAL, "tape entry %d does not match F", t);
         cap = std::max<int64_t>(cap, tape[t].cap);
     }
-    for (int t = 1; t < ntape; ++t)
+    if (D) {
+        rc = check_bsm(D, "D", true);
+        if (rc) return rc;
+        if (D->nb != nb || D->b != b || D->cap > cap) return fail(SPAMM_EINVAL, "D does not match the tape");
+    }
+    for (int t = 1; t <= T; ++t)
         if (log[t - 1].branch != 0 && log[t - 1].branch != 1)
             return fail(SPAMM_EINVAL, "log record %d is not a step", t - 1);
-    const size_t base = purify_sp2_adjoint_workspace_bytes(nb, b, cap, 0);
+    const size_t base = purify_sp2_adjoint_workspace_bytes(nb, b, cap, 0, every);
     if (!ws || ws_bytes < base + 512) return fail(SPAMM_EWORKSPACE, "adjoint needs more than %zu workspace bytes", base);
-    const int64_t max_pairs = (int64_t)((ws_bytes - base - 512) / sizeof(int2));
+    // the pair lists of the reverse step and (with checkpoints) of the
+    // recomputation share what is left of the workspace
+    const int64_t per_pair = every > 1 ? 2 * (int64_t)sizeof(int2) : (int64_t)sizeof(int2);
+    const int64_t max_pairs = (int64_t)((ws_bytes - base - 512) / per_pair);
     if (max_pairs >= ((int64_t)1 << 31)) return fail(SPAMM_EINVAL, "pair capacity must stay below 2^31");
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
-    double* gbuf[2];
-    gbuf[0] = c.take<double>((size_t)cap * b * b);
-    gbuf[1] = c.take<double>((size_t)cap * b * b);
-    double* rowtmp = c.take<double>(2 * (size_t)nb * b);
-    double* lam = c.take<double>(2);
-    AdjWs w;
-    carve_adj(c, nb, cap, max_pairs, w);
+    AdjRunWs w;
+    carve_adj_run(c, nb, b, cap, max_pairs, every, w);
     if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
+    const double tb_scale = p->variant == 0 ? 0.5 : 1.0;
 
-    fill_i32(w.ovf, 1, 0, s);
+    fill_i32(w.aw.ovf, 1, 0, s);
+    if (every > 1) fill_i32(w.mw.ovf, 1, 0, s);
+    // X~_t of the recorded run: tape entry, recomputed segment buffer, or D
+    int seg0 = -1;  // first step of the segment held in w.seg (X~_{seg0+1} ..)
+    auto iterate = [&](int t) -> const spamm_bsm* {
+        if (every == 1) return &tape[t];
+        if (t == T) return D;
+        if (t % every == 0) return &tape[t / every];
+        return &w.seg[t - seg0 - 1];
+    };
+    // recompute X~_{t0+1} .. X~_{t1-1} from the checkpoint X~_{t0} with the
+    // recorded decisions: the forward's own kernels, so bit-identical
+    auto recompute = [&](int t0, int t1) -> int {
+        seg0 = t0;
+        for (int t = t0 + 1; t < t1; ++t) {
+            const spamm_bsm* Xc = (t - 1 == t0) ? &tape[t0 / every] : &w.seg[t - 1 - t0 - 1];
+            const spamm_bsm* Xn = &w.seg[t - t0 - 1];
+            Sp2Ctl hc;
+            memset(&hc, 0, sizeof(hc));
+            hc.tau = log[t - 1].tau;
+            hc.branch = log[t - 1].branch;
+            hc.delta = log[t - 1].delta;
+            HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+            MatView xv = view(Xc), nv = view(Xn);
+            run_pairs(xv, xv, 1, 1, &w.ctl->tau, nullptr, nv, w.fromc, w.mw, xv.map, &w.ctl->branch, nullptr, s);
+            run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, nullptr, s);
+            launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, s);
+            if (p->variant != 1)
+                launch_truncate(nv, &w.ctl->delta, 0.0, tb_scale, w.trunc_tmp, cap, w.tstats, w.mw.ovf, nullptr, s);
+            // the host copy of hc must outlive the enqueued copy
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        return SPAMM_OK;
+    };
+
     // gradient of the last iterate, symmetrised
-    launch_sym_half(view(&tape[ntape - 1]), dbar_val, gbuf[0], s);
+    launch_sym_half(view(iterate(T)), dbar_val, w.gbuf[0], s);
     int cur = 0;
-    for (int t = ntape - 1; t >= 1; --t) {
-        MatView gv = view(&tape[t]);
-        gv.val = gbuf[cur];
-        run_adjoint_step(view(&tape[t - 1]), gv, log[t - 1].tau, log[t - 1].branch, gbuf[1 - cur], w, s);
-        cur = 1 - cur;
+    int t = T;
+    while (t >= 1) {
+        // segment [t0, t]: t0 the checkpoint at or below t - 1
+        const int t0 = every == 1 ? t - 1 : ((t - 1) / every) * every;
+        if (every > 1) {
+            rc = recompute(t0, t);
+            if (rc) return rc;
+        }
+        for (; t > t0; --t) {
+            MatView gv = view(iterate(t));
+            gv.val = w.gbuf[cur];
+            run_adjoint_step(view(iterate(t - 1)), gv, log[t - 1].tau, log[t - 1].branch, w.gbuf[1 - cur], w.aw, s);
+            cur = 1 - cur;
+        }
     }
     // X~_0 = mask((lmax I - F) / (lmax - lmin)) with the same bounds as the forward run
-    launch_gersch(view(F), rowtmp, lam, s);
-    launch_adj_fbar(view(F), tape[0].map, gbuf[cur], lam, fbar_val, s);
-    int32_t ovf = 0;
-    HIP_TRY(hipMemcpyAsync(&ovf, w.ovf, sizeof(ovf), hipMemcpyDeviceToHost, s));
+    launch_gersch(view(F), w.rowtmp, w.lam, s);
+    launch_adj_fbar(view(F), tape[0].map, w.gbuf[cur], w.lam, fbar_val, s);
+    int32_t ovf[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&ovf[0], w.aw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (every > 1) HIP_TRY(hipMemcpyAsync(&ovf[1], w.mw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipGetLastError());
-    if (ovf) return fail(SPAMM_ECAPACITY, "adjoint pair list exceeded %lld pairs", (long long)max_pairs);
+    if (ovf[0] || ovf[1]) return fail(SPAMM_ECAPACITY, "adjoint pair list exceeded %lld pairs", (long long)max_pairs);
     return SPAMM_OK;
 }
 
