@@ -53,7 +53,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision purification")
     ap.add_argument("--graph", type=int, default=8,
                     help="also time the graph-captured loop, polling every K iterations (0: skip)")
-    ap.add_argument("--adjoint", action="store_true", help="also time the reverse mode (tape + adjoint)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the reverse mode on the n = 32768 system with a banded W (checkpointed tape)")
     ap.add_argument("--batch", type=int, default=0,
                     help="also time the batched workload: the first N of the 64 systems (sizes log-uniform in "
                          "[2048, 32768], seed 4), leaf sizes by the autotuner")
@@ -164,27 +165,10 @@ def main():
                              "speedup_vs_host_loop": round(float(np.median(times)) / float(np.median(gtimes)), 4),
                              "same_decisions": bool(same)}
 
-    # reverse mode: forward with a tape, then the adjoint of a random loss
+    # reverse mode at n = 32768 with a banded W (checkpointed tape)
     if args.adjoint:
-        live_max = max(l["nslot_hat"] for l in steps) + nb
-        capt = int(min(cap, live_max * 1.1 + 64))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rt = run_once(keep_tape=True, cap_=capt)
-        torch.cuda.synchronize()
-        t_fwd = time.perf_counter() - t0
-        g = torch.Generator(device=dev).manual_seed(0)
-        dbar = torch.randn(capt * b * b, dtype=torch.float64, device=dev, generator=g)
-        P.purify_adjoint(rt, F, dbar)   # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        P.purify_adjoint(rt, F, dbar)
-        torch.cuda.synchronize()
-        t_adj = time.perf_counter() - t0
-        log(f"adjoint: forward with tape {t_fwd:.3f} s, adjoint {t_adj:.3f} s")
-        out["adjoint"] = {"forward_with_tape_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
-                          "tape_entries": rt.nlog, "cap_blocks": capt}
-        del rt, dbar
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_leg(dev, P, synth, torch)
 
     # mixed precision (FP32 and split-BF16 leaf-product tiers) on the same workload
     res_mixed = {}
@@ -290,6 +274,94 @@ def measured_traffic(n, b, seed):
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def adjoint_leg(dev, P, synth, torch):
+    """Reverse mode of the purification of the 3D system n = 32768 (seed 5,
+    leaf 64) for L = <D~, W>, W symmetric banded (bandwidth 64, N(0,1)
+    entries, seed 55): forward with checkpoints every 8 iterates, then
+    purify_sp2_adjoint (segments recomputed).  Without a dense spectrum at
+    this size the per-step delta is a constant (1e-9).  Checked against
+    central differences of L along a random symmetric direction H on F's
+    pattern, with the perturbed runs' decisions compared to the base run's
+    (equal decisions: the frozen map is the map that ran)."""
+    n, b, seed, every, nmax = 32768, 64, 5, 8, 60
+    taus = synth.tau_log(32)
+    eps, dconst = 1e-6, 1e-9
+    t0 = time.perf_counter()
+    Fh = synth.sys3d(n, seed, b)
+    Wh = synth.band_w(n, b, 64, 55)
+    Uh = synth.symmetric_direction(n, b, Fh, 7)
+    log(f"adjoint: inputs n={n} generated in {time.perf_counter() - t0:.1f} s")
+    F = P.BlockSparse.from_host(Fh)
+    W = P.BlockSparse.from_host(Wh)
+    # relative direction H = F * U (U symmetric, entries in (-1, 1)): zeros
+    # stay zero and tiny entries move by tiny amounts, so the run's
+    # decisions can stay those of the base run
+    H = (torch.from_numpy(np.ascontiguousarray(Uh.vals).reshape(-1)).to(dev) *
+         torch.from_numpy(np.ascontiguousarray(Fh.vals).reshape(-1)).to(dev))
+    nb = F.nb
+    kw = dict(delta_const=dconst, n_max=nmax)
+
+    def loss_and_dbar(D):
+        cap = D.cap
+        nsl = int(D.nslot.item())
+        brow = D.brow.long()
+        bcol = D.bcol.long()
+        live = (torch.arange(cap, device=dev) < nsl) & (brow >= 0)
+        key = torch.where(live, brow * nb + bcol, torch.zeros_like(brow))
+        ws_ = torch.where(live, W.map.long()[key], torch.full_like(brow, -1))
+        Dv = D.val.view(cap, b * b)
+        dbar = torch.zeros_like(Dv)
+        m = ws_ >= 0
+        dbar[m] = W.val.view(-1, b * b)[ws_[m]]
+        return float((Dv * dbar).sum().item()), dbar.view(-1)
+
+    P.purify(F, n // 2, eps, taus, **kw)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = P.purify(F, n // 2, eps, taus, keep_tape=every, **kw)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    L0, dbar = loss_and_dbar(res.D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fbar = P.purify_adjoint(res, F, dbar)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    got = float((fbar * H).sum().item())
+    base = [(l["branch"], l["idx"], l["npairs"], l["nslot_kept"], l["removed_units"]) for l in res.logs]
+    steps = sum(1 for l in res.logs if l["branch"] >= 0)
+    status = res.status
+    pairs = sum(l["npairs"] for l in res.logs if l["branch"] >= 0)
+    log(f"adjoint: {steps} steps, forward with checkpoints {t_fwd:.3f} s, adjoint {t_adj:.3f} s")
+    del res, dbar
+    torch.cuda.empty_cache()
+    fd = {}
+    for h in (1e-5, 1e-6):
+        vals, ndiff, maxdp, nrec = [], 0, 0, []
+        for sgn in (1.0, -1.0):
+            Fp = P.with_values(F, F.val + sgn * h * H)
+            rp = P.purify(Fp, n // 2, eps, taus, **kw)
+            mine = [(l["branch"], l["idx"], l["npairs"], l["nslot_kept"], l["removed_units"]) for l in rp.logs]
+            nrec.append(len(mine))
+            for a, c in zip(base, mine):
+                if a != c:
+                    ndiff += 1
+                    maxdp = max(maxdp, abs(a[2] - c[2]))
+            vals.append(loss_and_dbar(rp.D)[0])
+            del rp, Fp
+        d = (vals[0] - vals[1]) / (2.0 * h)
+        fd[str(h)] = {"fd": d, "rel_diff": abs(d - got) / max(abs(d), 1e-300),
+                      "records_base_plus_minus": [len(base)] + nrec,
+                      "steps_with_other_decisions": ndiff, "max_kept_pair_difference": maxdp}
+        log(f"adjoint: h={h:g} central difference {d:.9e} vs <Fbar, H> {got:.9e}; records {len(base)} vs {nrec}, "
+            f"{ndiff} common steps with other decisions (kept pairs differ by at most {maxdp})")
+    return {"workload": f"sys3d_n{n}_s{seed}_leaf{b}_bandW64", "steps": steps, "status": int(status),
+            "kept_pairs_forward": int(pairs),
+            "checkpoint_every": every, "delta_const": dconst, "loss": L0,
+            "forward_with_checkpoints_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
+            "directional_derivative": got, "central_differences": fd}
 
 
 def _gen_leaf32(arg):
