@@ -461,6 +461,7 @@ class SP2Params:
     e_tol: float = 0.0
     precision: int = 0            # 1: FP32 tier, 2: split-BF16 tier, for tau <= p < sigma (rounding folded into the bound)
     tier_split: float = 0.5       # share of the product budget given to skipping when tiered
+    bound: str = "tree"           # "tree": Algorithm 3's recursive bound; "flat" / "sum": leaf-level eq. (6) / plain sum
 
 
 @dataclass
@@ -540,7 +541,13 @@ def sp2_step(X: BSM, st: SP2State, p: SP2Params):
         bound, idx, tau = np.zeros(len(taus)), len(taus), 0.0
     else:
         skip_budget = p.tier_split * budget if p.precision else budget
-        bound = cse_tree(X, X, taus, nu, nu)
+        if p.bound == "tree":
+            bound = cse_tree(X, X, taus, nu, nu)
+        else:
+            if p.precision:
+                raise ValueError("the precision tiers select with the recursive bound")
+            flat, ssum = cse_flat_sum(X, X, taus, nu, nu)
+            bound = flat if p.bound == "flat" else ssum
         idx, tau = select(bound, taus, skip_budget)
     sidx, sigma, nlow = len(taus), 0.0, 0
     if p.precision:

@@ -123,3 +123,46 @@ def test_tier_selection_converges(precision):
     assert any(l.npairs_low > 0 for l in steps)
     assert all(l.sigma == 0.0 or l.sigma > l.tau for l in steps if l.npairs_low > 0)
     assert np.linalg.norm(D.to_dense() - Dref) < 1e-6
+
+
+@pytest.mark.parametrize("bound", ["flat", "sum"])
+def test_leaf_bounds_step_conditions(bound):
+    """Selection with the leaf-level bounds (eq. (6) at the leaves, or the
+    plain sum of skipped products): both still bound the product error, so
+    both Algorithm 5 conditions hold at every step and the run converges;
+    on the same iterate, B_flat <= B_tree <= B_sum orders the selected
+    indices idx_flat <= idx_tree <= idx_sum (a smaller bound admits a larger
+    threshold)."""
+    n, b = 768, 32
+    F = oracle.BSM.of(synth.sys3d(n, 7, b))
+    n_occ = n // 2
+    Dref, w = eigh_density(F, n_occ)
+    taus = synth.tau_log(32)
+    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=taus, homo=w[n_occ - 1], lumo=w[n_occ], bound=bound)
+    X, X0, st, _ = oracle.sp2_start(F, p)
+    strict = 0
+    while True:
+        Xn, Xh, log, st = oracle.sp2_step(X, st, p)
+        if Xn is None:
+            break
+        Xd = X.to_dense()
+        f = Xd @ Xd if log.branch == 0 else 2 * Xd - Xd @ Xd
+        assert np.linalg.norm(Xh.to_dense() - f) < log.delta / 2
+        assert np.linalg.norm(Xn.to_dense() - Xh.to_dense()) < log.delta / 2
+        nu = oracle.norms(X)[1]
+        tree = oracle.cse_tree(X, X, taus, nu, nu)
+        flat, ssum = oracle.cse_flat_sum(X, X, taus, nu, nu)
+        assert np.array_equal(log.bound, flat if bound == "flat" else ssum)
+        i_tree = oracle.select(tree, taus, log.delta / 2)[0]
+        i_flat = oracle.select(flat, taus, log.delta / 2)[0]
+        i_sum = oracle.select(ssum, taus, log.delta / 2)[0]
+        assert i_flat <= i_tree <= i_sum
+        assert log.idx == (i_flat if bound == "flat" else i_sum)
+        strict += int(i_flat < i_sum)
+        X = Xn
+    assert strict > 0
+    assert np.linalg.norm(X.to_dense() - Dref) < 1e-6
+    with pytest.raises(ValueError):
+        oracle.sp2_step(X0, oracle.sp2_start(F, p)[2],
+                        oracle.SP2Params(n_occ=n_occ, taus=taus, homo=w[n_occ - 1], lumo=w[n_occ], bound=bound,
+                                         precision=1))
