@@ -53,6 +53,9 @@ extern "C" {
 #define SPAMM_SYMMETRIC 1u   /* A = B = X symmetric: outputs i <= j, C_ji = C_ij^T */
 #define SPAMM_B_TRANSPOSED 2u /* B is given as its transpose Bt (Bt_jk = B_kj^T) */
 #define SPAMM_SYNC 4u        /* synchronise the stream before returning */
+#define SPAMM_BOUND_FLAT 16u  /* spamm_sweep_tau: B_flat = sqrt(sum_ij (sum_{k skipped} p_ikj)^2) (eq. (6) at the
+                                 leaves) instead of Algorithm 3's recursive bound */
+#define SPAMM_BOUND_SUM 32u   /* spamm_sweep_tau: B_sum = sum of the skipped p_ikj */
 #define SPAMM_TIER_BF16 8u   /* spamm_multiply_tiered: low-tier pairs as split-BF16 products (needs
                                 SPAMM_B_TRANSPOSED); default: FP32 products */
 
@@ -94,6 +97,13 @@ int spamm_build_norms(spamm_bsm* X, spamm_stream_t stream);
  *   mode      : 0 = the paper's leaf errors; 1 = precision tiers (tau is the
  *               list of low-precision limits sigma, tau0_dev[0] the fixed skip
  *               threshold, c_low the per-pair rounding factor of the low tier).
+ *   flags     : SPAMM_B_TRANSPOSED, SPAMM_SYNC, and at most one of
+ *               SPAMM_BOUND_FLAT / SPAMM_BOUND_SUM to replace Algorithm 3's
+ *               recursive bound by a leaf-level one (mode 0 only; both flags
+ *               -> SPAMM_EINVAL).  B_flat <= B_tree <= B_sum, and all three
+ *               bound the product error, so FLAT admits the largest threshold.
+ *               The leaf-level bounds add their per-output sums in a fixed
+ *               order and are deterministic.
  *   bound_out : device [N] bound of ||SpAMM(A,B,tau_k) - AB||_F per candidate.
  *   idx_out   : device [1] selected index (N when none qualifies).
  *   tau_out   : device [1] selected threshold (0 when none qualifies).
@@ -184,7 +194,8 @@ typedef struct sp2_params {
                             captured once as a HIP graph with its decisions taken on the device
                             and replayed, the host polling the stop flag every K iterations
                             (requires keep_tape == 0; phase timings are 0) */
-    int32_t pad_;
+    int32_t bound_kind;  /* threshold selection: 0 Algorithm 3 (B_tree), 1 B_flat, 2 B_sum (see
+                            SPAMM_BOUND_FLAT / SPAMM_BOUND_SUM); the precision tiers need 0 */
 } sp2_params;
 
 /* Per-iteration record written by purify_sp2 (host memory). */

@@ -33,9 +33,12 @@ SYMMETRIC = 1
 B_TRANSPOSED = 2
 SYNC = 4
 TIER_BF16 = 8
+BOUND_FLAT = 16
+BOUND_SUM = 32
 
 VARIANTS = {"hybrid": 0, "spamm": 1, "truncmul": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+BOUNDS = {"tree": 0, "flat": 1, "sum": 2}
 
 
 class SpammError(RuntimeError):
@@ -56,7 +59,7 @@ class sp2_params(ctypes.Structure):
                 ("variant", ctypes.c_int32), ("tau", ctypes.c_void_p), ("N", ctypes.c_int32),
                 ("homo", ctypes.c_double), ("lumo", ctypes.c_double), ("delta_const", ctypes.c_double),
                 ("e_tol", ctypes.c_double), ("keep_tape", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("tier_split", ctypes.c_double), ("graph_steps", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("tier_split", ctypes.c_double), ("graph_steps", ctypes.c_int32), ("bound_kind", ctypes.c_int32)]
 
 
 class sp2_iter_log(ctypes.Structure):
@@ -305,9 +308,11 @@ def build_norms(X: BlockSparse) -> None:
 
 
 def sweep_tau(A: BlockSparse, B: BlockSparse, taus, budget, b_transposed=False, mode=0, tau0=None, c_low=0.0,
-              sync=False):
-    """Error bound of SpAMM(A, B, tau_k) for every candidate (Algorithm 3) and
-    the selected candidate.  Returns device tensors (bound[N], idx[1], tau[1])."""
+              sync=False, bound="tree"):
+    """Error bound of SpAMM(A, B, tau_k) for every candidate (Algorithm 3's
+    recursive bound, or the leaf-level "flat" / "sum" bounds) and the
+    selected candidate.  Returns device tensors (bound[N], idx[1], tau[1])."""
+    kind_flag = {0: 0, 1: BOUND_FLAT, 2: BOUND_SUM}[BOUNDS[bound]]
     dev = A.device
     taus = torch.as_tensor(taus, dtype=torch.float64, device=dev).contiguous()
     N = int(taus.shape[0])
@@ -317,7 +322,7 @@ def sweep_tau(A: BlockSparse, B: BlockSparse, taus, budget, b_transposed=False, 
     ws = _ws(lib().spamm_sweep_workspace_bytes(A.nb, N), dev)
     bdev = budget if isinstance(budget, torch.Tensor) else None
     t0 = torch.as_tensor([tau0 if tau0 is not None else 0.0], dtype=torch.float64, device=dev)
-    flags = (B_TRANSPOSED if b_transposed else 0) | (SYNC if sync else 0)
+    flags = (B_TRANSPOSED if b_transposed else 0) | (SYNC if sync else 0) | kind_flag
     _check(lib().spamm_sweep_tau(ctypes.byref(A.struct()), ctypes.byref(B.struct()), _ptr(taus), N,
                                  _ptr(bdev) if bdev is not None else None,
                                  float(budget) if bdev is None else 0.0, int(mode), _ptr(t0), float(c_low), flags,
@@ -406,7 +411,7 @@ class PurifyResult:
 
 def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo=float("nan"),
            variant="hybrid", n_max=60, delta_const=float("nan"), e_tol=0.0, cap=None, max_pairs=None,
-           keep_tape=False, precision="fp64", tier_split=0.5, graph_steps=0) -> PurifyResult:
+           keep_tape=False, precision="fp64", tier_split=0.5, graph_steps=0, bound="tree") -> PurifyResult:
     """SP2 purification with SpAMM and error control (Algorithms 1, 4, 5).
     graph_steps > 0: the step runs as a replayed HIP graph with its
     decisions taken on the device, the host polling every graph_steps
@@ -428,7 +433,7 @@ def purify(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo
     D = BlockSparse(F.n, b, cap, dev)
     p = sp2_params(int(n_occ), float(eps), int(n_max), VARIANTS[variant], taus.data_ptr(), N, float(homo),
                    float(lumo), float(delta_const), float(e_tol), every, prec, float(tier_split),
-                   int(graph_steps), 0)
+                   int(graph_steps), BOUNDS[bound])
     logs = (sp2_iter_log * (n_max + 2))()
     nlog = ctypes.c_int32(0)
     rc = lib().purify_sp2(ctypes.byref(F.struct()), ctypes.byref(p), ctypes.byref(D.struct()), logs,
@@ -449,7 +454,7 @@ class BatchResult:
 
 def purify_batched(Fs, n_occ, eps, taus, homo, lumo, variant="hybrid", n_max=60, delta_const=float("nan"),
                    e_tol=0.0, caps=None, max_pairs=None, precision="fp64", tier_split=0.5, graph_steps=8,
-                   raise_on_error=True) -> BatchResult:
+                   raise_on_error=True, bound="tree") -> BatchResult:
     """Purify independent systems together (purify_sp2_batched): per step one
     persistent product launch for all systems of a leaf size and tier.
     Per-system arguments (n_occ, homo, lumo, taus, variant, precision,
@@ -459,6 +464,7 @@ def purify_batched(Fs, n_occ, eps, taus, homo, lumo, variant="hybrid", n_max=60,
     def per(v):
         return list(v) if isinstance(v, (list, tuple)) else [v] * ns
     n_occ, homo, lumo, variant, precision = per(n_occ), per(homo), per(lumo), per(variant), per(precision)
+    bound = per(bound)
     taus_l = taus if isinstance(taus, (list, tuple)) else [taus] * ns
     dev = Fs[0].device
     tt = [torch.as_tensor(t, dtype=torch.float64, device=dev).contiguous() for t in taus_l]
@@ -471,7 +477,7 @@ def purify_batched(Fs, n_occ, eps, taus, homo, lumo, variant="hybrid", n_max=60,
     for q in range(ns):
         pa[q] = sp2_params(int(n_occ[q]), float(eps), int(n_max), VARIANTS[variant[q]], tt[q].data_ptr(),
                            int(tt[q].shape[0]), float(homo[q]), float(lumo[q]), float(delta_const), float(e_tol), 0,
-                           PRECISIONS[precision[q]], float(tier_split), int(graph_steps), 0)
+                           PRECISIONS[precision[q]], float(tier_split), int(graph_steps), BOUNDS[bound[q]])
     capa = (ctypes.c_int64 * ns)(*[int(c) for c in caps])
     mpa = (ctypes.c_int64 * ns)(*[int(m) for m in mps])
     need = lib().purify_sp2_batched_workspace_bytes(ns, Fa, pa, capa, mpa)

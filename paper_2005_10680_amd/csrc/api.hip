@@ -107,6 +107,12 @@ struct SweepWs {
     int64_t* cnt;  // [4]
     int32_t* ovf;
     void* scan_tmp;
+    // leaf-level bounds (B_flat, B_sum)
+    int nw;
+    uint32_t *bitsA, *bitsB;
+    double* part;   // per-wave partial sums [waves][N]
+    double* bleaf;  // [N]
+    int64_t* one;
 };
 
 void carve_sweep(Carver& c, int nb, int N, SweepWs& w) {
@@ -129,6 +135,28 @@ void carve_sweep(Carver& c, int nb, int N, SweepWs& w) {
     w.cnt = c.take<int64_t>(4);
     w.ovf = c.take<int32_t>(4);
     w.scan_tmp = c.take<char>(scan_temp_bytes(w.ncap));
+    w.nw = (nb + 31) / 32;
+    w.bitsA = c.take<uint32_t>((size_t)nb * w.nw);
+    w.bitsB = c.take<uint32_t>((size_t)nb * w.nw);
+    w.part = c.take<double>((size_t)bound_part_waves(nb) * N);
+    w.bleaf = c.take<double>(N);
+    w.one = c.take<int64_t>(1);
+}
+
+// The leaf-level bounds B_flat (kind 1) or B_sum (kind 2) for every
+// candidate, then the selection rule.
+void run_sweep_leaf(const MatView& A, const MatView& B, int btrans, const double* tau, int N,
+                    const double* budget_dev, double budget_host, int kind, double* bound_out, int32_t* idx_out,
+                    double* tau_out, SweepWs& w, const int32_t* done, hipStream_t s) {
+    const int nb = A.nb;
+    fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
+    fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
+    launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
+    launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
+    launch_bound_leaf(nb, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, tau, N, kind == 1 ? 1 : 0,
+                      w.part, w.bleaf, done, s);
+    fill_i64(w.one, 1, 1, s);
+    launch_select(w.bleaf, w.one, tau, N, budget_dev, budget_host, bound_out, idx_out, tau_out, done, s);
 }
 
 void run_sweep(const MatView& A, const MatView& B, int btrans, const double* tau, int N, const double* budget_dev,
@@ -424,6 +452,9 @@ int check_sp2(const spamm_bsm* F, const sp2_params* p, const spamm_bsm* D) {
     if (p->graph_steps < 0) return fail(SPAMM_EINVAL, "graph_steps must be >= 0");
     if (p->graph_steps > 0 && p->keep_tape) return fail(SPAMM_EINVAL, "graph mode needs keep_tape = 0");
     if (p->keep_tape < 0 || p->keep_tape > p->n_max) return fail(SPAMM_EINVAL, "keep_tape must be in 0..n_max");
+    if (p->bound_kind < 0 || p->bound_kind > 2) return fail(SPAMM_EINVAL, "bound_kind must be 0, 1 or 2");
+    if (p->bound_kind != 0 && p->precision != 0)
+        return fail(SPAMM_ENOTSUP, "the precision tiers select with Algorithm 3's bound (bound_kind 0)");
     if (p->precision != 0 && F->b > 64) return fail(SPAMM_ENOTSUP, "the precision tiers support leaf 32 and 64");
     if (p->precision != 0 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
         return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
@@ -554,6 +585,10 @@ int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, i
     if (!tau || !idx_out || !tau_out) return fail(SPAMM_EINVAL, "NULL output");
     if (mode == 1 && !tau0_dev) return fail(SPAMM_EINVAL, "mode 1 needs tau0");
     if (mode != 0 && mode != 1) return fail(SPAMM_EINVAL, "mode must be 0 or 1");
+    const int kind = (flags & SPAMM_BOUND_FLAT) ? 1 : ((flags & SPAMM_BOUND_SUM) ? 2 : 0);
+    if ((flags & SPAMM_BOUND_FLAT) && (flags & SPAMM_BOUND_SUM))
+        return fail(SPAMM_EINVAL, "choose one of SPAMM_BOUND_FLAT and SPAMM_BOUND_SUM");
+    if (kind != 0 && mode != 0) return fail(SPAMM_EINVAL, "the leaf-level bounds have no tier mode");
     size_t need = spamm_sweep_workspace_bytes(A->nb, N);
     if (!ws || ws_bytes < need) return fail(SPAMM_EWORKSPACE, "sweep needs %zu workspace bytes", need);
     hipStream_t s = (hipStream_t)stream;
@@ -569,8 +604,12 @@ int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, i
     SweepWs w;
     carve_sweep(c, A->nb, N, w);
     fill_i32(w.ovf, 1, 0, s);
-    run_sweep(view(A), view(B), (flags & SPAMM_B_TRANSPOSED) ? 1 : 0, tau, N, budget, budget_host, mode, tau0_dev,
-              c_low, bound_out, idx_out, tau_out, w, nullptr, s);
+    if (kind != 0)
+        run_sweep_leaf(view(A), view(B), (flags & SPAMM_B_TRANSPOSED) ? 1 : 0, tau, N, budget, budget_host, kind,
+                       bound_out, idx_out, tau_out, w, nullptr, s);
+    else
+        run_sweep(view(A), view(B), (flags & SPAMM_B_TRANSPOSED) ? 1 : 0, tau, N, budget, budget_host, mode, tau0_dev,
+                  c_low, bound_out, idx_out, tau_out, w, nullptr, s);
     HIP_TRY(hipGetLastError());
     if (flags & SPAMM_SYNC) HIP_TRY(hipStreamSynchronize(s));
     return SPAMM_OK;
@@ -830,7 +869,10 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     auto enqueue_step = [&](const MatView& xv, const MatView& nv, const int32_t* done, hipEvent_t* evs,
                             hipStream_t st) -> int {
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
-        if (p->variant != 2)
+        if (p->variant != 2 && p->bound_kind != 0)
+            run_sweep_leaf(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, p->bound_kind, w.bound, &w.ctl->idx,
+                           &w.ctl->tau, w.sw, done, st);
+        else if (p->variant != 2)
             run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
                       &w.ctl->tau, w.sw, done, st);
         if (tiered) {
@@ -1473,7 +1515,10 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             const int32_t* done = &w.ctl->done;
             MatView xv = view(&w.X[par]);
             MatView nv = view(&w.X[1 - par]);
-            if (pq->variant != 2)
+            if (pq->variant != 2 && pq->bound_kind != 0)
+                run_sweep_leaf(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, pq->bound_kind, w.bound,
+                               &w.ctl->idx, &w.ctl->tau, w.sw, done, gg.cs);
+            else if (pq->variant != 2)
                 run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
                           &w.ctl->tau, w.sw, done, gg.cs);
             if (tiered) {

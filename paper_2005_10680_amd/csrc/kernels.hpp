@@ -29,6 +29,29 @@ void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const in
                    const double* val, const double* sq, const double* sqlo, double* temp, double* out,
                    const int32_t* done, hipStream_t s);
 
+// Row bitmaps of A (bit k of row i: A_ik present) and column bitmaps of B
+// (bit k of column j: B_kj present) turn the inner indices of output (i, j)
+// into a word AND.
+// Visit the kept inner indices of output (i, j) in ascending k.
+template <typename F>
+SPAMM_DEV void for_each_kept(int i, int j, int nb, int nw, const uint32_t* bitsA, const uint32_t* bitsB,
+                             const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB,
+                             int btrans, double tau, F&& f) {
+    for (int w = 0; w < nw; ++w) {
+        uint32_t m = bitsA[(size_t)i * nw + w] & bitsB[(size_t)j * nw + w];
+        while (m) {
+            int t = __ffs(m) - 1;
+            m &= m - 1;
+            int k = w * 32 + t;
+            int sa = mapA[(size_t)i * nb + k];
+            int sb = btrans ? mapB[(size_t)j * nb + k] : mapB[(size_t)k * nb + j];
+            if (sa < 0 || sb < 0) continue;
+            double p = normA[sa] * normB[sb];
+            if (p >= tau) f(k, sa, sb, p);
+        }
+    }
+}
+
 // pairs.hip
 enum OccMode { kOccA = 0, kOccB = 1, kOccBt = 2 };
 void launch_occupancy(const MatView& M, int mode, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0,
@@ -137,6 +160,13 @@ void launch_adj_pairs(int nb, int nw, int64_t cap_out, const int64_t* nout, cons
                       int64_t cap_pairs, int2* pairs, int32_t* ovf, void* scan_tmp, hipStream_t s);
 void launch_adj_fbar(const MatView& F, const int32_t* map0, const double* g0, const double* lam, double* fbar,
                      hipStream_t s);
+
+// bounds.hip: leaf-level bounds B_flat (flat = 1) / B_sum (flat = 0) for the N
+// candidates into out [N]; part holds bound_part_waves(nb) * N doubles
+int64_t bound_part_waves(int nb);
+void launch_bound_leaf(int nb, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
+                       const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
+                       int N, int flat, double* part, double* out, const int32_t* done, hipStream_t s);
 
 // control.hip
 void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,

@@ -39,25 +39,6 @@ void launch_occupancy(const MatView& M, int mode, uint32_t* bits, int nw, uint8_
                        l0, done);
 }
 
-// Visit the kept inner indices of output (i, j) in ascending k.
-template <typename F>
-SPAMM_DEV void for_each_kept(int i, int j, int nb, int nw, const uint32_t* bitsA, const uint32_t* bitsB,
-                             const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB,
-                             int btrans, double tau, F&& f) {
-    for (int w = 0; w < nw; ++w) {
-        uint32_t m = bitsA[(size_t)i * nw + w] & bitsB[(size_t)j * nw + w];
-        while (m) {
-            int t = __ffs(m) - 1;
-            m &= m - 1;
-            int k = w * 32 + t;
-            int sa = mapA[(size_t)i * nb + k];
-            int sb = btrans ? mapB[(size_t)j * nb + k] : mapB[(size_t)k * nb + j];
-            if (sa < 0 || sb < 0) continue;
-            double p = normA[sa] * normB[sb];
-            if (p >= tau) f(k, sa, sb, p);
-        }
-    }
-}
 
 __global__ void k_kept_count(int nb, int P, int nw, const uint32_t* __restrict__ bitsA,
                              const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
