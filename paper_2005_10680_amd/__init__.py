@@ -236,16 +236,35 @@ class BlockSparse:
         """Host copy of the live blocks, sorted row-major:
         (brow, bcol, vals[k, col, row], norm, sq, slots)."""
         torch.cuda.synchronize()
-        ns = int(_host(self.nslot)[0])
-        brow = _host(self.brow)[:ns]
-        bcol = _host(self.bcol)[:ns]
+        ns = min(int(_host(self.nslot)[0]), self.cap)
+        brow = _host(self.brow, ns)
+        bcol = _host(self.bcol, ns)
         keep = np.nonzero(brow >= 0)[0]
         key = brow[keep].astype(np.int64) * self.nb + bcol[keep]
         o = keep[np.argsort(key, kind="stable")]
         b = self.b
-        vals = _host(self.val)[: ns * b * b].reshape(ns, b, b)[o] if ns else np.zeros((0, b, b))
-        return (brow[o].copy(), bcol[o].copy(), np.ascontiguousarray(vals), _host(self.norm)[:ns][o].copy(),
-                _host(self.sq)[:ns][o].copy(), o)
+        vals = _host(self.val, ns * b * b).reshape(ns, b, b)[o] if ns else np.zeros((0, b, b))
+        return (brow[o].copy(), bcol[o].copy(), np.ascontiguousarray(vals), _host(self.norm, ns)[o].copy(),
+                _host(self.sq, ns)[o].copy(), o)
+
+    def block_map(self) -> np.ndarray:
+        """Host copy of the block map: slot of block (r, c) at r * nb + c, or -1."""
+        torch.cuda.synchronize()
+        return _host(self.map)
+
+    def blocks_at(self, rows, cols):
+        """Host copies of the blocks (rows[t], cols[t]): (present[t], vals[t, col, row]),
+        zeros where a block is absent; copies only those blocks."""
+        b = self.b
+        bmap = self.block_map()
+        rows = np.asarray(rows, dtype=np.int64)
+        cols = np.asarray(cols, dtype=np.int64)
+        slots = bmap[rows * self.nb + cols]
+        out = np.zeros((rows.shape[0], b, b))
+        for t, sl in enumerate(slots):
+            if sl >= 0:
+                out[t] = _host_range(self.val, int(sl) * b * b, b * b).reshape(b, b)
+        return slots >= 0, out
 
     def to_host(self):
         """(n, b, brow, bcol, vals) of the live blocks as a plain record."""
@@ -262,17 +281,32 @@ class _DeviceView:
     def data_ptr(self):
         return self.ptr
 
-    def numpy(self):
+    def numpy(self, count=None):
         npdt = {torch.int32: np.int32, torch.float64: np.float64}[self.dtype]
-        out = np.empty(self.count, dtype=npdt)
-        hip_memcpy_d2h(out, self.ptr)
+        out = np.empty(self.count if count is None else min(int(count), self.count), dtype=npdt)
+        if out.size:
+            hip_memcpy_d2h(out, self.ptr)
         return out
 
 
-def _host(t) -> np.ndarray:
+def _host(t, count=None) -> np.ndarray:
+    """Host copy of t, or of its first count elements."""
     if isinstance(t, _DeviceView):
-        return t.numpy()
+        return t.numpy(count)
+    if count is not None:
+        t = t[: int(count)]
     return t.detach().cpu().numpy()
+
+
+def _host_range(t, start: int, count: int) -> np.ndarray:
+    """Host copy of elements [start, start + count) of t."""
+    if isinstance(t, _DeviceView):
+        npdt = {torch.int32: np.int32, torch.float64: np.float64}[t.dtype]
+        assert 0 <= start and start + count <= t.count
+        out = np.empty(count, dtype=npdt)
+        hip_memcpy_d2h(out, t.ptr + start * out.itemsize)
+        return out
+    return t[start:start + count].detach().cpu().numpy()
 
 
 _hiprt = None
