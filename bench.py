@@ -8,7 +8,15 @@ synthetic 3D system n = 16384, leaf 64, 32 candidate thresholds, eps = 1e-6,
 with the input resident in HBM.  value = executed kept-pair flops (2 b^3 per
 pair, i <= j outputs) over the whole timed purification.
 
+Besides the timed steps the line carries: the same purification as a
+replayed graph, with the FP32 and split-BF16 leaf-product tiers; the
+paper's multiplication experiment on the converged D~ (SpAMM at the swept
+threshold against the exact product plus truncation, delta = 1e-6, 1e-8,
+1e-10); the n = 65536 system in FP64 and both tiers against a reference
+run; the oracle timed on a sample of the workload (cpu_baseline).
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--verify]
+                    [--adjoint] [--batch N] [--no-big] [--no-protocol] [--no-mixed]
 """
 from __future__ import annotations
 
@@ -58,6 +66,11 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="also time the batched workload: the first N of the 64 systems (sizes log-uniform in "
                          "[2048, 32768], seed 4), leaf sizes by the autotuner")
+    ap.add_argument("--no-protocol", action="store_true",
+                    help="skip the paper's multiplication experiment on the converged D~ "
+                         "(delta = 1e-6, 1e-8, 1e-10)")
+    ap.add_argument("--no-big", action="store_true",
+                    help="skip the n = 65536 system (FP64 and both precision tiers against a reference run)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -231,8 +244,16 @@ def main():
         log(f"plain copy of {args.copy_mb} MiB done")
         del src, dst
 
+    if not args.no_protocol:
+        out["protocol"] = protocol_leg(P, torch, res.D, taus)
+
     if args.batch > 0:
         out["batched"] = batch_leg(args, dev, P, synth, batch_mats)
+
+    if not args.no_big:
+        keep = res
+        out["big"] = big_leg(P, torch, synth)
+        res = keep
 
     if not args.no_cpu:
         log("timing the oracle on a sample (cpu baseline)")
@@ -362,6 +383,176 @@ def adjoint_leg(dev, P, synth, torch):
             "checkpoint_every": every, "delta_const": dconst, "loss": L0,
             "forward_with_checkpoints_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
             "directional_derivative": got, "central_differences": fd}
+
+
+def fro_diff(A, B, torch):
+    """||A - B||_F of two device block-sparse matrices of the same shape and
+    leaf size (block-wise over the union of their patterns)."""
+    b, nb = A.b, A.nb
+    bb = b * b
+
+    def live(M):
+        ns = min(int(M.nslot.item()), M.cap)
+        br, bc = M.brow[:ns].long(), M.bcol[:ns].long()
+        ok = br >= 0
+        return torch.nonzero(ok).flatten(), (br * nb + bc)[ok]
+
+    sa, ka = live(A)
+    sb, kb = live(B)
+    va = A.val.view(-1, bb)
+    vb = B.val.view(-1, bb)
+    tot = 0.0
+    chunk = 1 << 14
+    for q in range(0, sa.shape[0], chunk):
+        s_a, k_a = sa[q:q + chunk], ka[q:q + chunk]
+        m_b = B.map[k_a].long()
+        other = torch.where((m_b >= 0)[:, None], vb[m_b.clamp(min=0)], torch.zeros((), dtype=va.dtype, device=va.device))
+        tot += float(((va[s_a] - other) ** 2).sum().item())
+    for q in range(0, sb.shape[0], chunk):
+        s_b, k_b = sb[q:q + chunk], kb[q:q + chunk]
+        only = A.map[k_b].long() < 0
+        if bool(only.any()):
+            tot += float((vb[s_b[only]] ** 2).sum().item())
+    return math.sqrt(tot)
+
+
+def live_blocks(M):
+    ns = min(int(M.nslot.item()), M.cap)
+    return int((M.brow[:ns] >= 0).sum().item())
+
+
+def timed(fn, torch, reps):
+    """(median seconds, last result) of fn() with device syncs around each call."""
+    ts, r = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), r
+
+
+def protocol_leg(P, torch, D, taus, deltas=(1e-6, 1e-8, 1e-10), reps=3):
+    """The paper's multiplication experiment on a converged density matrix:
+    C~ = SpAMM(D~, D~) with tau from the sweep for each error budget delta,
+    against the exact product (tau = 0) followed by truncation at delta.
+    Times are whole library calls (sweep / multiply / truncate), median of
+    reps; reports whether the measured error ||C~ - D~^2||_F sits below the
+    bound and below delta."""
+    b = D.b
+    P.build_norms(D)
+    nb = D.nb
+    Cx = P.BlockSparse(D.n, b, nb * nb, D.device)
+    t_mul, r = timed(lambda: P.multiply(D, D, 0.0, symmetric=True, b_transposed=True, out=Cx), torch, reps)
+    all_pairs = int(r[1][0].item())
+    nnz_exact = live_blocks(Cx)
+    Ca = P.BlockSparse(D.n, b, nb * nb, D.device)
+    Ct = P.BlockSparse(D.n, b, nb * nb, D.device)
+    rows = []
+    for delta in deltas:
+        t_cse, (bound, idx, tau) = timed(lambda: P.sweep_tau(D, D, taus, delta, b_transposed=True), torch, reps)
+        m = int(idx.item())
+        tau_v = float(tau.item())
+        bnd = float(bound[m].item()) if m < len(taus) else 0.0
+        flat = P.sweep_tau(D, D, taus, delta, b_transposed=True, bound="flat")
+        t_sp, r = timed(lambda: P.multiply(D, D, tau_v, symmetric=True, b_transposed=True, out=Ca), torch, reps)
+        kept = int(r[1][0].item())
+        err = fro_diff(Ca, Cx, torch)
+
+        # time only the truncation call, on a fresh copy of the exact product each time
+        tt = []
+        for _ in range(reps):
+            ns = int(Cx.nslot.item())
+            for a in ("nslot", "brow", "bcol", "map"):
+                getattr(Ct, a).copy_(getattr(Cx, a))
+            Ct.val[: ns * b * b].copy_(Cx.val[: ns * b * b])
+            P.build_norms(Ct)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.truncate(Ct, delta, sync=True)
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - t0)
+        t_tr = float(np.median(tt))
+        err_tr = fro_diff(Ct, Cx, torch)
+        rows.append({"delta": delta, "tau": tau_v, "bound": bnd, "err_measured": err,
+                     "tau_flat": float(flat[2].item()), "kept_pairs": kept, "all_pairs": all_pairs,
+                     "nnz_spamm": live_blocks(Ca), "nnz_trunc": live_blocks(Ct), "nnz_exact": nnz_exact,
+                     "ms_cse": round(1e3 * t_cse, 3), "ms_spamm": round(1e3 * t_sp, 3),
+                     "ms_mul": round(1e3 * t_mul, 3), "ms_trunc": round(1e3 * t_tr, 3),
+                     "err_trunc": err_tr,
+                     "spamm_kept_TFLOP_per_s": round(kept * 2.0 * b ** 3 / t_sp / 1e12, 3)})
+        log(f"protocol delta={delta:.0e}: tau={tau_v:.3e} kept {kept}/{all_pairs} err {err:.3e} <= bound "
+            f"{bnd:.3e}; cse {1e3 * t_cse:.2f} ms, spamm {1e3 * t_sp:.2f} ms, mul {1e3 * t_mul:.2f} ms, "
+            f"trunc {1e3 * t_tr:.2f} ms")
+        rows[-1]["err_below_bound"] = bool(err <= bnd or err < 1e-300)
+        rows[-1]["err_below_delta"] = bool(err < delta)
+    del Cx, Ca, Ct
+    torch.cuda.empty_cache()
+    return rows
+
+
+def big_leg(P, torch, synth, reps=1):
+    """The 65536 workload (3D system, seed 3, leaf 64): time to D~ in FP64
+    and with the FP32 and split-BF16 leaf-product tiers, each D~ compared
+    with a reference run of the FP64 path at a 100 times smaller per-step
+    delta (no dense eigensolver at this size; the per-step delta is a
+    constant, 1e-9)."""
+    n, b, seed = 65536, 64, 3
+    t0 = time.perf_counter()
+    Fh = synth.sys3d(n, seed, b)
+    log(f"big: input n={n} generated in {time.perf_counter() - t0:.1f} s ({Fh.nblk} blocks)")
+    F = P.BlockSparse.from_host(Fh)
+    del Fh
+    taus = synth.tau_log(32)
+    nb = F.nb
+    n_occ = n // 2
+
+    def run(precision, dconst):
+        return P.purify(F, n_occ, 1e-6, taus, delta_const=dconst, cap=nb * nb, precision=precision)
+
+    def keep_d(res):
+        """A compact device copy of the result (only its live slots)."""
+        D = res.D
+        ns = int(D.nslot.item())
+        K = P.BlockSparse(n, b, max(ns, 1), D.device)
+        K.nslot.copy_(D.nslot)
+        K.brow.copy_(D.brow[:K.cap])
+        K.bcol.copy_(D.bcol[:K.cap])
+        K.map.copy_(D.map)
+        K.val.copy_(D.val[: K.cap * b * b])
+        return K
+
+    ref = run("fp64", 1e-11)
+    rsteps = [lg for lg in ref.logs if lg["branch"] >= 0]
+    Dref = keep_d(ref)
+    del ref
+    torch.cuda.empty_cache()
+    log(f"big: reference run done, {len(rsteps)} iterations")
+    out = {"workload": f"sp2_hybrid_sys3d_n{n}_leaf{b}_tau32_eps1e-6_seed{seed}", "delta_const": 1e-9,
+           "reference": {"delta_const": 1e-11, "iterations": len(rsteps),
+                         "kept_pairs": int(sum(lg["npairs"] for lg in rsteps))}}
+    base_t = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        run(prec, 1e-9)                         # warm-up
+        t, r = timed(lambda: run(prec, 1e-9), torch, reps)
+        st = [lg for lg in r.logs if lg["branch"] >= 0]
+        pairs = sum(lg["npairs"] for lg in st)
+        low = sum(lg["npairs_low"] for lg in st)
+        err = fro_diff(r.D, Dref, torch)
+        base_t = t if prec == "fp64" else base_t
+        out[prec] = {"sp2_time_s": round(t, 4), "iterations": len(st), "kept_pairs": int(pairs),
+                     "low_tier_pairs": int(low), "kept_TFLOP_per_s": round(pairs * 2.0 * b ** 3 / t / 1e12, 3),
+                     "fro_err_vs_reference": err, "peak_blocks": int(max(lg["nslot_hat"] for lg in st)),
+                     "speedup_vs_fp64": round(base_t / t, 4),
+                     "phase_ms": {k: round(sum(lg[k] for lg in st), 2)
+                                  for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc")}}
+        log(f"big {prec}: {t:.3f} s, {len(st)} iterations, low-tier {low}/{pairs}, err vs reference {err:.3e}")
+        del r
+        torch.cuda.empty_cache()
+    del Dref, F
+    torch.cuda.empty_cache()
+    return out
 
 
 def _gen_leaf32(arg):

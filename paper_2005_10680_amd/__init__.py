@@ -364,15 +364,17 @@ def sweep_tau(A: BlockSparse, B: BlockSparse, taus, budget, b_transposed=False, 
     return bound, idx, tau
 
 
-def multiply(A: BlockSparse, B: BlockSparse, tau, symmetric=False, b_transposed=False, cap=None, max_pairs=None):
-    """C~ = SpAMM(A, B, tau) (Algorithm 2).  Returns (C, kept[2] = pairs, outputs)."""
+def multiply(A: BlockSparse, B: BlockSparse, tau, symmetric=False, b_transposed=False, cap=None, max_pairs=None,
+             out=None):
+    """C~ = SpAMM(A, B, tau) (Algorithm 2).  Returns (C, kept[2] = pairs, outputs).
+    out: an existing BlockSparse of the same n and leaf size to overwrite."""
     dev = A.device
     nb = A.nb
     if cap is None:
         cap = nb * nb
     if max_pairs is None:
         max_pairs = max(1, nb * nb * nb // (2 if symmetric else 1))
-    C = BlockSparse(A.n, A.b, cap, dev)
+    C = out if out is not None else BlockSparse(A.n, A.b, cap, dev)
     tau_t = tau if isinstance(tau, torch.Tensor) else torch.tensor([float(tau)], dtype=torch.float64, device=dev)
     kept = torch.zeros(2, dtype=torch.int64, device=dev)
     ws = _ws(lib().spamm_multiply_workspace_bytes(nb, 0) + 8 * int(max_pairs) + 1024, dev)
