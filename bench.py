@@ -574,6 +574,19 @@ def generate_batch(count, synth):
     return mats
 
 
+def batch_bytes(P, F, cap, max_pairs, taus, prec):
+    """Device bytes one system adds to a batched call: its share of the
+    workspace and its output matrix."""
+    import ctypes
+    p = P.sp2_params(F.n // 2, 1e-6, 60, 0, 0, len(taus), float("nan"), float("nan"), 1e-9, 0.0, 0,
+                     P.PRECISIONS[prec], 0.5, 8, 0)
+    ws = P.lib().purify_sp2_batched_workspace_bytes(1, ctypes.byref(F.struct()), ctypes.byref(p),
+                                                    (ctypes.c_int64 * 1)(int(cap)),
+                                                    (ctypes.c_int64 * 1)(int(max_pairs)))
+    out = cap * (F.b * F.b * 8 + 4 * 8) + F.nb * F.nb * 4
+    return float(ws + out)
+
+
 def batch_leg(args, dev, P, synth, mats):
     """The batched workload: independent 3D systems (sizes log-uniform in
     [2048, 32768], generator seed 4, system seeds 4000 + s), generated at
@@ -597,6 +610,8 @@ def batch_leg(args, dev, P, synth, mats):
         leaves.append(b)
         del F32
         torch.cuda.empty_cache()
+        if len(leaves) % 8 == 0:
+            log(f"batch: autotuned {len(leaves)}/{len(mats)} systems")
     log(f"batch: autotuned leaf sizes {dict((b, leaves.count(b)) for b in sorted(set(leaves)))} "
         f"in {time.perf_counter() - t0:.1f} s")
     del mats
@@ -608,13 +623,15 @@ def batch_leg(args, dev, P, synth, mats):
         # one after another (graph loop each, capacity nb^2): the comparison,
         # and the peak block count of every system (runs are deterministic,
         # so the batched run needs exactly these capacities)
-        peaks = []
+        peaks, pair_peaks = [], []
         for F in Fs:
             r1 = P.purify(F, F.n // 2, eps, taus, delta_const=dconst, precision=prec, graph_steps=8)
             nf = int(F.live()[0].shape[0])
             peaks.append(max([nf + F.nb] + [int(l["nslot_hat"]) for l in r1.logs]))
+            pair_peaks.append(max([1] + [int(l["npairs"]) for l in r1.logs]))
             del r1
         torch.cuda.empty_cache()
+        log(f"batch {prec}: peak capacities measured")
         caps = [min(F.nb * F.nb, pk) for F, pk in zip(Fs, peaks)]
         caps_used = caps
         torch.cuda.synchronize()
@@ -624,24 +641,50 @@ def batch_leg(args, dev, P, synth, mats):
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
         torch.cuda.empty_cache()
-        kw = dict(delta_const=dconst, precision=prec, caps=caps, graph_steps=8, raise_on_error=False)
-        r = P.purify_batched(Fs, [F.n // 2 for F in Fs], eps, taus, float("nan"), float("nan"), **kw)
+        # the systems go into as few batched calls as fit in free device memory
+        # (workspace plus output, which doubles as the second iterate buffer)
+        free, _ = torch.cuda.mem_get_info()
+        budget = 0.8 * free
+        chunks, cur, used = [], [], 0.0
+        for q, (F, cp, mp) in enumerate(zip(Fs, caps, pair_peaks)):
+            need = batch_bytes(P, F, cp, mp, taus, prec)
+            if cur and used + need > budget:
+                chunks.append(cur)
+                cur, used = [], 0.0
+            cur.append(q)
+            used += need
+        chunks.append(cur)
+
+        def run_chunks():
+            out_logs, out_status = [None] * len(Fs), [None] * len(Fs)
+            for ch in chunks:
+                kw = dict(delta_const=dconst, precision=prec, caps=[caps[q] for q in ch],
+                          max_pairs=[pair_peaks[q] for q in ch], graph_steps=8, raise_on_error=False)
+                r = P.purify_batched([Fs[q] for q in ch], [Fs[q].n // 2 for q in ch], eps, taus, float("nan"),
+                                     float("nan"), **kw)
+                for t, q in enumerate(ch):
+                    out_logs[q], out_status[q] = r.logs[t], r.status[t]
+                del r
+            return out_logs, out_status
+        run_chunks()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = P.purify_batched(Fs, [F.n // 2 for F in Fs], eps, taus, float("nan"), float("nan"), **kw)
+        logs_b, status_b = run_chunks()
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
-        ok = sum(1 for st in r.status if st >= 0)
-        flops = sum(sum(l["npairs"] for l in lg if l["branch"] >= 0) * 2.0 * F.b ** 3 for lg, F in zip(r.logs, Fs))
-        iters = [sum(1 for l in lg if l["branch"] >= 0) for lg in r.logs]
-        del r
+        ok = sum(1 for st in status_b if st >= 0)
+        flops = sum(sum(l["npairs"] for l in lg if l["branch"] >= 0) * 2.0 * F.b ** 3 for lg, F in zip(logs_b, Fs))
+        iters = [sum(1 for l in lg if l["branch"] >= 0) for lg in logs_b]
         torch.cuda.empty_cache()
-        log(f"batch {prec}: {tb:.3f} s together, {ts:.3f} s one by one, {ok}/{len(Fs)} systems ok")
+        log(f"batch {prec}: {tb:.3f} s together ({len(chunks)} batched calls), {ts:.3f} s one by one, "
+            f"{ok}/{len(Fs)} systems ok")
         res_all[prec] = {"time_s": round(tb, 4), "kept_TFLOP_per_s": round(flops / tb / 1e12, 4),
+                         "batched_calls": len(chunks), "systems_per_call": [len(c) for c in chunks],
                          "sequential_time_s": round(ts, 4), "speedup_vs_sequential": round(ts / tb, 4),
                          "systems_ok": ok, "iterations_min_max": [min(iters), max(iters)]}
     dense = sum(F.nb * F.nb for F in Fs)
-    return {"systems": len(Fs), "sum_n": int(sum(F.n for F in Fs)),
+    gib = sum(cp * F.b * F.b * 8 for cp, F in zip(caps_used, Fs)) / 2 ** 30 if caps_used else None
+    return {"systems": len(Fs), "iterate_capacity_GiB": round(gib, 2) if gib else None, "sum_n": int(sum(F.n for F in Fs)),
             "leaf_counts": {str(b): leaves.count(b) for b in sorted(set(leaves))},
             "capacity_fraction_of_dense": round(sum(caps_used) / dense, 4) if caps_used else None,
             "delta_const": dconst, **res_all}

@@ -321,7 +321,12 @@ int purify_sp2_adjoint(const spamm_bsm* F, const sp2_params* p, const spamm_bsm*
  * output lists, balanced by kept-pair count over the 8 XCDs.  Each system's
  * result, records and status are bit-identical to its own purify_sp2 run.
  *   F, p, D    : host arrays [nsys] (same contracts as purify_sp2; keep_tape
- *                must be 0; capacities D[q].cap).
+ *                must be 0; capacities D[q].cap).  D[q] also serves as the
+ *                second iterate buffer of system q during the run (the
+ *                workspace holds one matrix of that capacity per system, not
+ *                two); on return it holds D~ of system q, or scratch contents
+ *                when that system failed.  D[q] must not overlap F or the
+ *                workspace.
  *   max_pairs  : host [nsys] kept-pair capacity per system.
  *   log        : host [nsys * log_stride], log_stride >= n_max + 2 of every
  *                system; nlog_out, status_out: host [nsys].

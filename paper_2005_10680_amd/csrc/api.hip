@@ -405,11 +405,13 @@ struct Sp2Ws {
 
 constexpr int kMaxLog = 10002;  // n_max <= 10000, plus the stop record
 
+// x1_outside: the second iterate buffer X[1] is not carved (the batched
+// loop uses the caller's output matrix for it)
 void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, int tape_steps, Sp2Ws& w,
-               int precision = 0) {
+               int precision = 0, bool x1_outside = false) {
     const int64_t n = (int64_t)nb * b;
     carve_mat(c, n, b, cap, w.X[0]);
-    carve_mat(c, n, b, cap, w.X[1]);
+    if (!x1_outside) carve_mat(c, n, b, cap, w.X[1]);
     w.tape.resize(tape_steps > 0 ? tape_steps + 1 : 0);
     for (auto& t : w.tape) carve_mat(c, n, b, cap, t);
     carve_sweep(c, nb, N, w.sw);
@@ -1304,7 +1306,7 @@ size_t purify_sp2_batched_workspace_bytes(int32_t nsys, const spamm_bsm* F, cons
     for (int q = 0; q < nsys; ++q) {
         if (F[q].nb < 1 || p[q].N < 1 || cap_blocks[q] < 1 || max_pairs[q] < 0) return 0;
         Sp2Ws w;
-        carve_sp2(c, F[q].nb, F[q].b, p[q].N, cap_blocks[q], max_pairs[q], 0, w, p[q].precision);
+        carve_sp2(c, F[q].nb, F[q].b, p[q].N, cap_blocks[q], max_pairs[q], 0, w, p[q].precision, true);
     }
     c.take<GemmArgs>(2 * (size_t)nsys);        // descriptors, two parities
     c.take<int64_t>(2 * (size_t)(nsys + 1) * 5);  // out_off / pair_off per group (<= 5 groups)
@@ -1349,7 +1351,12 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     std::vector<Sp2Ws> W(nsys);
-    for (int q = 0; q < nsys; ++q) carve_sp2(c, F[q].nb, F[q].b, p[q].N, caps[q], max_pairs[q], 0, W[q], p[q].precision);
+    for (int q = 0; q < nsys; ++q) {
+        carve_sp2(c, F[q].nb, F[q].b, p[q].N, caps[q], max_pairs[q], 0, W[q], p[q].precision, true);
+        // D[q] is the second ping-pong iterate: one matrix of capacity less per system
+        W[q].X[1] = D[q];
+        W[q].X[1].n = (int64_t)F[q].nb * F[q].b;
+    }
     GemmArgs* descs_dev = c.take<GemmArgs>(2 * (size_t)nsys);
     int64_t* offs = c.take<int64_t>(2 * (size_t)(nsys + 1) * 5);
     int32_t* counters = c.take<int32_t>(16 * 5);
@@ -1590,17 +1597,11 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             continue;
         }
         if (cs.status > 0 && worst == SPAMM_OK) worst = cs.status;
-        spamm_bsm* Xf = &w.X[(nl - 1) & 1];
-        const int64_t cap = caps[q];
-        const int b = F[q].b, nb = F[q].nb;
-        HIP_TRY(hipMemcpyAsync(D[q].nslot, Xf->nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D[q].brow, Xf->brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D[q].bcol, Xf->bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D[q].map, Xf->map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D[q].val, Xf->val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D[q].norm, Xf->norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D[q].sq, Xf->sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(D[q].sqlo, Xf->sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+        // the final iterate lives in X[0] (workspace) or X[1] (= D[q] itself)
+        if (((nl - 1) & 1) == 0) {
+            int rc = copy_mat(D[q], w.X[0], caps[q], s);
+            if (rc) return rc;
+        }
     }
     HIP_TRY(hipStreamSynchronize(s));
     if (worst < 0) return fail(worst, "a system of the batch failed (see status_out)");
