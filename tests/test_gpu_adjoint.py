@@ -172,3 +172,55 @@ def test_checkpointed_adjoint_equals_full_tape(every):
     g_ck = P.purify_adjoint(ck, G, dval)
     assert torch.equal(g_full, g_ck)
     assert float(g_ck.abs().sum()) > 0.0
+
+
+def test_zero_tolerance_gradient_equals_dense_references():
+    """With zero tolerances (tau = 0, nothing truncated) the GPU's dL/dF
+    equals the dense FP64 chain rule of the SP2 polynomials with the run's
+    branches and Gerschgorin bounds, and (SP2 having converged) the
+    derivative of the exact spectral projector onto the n_occ lowest
+    eigenvectors: sum over occupied a, virtual v of the (a, v) entry of
+    U^T W U divided by e_a - e_v, on both (a, v) and (v, a)."""
+    rng = np.random.default_rng(31)
+    Fm = synth.chain1d(512, 2, 32)
+    F = oracle.BSM.of(Fm)
+    n, n_occ = F.n, 256
+    G = P.BlockSparse.from_host(Fm)
+    res = P.purify(G, n_occ, 1e-6, synth.tau_paper(), delta_const=0.0, n_max=40, keep_tape=True)
+    steps = [lg for lg in res.logs if lg["branch"] >= 0]
+    assert all(lg["tau"] == 0.0 for lg in steps) and len(steps) >= 10
+    dval, Do = sym_random_on(res.D, rng)
+    Wm = Do.to_dense()
+    fbar = P.purify_adjoint(res, G, dval)
+    got = np.zeros((n, n))
+    vals = slot_values(G, fbar)
+    brow, bcol, _, _, _, _ = G.live()
+    mask = np.zeros((n, n), dtype=bool)
+    b = F.b
+    for t in range(brow.shape[0]):
+        r, c = int(brow[t]), int(bcol[t])
+        got[r * b:(r + 1) * b, c * b:(c + 1) * b] = vals[t].T
+        mask[r * b:(r + 1) * b, c * b:(c + 1) * b] = True
+    # dense chain rule with the run's own branches and bounds
+    lmin, lmax = oracle.gerschgorin(F)
+    Xs = [(lmax * np.eye(n) - F.to_dense()) / (lmax - lmin)]
+    for lg in steps:
+        X = Xs[-1]
+        Xs.append(X @ X if lg["branch"] == 0 else 2 * X - X @ X)
+    Gb = Wm.copy()
+    for t in range(len(steps), 0, -1):
+        X = Xs[t - 1]
+        GX = Gb @ X + X @ Gb
+        Gb = GX if steps[t - 1]["branch"] == 0 else 2 * Gb - GX
+    want = -Gb / (lmax - lmin)
+    assert np.linalg.norm((got - want)[mask]) <= 1e-10 * np.linalg.norm(want[mask])
+    # the exact projector's derivative
+    e, U = np.linalg.eigh(F.to_dense())
+    Wt = U.T @ Wm @ U
+    occ = np.arange(n) < n_occ
+    Gam = np.zeros((n, n))
+    de = e[:, None] - e[None, :]
+    cross = occ[:, None] != occ[None, :]
+    Gam[cross] = (occ[:, None].astype(float) - occ[None, :].astype(float))[cross] / de[cross]
+    Fex = U @ (Gam * Wt) @ U.T
+    assert np.linalg.norm((got - Fex)[mask]) <= 1e-8 * np.linalg.norm(Fex[mask])
