@@ -62,7 +62,7 @@ def lib():
         L.o_cse_tree.restype = i32
         L.o_cse_tree_leafvals.argtypes = [i32, P, P, P, P]
         L.o_cse_tree_leafvals.restype = i32
-        L.o_cse_flat_sum.argtypes = [i32, P, P, P, P, P, i32, P, P]
+        L.o_cse_flat_sum.argtypes = [i32, P, P, P, P, P, i32, i32, d, d, P, P]
         L.o_kept_counts.argtypes = [i32, P, P, P, P, d, i32, P]
         L.o_kept_lists.argtypes = [i32, P, P, P, P, d, i64, P, P, P, P]
         L.o_block_products.argtypes = [i32, i32, P, P, P, P, i64, P, P, P, P, P]
@@ -188,14 +188,20 @@ def cse_tree_leafvals(A: BSM, B: BSM, leafvals: np.ndarray) -> float:
     return float(out[0])
 
 
-def cse_flat_sum(A: BSM, B: BSM, taus, nuA=None, nuB=None):
+def cse_flat_sum(A: BSM, B: BSM, taus, nuA=None, nuB=None, mode=0, tau0=0.0, c_low=0.0):
+    """Leaf-level bounds for every candidate: B_flat = (sum over outputs of
+    (sum over k of the leaf values)^2)^(1/2) (eq. (6) applied to each output's
+    leaf blocks) and B_sum = the sum of all leaf values.  Leaf values as in
+    Algorithm 3: p when p < tau_k (mode 0); in mode 1 (precision tiers) p when
+    p < tau0, c_low p when tau0 <= p < tau_k, else 0.  Plain FP64 sums in
+    the order outputs (i, j) row-major, k ascending."""
     taus = np.ascontiguousarray(taus, dtype=np.float64)
     nuA = norms(A)[1] if nuA is None else np.ascontiguousarray(nuA)
     nuB = norms(B)[1] if nuB is None else np.ascontiguousarray(nuB)
     flat = np.zeros(taus.shape[0])
     ssum = np.zeros(taus.shape[0])
     lib().o_cse_flat_sum(A.nb, _p(A.block_map()), _p(nuA), _p(B.block_map()), _p(nuB), _p(taus),
-                         taus.shape[0], _p(flat), _p(ssum))
+                         taus.shape[0], int(mode), float(tau0), float(c_low), _p(flat), _p(ssum))
     return flat, ssum
 
 
@@ -544,8 +550,6 @@ def sp2_step(X: BSM, st: SP2State, p: SP2Params):
         if p.bound == "tree":
             bound = cse_tree(X, X, taus, nu, nu)
         else:
-            if p.precision:
-                raise ValueError("the precision tiers select with the recursive bound")
             flat, ssum = cse_flat_sum(X, X, taus, nu, nu)
             bound = flat if p.bound == "flat" else ssum
         idx, tau = select(bound, taus, skip_budget)
@@ -554,7 +558,11 @@ def sp2_step(X: BSM, st: SP2State, p: SP2Params):
         # the largest low-precision limit whose bound (skipped p, plus c p for
         # pairs evaluated in the low tier) stays below the product budget
         c_low = tier_constant(p.precision, X.b)
-        bound2 = cse_tree(X, X, taus, nu, nu, mode=1, tau0=tau, c_low=c_low)
+        if p.bound == "tree":
+            bound2 = cse_tree(X, X, taus, nu, nu, mode=1, tau0=tau, c_low=c_low)
+        else:
+            f2, s2 = cse_flat_sum(X, X, taus, nu, nu, mode=1, tau0=tau, c_low=c_low)
+            bound2 = f2 if p.bound == "flat" else s2
         sidx, sigma = select(bound2, taus, budget)
     C, K = spamm(X, X, tau, sym=True, nuA=nu, nuB=nu)
     if p.precision:

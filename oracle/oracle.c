@@ -271,7 +271,7 @@ int o_cse_tree_leafvals(int nb, const int32_t* mapA, const int32_t* mapB, const 
  *   flat[k] = sqrt( sum_ij ( sum_{kk: p < tau_k} p )^2 )   (eq. (6) at leaf level)
  *   sum[k]  = sum over skipped pairs of p.                                      */
 void o_cse_flat_sum(int nb, const int32_t* mapA, const double* nuA, const int32_t* mapB, const double* nuB,
-                    const double* tau, int N, double* flat, double* sum) {
+                    const double* tau, int N, int mode, double tau0, double c_low, double* flat, double* sum) {
     double* colsum = (double*)malloc(sizeof(double) * N);
     for (int k = 0; k < N; ++k) { flat[k] = 0.0; sum[k] = 0.0; }
     for (int i = 0; i < nb; ++i)
@@ -282,8 +282,14 @@ void o_cse_flat_sum(int nb, const int32_t* mapA, const double* nuA, const int32_
                 int sa = mapA[(int64_t)i * nb + kk], sb = mapB[(int64_t)kk * nb + j];
                 if (sa < 0 || sb < 0) continue;
                 double p = nuA[sa] * nuB[sb];
-                for (int k = 0; k < N; ++k)
-                    if (p < tau[k]) { colsum[k] += p; sum[k] += p; any = 1; }
+                for (int k = 0; k < N; ++k) {
+                    /* the leaf value of the CSE rule: p when skipped, c_low p
+                       in the low tier (mode 1), nothing when kept exactly */
+                    double v;
+                    if (mode == 0) v = p < tau[k] ? p : 0.0;
+                    else v = p < tau0 ? p : (p < tau[k] ? c_low * p : 0.0);
+                    if (v != 0.0) { colsum[k] += v; sum[k] += v; any = 1; }
+                }
             }
             if (any)
                 for (int k = 0; k < N; ++k) flat[k] += colsum[k] * colsum[k];

@@ -384,3 +384,63 @@ def test_bf16_rounding_helper():
     assert _rn_bf16(-(1.0 + 3 * 2.0 ** -8)) == -(1.0 + 2.0 ** -6)
     assert _rn_bf16(3 * 2.0 ** -134) == 2.0 ** -132             # subnormal spacing 2^-133, tie to even
     assert _rn_bf16(2.0 ** -140) == 0.0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_leaf_bounds_tier_mode(seed):
+    """Tier mode of B_flat / B_sum: the same special cases as the recursive
+    bound's tier mode (sigma <= tau0 or c = 0: the plain bound at tau0;
+    c = 1: the plain bound at sigma), and both bound the error of a product
+    that skips p < tau0, evaluates tau0 <= p < sigma in FP32 (folded into
+    FP64 per pair) and the rest in FP64, against the exact product."""
+    rng = np.random.default_rng(400 + seed)
+    A = rand_bsm(rng, 6, 8, 0.7, decay=0.8)
+    B = rand_bsm(rng, 6, 8, 0.7, decay=0.8, n=A.n)
+    taus = synth.tau_log(24, -12.0) * 10.0
+    fl, sm = oracle.cse_flat_sum(A, B, taus)
+    for t0 in [taus[5], taus[12]]:
+        f0, s0 = oracle.cse_flat_sum(A, B, np.array([t0]))
+        low = np.array([t for t in taus if t <= t0])
+        f1, s1 = oracle.cse_flat_sum(A, B, low, mode=1, tau0=t0, c_low=0.3)
+        assert np.all(f1 == f0[0]) and np.all(s1 == s0[0])
+        hi = np.array([t for t in taus if t >= t0])
+        f1, s1 = oracle.cse_flat_sum(A, B, hi, mode=1, tau0=t0, c_low=1.0)
+        assert np.array_equal(f1, fl[:hi.shape[0]]) and np.array_equal(s1, sm[:hi.shape[0]])
+        f1, s1 = oracle.cse_flat_sum(A, B, hi, mode=1, tau0=t0, c_low=0.0)
+        assert np.all(f1 == f0[0]) and np.all(s1 == s0[0])
+    # the bound holds for a real tiered product
+    b = A.b
+    c = oracle.tier_constant(1, b)
+    nuA, nuB = oracle.norms(A)[1], oracle.norms(B)[1]
+    exact = A.to_dense() @ B.to_dense()
+    mA, mB = A.block_map(), B.block_map()
+    nb = A.nb
+    ps = np.array([nuA[mA[i * nb + k]] * nuB[mB[k * nb + j]] for i in range(nb) for k in range(nb)
+                   for j in range(nb) if mA[i * nb + k] >= 0 and mB[k * nb + j] >= 0])
+    for q0, q1 in [(0.2, 0.6), (0.5, 0.9)]:
+        t0, sig = np.quantile(ps, q0), np.quantile(ps, q1)
+        assert np.sum(ps < t0) > 0 and np.sum((ps >= t0) & (ps < sig)) > 0
+        C = np.zeros((nb * b, nb * b))
+        for i in range(nb):
+            for j in range(nb):
+                acc = np.zeros((b, b))
+                for k in range(nb):
+                    sa, sb = mA[i * nb + k], mB[k * nb + j]
+                    if sa < 0 or sb < 0:
+                        continue
+                    p = nuA[sa] * nuB[sb]
+                    Ab, Bb = A.vals[sa].T, B.vals[sb].T
+                    if p < t0:
+                        continue
+                    if p < sig:
+                        acc = acc + (Ab.astype(np.float32) @ Bb.astype(np.float32)).astype(np.float64)
+                    else:
+                        acc = acc + Ab @ Bb
+                C[i * b:(i + 1) * b, j * b:(j + 1) * b] = acc
+        err = np.linalg.norm(C[:A.n, :A.n] - exact)
+        f1, s1 = oracle.cse_flat_sum(A, B, np.array([sig]), mode=1, tau0=t0, c_low=c)
+        tr = oracle.cse_tree(A, B, np.array([sig]), mode=1, tau0=t0, c_low=c)
+        # (the FP64 pairs' own rounding, ~1e-16 of the product, is outside the bound)
+        assert err <= f1[0] + 1e-13 * np.linalg.norm(exact)
+        assert f1[0] <= tr[0] * (1 + 1e-12) and tr[0] <= s1[0] * (1 + 1e-12)
+        assert f1[0] > 0

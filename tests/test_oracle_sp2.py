@@ -162,7 +162,31 @@ def test_leaf_bounds_step_conditions(bound):
         X = Xn
     assert strict > 0
     assert np.linalg.norm(X.to_dense() - Dref) < 1e-6
-    with pytest.raises(ValueError):
-        oracle.sp2_step(X0, oracle.sp2_start(F, p)[2],
-                        oracle.SP2Params(n_occ=n_occ, taus=taus, homo=w[n_occ - 1], lumo=w[n_occ], bound=bound,
-                                         precision=1))
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_leaf_bound_tier_selection_converges(precision):
+    """The tier selection with B_flat (tau from a share of the budget, then
+    sigma from the tier mode of B_flat) uses low-tier pairs and converges;
+    at every step sigma's B_flat is below the product budget."""
+    n = 768
+    F = oracle.BSM.of(synth.sys3d(n, 7, 32))
+    Dref, w = eigh_density(F, n // 2)
+    taus = synth.tau_log(32)
+    p = oracle.SP2Params(n_occ=n // 2, eps=1e-6, taus=taus, homo=w[n // 2 - 1], lumo=w[n // 2],
+                         precision=precision, bound="flat")
+    X, X0, st, _ = oracle.sp2_start(F, p)
+    c = oracle.tier_constant(precision, 32)
+    nlow = 0
+    while True:
+        Xn, Xh, log, st = oracle.sp2_step(X, st, p)
+        if Xn is None:
+            break
+        if log.sidx < len(taus):
+            nu = oracle.norms(X)[1]
+            f2, _ = oracle.cse_flat_sum(X, X, np.array([log.sigma]), nu, nu, mode=1, tau0=log.tau, c_low=c)
+            assert f2[0] < log.delta / 2
+        nlow += log.npairs_low
+        X = Xn
+    assert nlow > 0
+    assert np.linalg.norm(X.to_dense() - Dref) < 1e-6
