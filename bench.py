@@ -101,9 +101,10 @@ def main():
     max_pairs = nb * nb * (nb + 1) // 2
     eps = 1e-6
 
-    def run_once(precision="fp64", graph_steps=0, keep_tape=False, cap_=None):
+    def run_once(precision="fp64", graph_steps=0, keep_tape=False, cap_=None, bound="tree"):
         return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap_ or cap,
-                        max_pairs=max_pairs, precision=precision, graph_steps=graph_steps, keep_tape=keep_tape)
+                        max_pairs=max_pairs, precision=precision, graph_steps=graph_steps, keep_tape=keep_tape,
+                        bound=bound)
 
     log(f"input ready: n={n} leaf={b} blocks={Fh.nblk}")
     for w in range(args.warmup):
@@ -178,13 +179,43 @@ def main():
                              "speedup_vs_host_loop": round(float(np.median(times)) / float(np.median(gtimes)), 4),
                              "same_decisions": bool(same)}
 
+    # the same purification selecting tau (and sigma) with the leaf-level bound B_flat
+    res_mixed = {}
+    res_flat = None
+    if not args.no_mixed:
+        for prec, key in (("fp64", "bound_flat"), ("bf16x3", "bound_flat_bf16x3")):
+            run_once(prec, bound="flat")
+            ftimes = []
+            for _ in range(args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rf = run_once(prec, bound="flat")
+                torch.cuda.synchronize()
+                ftimes.append(time.perf_counter() - t0)
+            if prec == "fp64":
+                res_flat = rf
+            fsteps = [l for l in rf.logs if l["branch"] >= 0]
+            fpairs = sum(l["npairs"] for l in fsteps)
+            flow = sum(l["npairs_low"] for l in fsteps)
+            log(f"B_flat selection ({prec}): {float(np.median(ftimes)):.3f} s, {len(fsteps)} iterations, "
+                f"kept pairs {fpairs} ({flow} low tier)")
+            out[key] = {"precision": prec, "sp2_time_s": round(float(np.median(ftimes)), 4),
+                        "iterations": len(fsteps), "kept_pairs_per_run": int(fpairs),
+                        "low_tier_pairs_per_run": int(flow),
+                        "kept_pairs_vs_tree_fp64": round(fpairs / max(1, sum(l["npairs"] for l in steps)), 4),
+                        "speedup_vs_fp64_tree": round(float(np.median(times)) / float(np.median(ftimes)), 4),
+                        "mean_tau_ratio_vs_tree_fp64": round(float(np.exp(np.mean(
+                            [np.log(a["tau"] / b["tau"]) for a, b in zip(fsteps, steps)
+                             if a["tau"] > 0 and b["tau"] > 0]))), 3)}
+            if prec != "fp64":
+                res_mixed[key] = rf
+
     # reverse mode at n = 32768 with a banded W (checkpointed tape)
     if args.adjoint:
         torch.cuda.empty_cache()
         out["adjoint"] = adjoint_leg(dev, P, synth, torch)
 
     # mixed precision (FP32 and split-BF16 leaf-product tiers) on the same workload
-    res_mixed = {}
     if not args.no_mixed:
         for tier, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3")):
             run_once(tier)
@@ -232,6 +263,16 @@ def main():
                 rr, cc = min(b, n - r * b), min(b, n - c * b)
                 Dd[r * b:r * b + rr, c * b:c * b + cc] = blk[:rr, :cc]
             out[key]["verify_fro_err"] = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
+        if res_flat is not None:
+            res_mixed["bound_flat"] = res_flat
+            Dm = res_flat.D.to_host()
+            Dd[:] = 0.0
+            for k in range(Dm.brow.shape[0]):
+                r, c = int(Dm.brow[k]), int(Dm.bcol[k])
+                blk = Dm.vals[k].T
+                rr, cc = min(b, n - r * b), min(b, n - c * b)
+                Dd[r * b:r * b + rr, c * b:c * b + cc] = blk[:rr, :cc]
+            out["bound_flat"]["verify_fro_err"] = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
         log(f"verified: fp64 {err:.3e}" + "".join(f", {k} {out[k]['verify_fro_err']:.3e}" for k in res_mixed))
         del Fd, U, Uo, Dref
 

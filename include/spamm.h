@@ -99,11 +99,12 @@ int spamm_build_norms(spamm_bsm* X, spamm_stream_t stream);
  *               threshold, c_low the per-pair rounding factor of the low tier).
  *   flags     : SPAMM_B_TRANSPOSED, SPAMM_SYNC, and at most one of
  *               SPAMM_BOUND_FLAT / SPAMM_BOUND_SUM to replace Algorithm 3's
- *               recursive bound by a leaf-level one (mode 0 only; both flags
- *               -> SPAMM_EINVAL).  B_flat <= B_tree <= B_sum, and all three
+ *               recursive bound by a leaf-level one with the same leaf values
+ *               (both modes; both flags -> SPAMM_EINVAL).  B_flat <= B_tree <= B_sum, and all three
  *               bound the product error, so FLAT admits the largest threshold.
  *               The leaf-level bounds add their per-output sums in a fixed
- *               order and are deterministic.
+ *               order and are deterministic; they need nb <= 2048
+ *               (SPAMM_ENOTSUP otherwise).
  *   bound_out : device [N] bound of ||SpAMM(A,B,tau_k) - AB||_F per candidate.
  *   idx_out   : device [1] selected index (N when none qualifies).
  *   tau_out   : device [1] selected threshold (0 when none qualifies).
@@ -195,7 +196,8 @@ typedef struct sp2_params {
                             and replayed, the host polling the stop flag every K iterations
                             (requires keep_tape == 0; phase timings are 0) */
     int32_t bound_kind;  /* threshold selection: 0 Algorithm 3 (B_tree), 1 B_flat, 2 B_sum (see
-                            SPAMM_BOUND_FLAT / SPAMM_BOUND_SUM); the precision tiers need 0 */
+                            SPAMM_BOUND_FLAT / SPAMM_BOUND_SUM); with a precision tier the
+                            same bound selects sigma */
 } sp2_params;
 
 /* Per-iteration record written by purify_sp2 (host memory). */

@@ -144,17 +144,18 @@ void carve_sweep(Carver& c, int nb, int N, SweepWs& w) {
 }
 
 // The leaf-level bounds B_flat (kind 1) or B_sum (kind 2) for every
-// candidate, then the selection rule.
+// candidate (mode 1: the tier mode, as in run_sweep), then the selection rule.
 void run_sweep_leaf(const MatView& A, const MatView& B, int btrans, const double* tau, int N,
-                    const double* budget_dev, double budget_host, int kind, double* bound_out, int32_t* idx_out,
-                    double* tau_out, SweepWs& w, const int32_t* done, hipStream_t s) {
+                    const double* budget_dev, double budget_host, int kind, int mode, const double* tau0_dev,
+                    double c_low, double* bound_out, int32_t* idx_out, double* tau_out, SweepWs& w,
+                    const int32_t* done, hipStream_t s) {
     const int nb = A.nb;
     fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
     fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
     launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
     launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
     launch_bound_leaf(nb, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, tau, N, kind == 1 ? 1 : 0,
-                      w.part, w.bleaf, done, s);
+                      mode, tau0_dev, c_low, w.part, w.bleaf, done, s);
     fill_i64(w.one, 1, 1, s);
     launch_select(w.bleaf, w.one, tau, N, budget_dev, budget_host, bound_out, idx_out, tau_out, done, s);
 }
@@ -455,8 +456,8 @@ int check_sp2(const spamm_bsm* F, const sp2_params* p, const spamm_bsm* D) {
     if (p->graph_steps > 0 && p->keep_tape) return fail(SPAMM_EINVAL, "graph mode needs keep_tape = 0");
     if (p->keep_tape < 0 || p->keep_tape > p->n_max) return fail(SPAMM_EINVAL, "keep_tape must be in 0..n_max");
     if (p->bound_kind < 0 || p->bound_kind > 2) return fail(SPAMM_EINVAL, "bound_kind must be 0, 1 or 2");
-    if (p->bound_kind != 0 && p->precision != 0)
-        return fail(SPAMM_ENOTSUP, "the precision tiers select with Algorithm 3's bound (bound_kind 0)");
+    if (p->bound_kind != 0 && F->nb > kBoundMaxNb)
+        return fail(SPAMM_ENOTSUP, "the leaf-level bounds support nb <= %d", kBoundMaxNb);
     if (p->precision != 0 && F->b > 64) return fail(SPAMM_ENOTSUP, "the precision tiers support leaf 32 and 64");
     if (p->precision != 0 && !(p->tier_split > 0.0 && p->tier_split < 1.0))
         return fail(SPAMM_EINVAL, "tier_split must be in (0, 1)");
@@ -590,7 +591,7 @@ int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, i
     const int kind = (flags & SPAMM_BOUND_FLAT) ? 1 : ((flags & SPAMM_BOUND_SUM) ? 2 : 0);
     if ((flags & SPAMM_BOUND_FLAT) && (flags & SPAMM_BOUND_SUM))
         return fail(SPAMM_EINVAL, "choose one of SPAMM_BOUND_FLAT and SPAMM_BOUND_SUM");
-    if (kind != 0 && mode != 0) return fail(SPAMM_EINVAL, "the leaf-level bounds have no tier mode");
+    if (kind != 0 && A->nb > kBoundMaxNb) return fail(SPAMM_ENOTSUP, "the leaf-level bounds support nb <= %d", kBoundMaxNb);
     size_t need = spamm_sweep_workspace_bytes(A->nb, N);
     if (!ws || ws_bytes < need) return fail(SPAMM_EWORKSPACE, "sweep needs %zu workspace bytes", need);
     hipStream_t s = (hipStream_t)stream;
@@ -608,6 +609,7 @@ int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, i
     fill_i32(w.ovf, 1, 0, s);
     if (kind != 0)
         run_sweep_leaf(view(A), view(B), (flags & SPAMM_B_TRANSPOSED) ? 1 : 0, tau, N, budget, budget_host, kind,
+                       mode, tau0_dev, c_low,
                        bound_out, idx_out, tau_out, w, nullptr, s);
     else
         run_sweep(view(A), view(B), (flags & SPAMM_B_TRANSPOSED) ? 1 : 0, tau, N, budget, budget_host, mode, tau0_dev,
@@ -872,7 +874,8 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                             hipStream_t st) -> int {
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
         if (p->variant != 2 && p->bound_kind != 0)
-            run_sweep_leaf(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, p->bound_kind, w.bound, &w.ctl->idx,
+            run_sweep_leaf(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, p->bound_kind, 0, nullptr, 0.0,
+                           w.bound, &w.ctl->idx,
                            &w.ctl->tau, w.sw, done, st);
         else if (p->variant != 2)
             run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
@@ -880,8 +883,12 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
         if (tiered) {
             // largest low-precision limit whose bound (skipped p plus c_low p for the low
             // tier) stays below the whole product budget
-            run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2, &w.ctl->sidx,
-                      &w.ctl->sigma, w.sw, done, st);
+            if (p->bound_kind != 0)
+                run_sweep_leaf(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, p->bound_kind, 1, &w.ctl->tau, c_low,
+                               w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st);
+            else
+                run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2,
+                          &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st);
             if (p->precision == 2)
                 launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp,
                                  done, st);
@@ -1523,15 +1530,21 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             MatView xv = view(&w.X[par]);
             MatView nv = view(&w.X[1 - par]);
             if (pq->variant != 2 && pq->bound_kind != 0)
-                run_sweep_leaf(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, pq->bound_kind, w.bound,
+                run_sweep_leaf(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, pq->bound_kind, 0, nullptr, 0.0,
+                               w.bound,
                                &w.ctl->idx, &w.ctl->tau, w.sw, done, gg.cs);
             else if (pq->variant != 2)
                 run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
                           &w.ctl->tau, w.sw, done, gg.cs);
             if (tiered) {
-                run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau,
-                          tier_constant(pq->precision, F[q].b), w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done,
-                          gg.cs);
+                if (pq->bound_kind != 0)
+                    run_sweep_leaf(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget, 0.0, pq->bound_kind, 1, &w.ctl->tau,
+                                   tier_constant(pq->precision, F[q].b), w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw,
+                                   done, gg.cs);
+                else
+                    run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau,
+                              tier_constant(pq->precision, F[q].b), w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done,
+                              gg.cs);
                 if (pq->precision == 2)
                     launch_to_bf16x2(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32),
                                      w.xexp, done, gg.cs);

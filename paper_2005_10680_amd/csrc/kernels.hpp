@@ -162,11 +162,15 @@ void launch_adj_fbar(const MatView& F, const int32_t* map0, const double* g0, co
                      hipStream_t s);
 
 // bounds.hip: leaf-level bounds B_flat (flat = 1) / B_sum (flat = 0) for the N
-// candidates into out [N]; part holds bound_part_waves(nb) * N doubles
+// candidates into out [N] (mode 1: tier mode, tau0 the fixed skip threshold,
+// c_low the low tier's per-pair factor); part holds bound_part_waves(nb) * N
+// doubles
+constexpr int kBoundMaxNb = 2048;
 int64_t bound_part_waves(int nb);
 void launch_bound_leaf(int nb, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
                        const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
-                       int N, int flat, double* part, double* out, const int32_t* done, hipStream_t s);
+                       int N, int flat, int mode, const double* tau0, double c_low, double* part, double* out,
+                       const int32_t* done, hipStream_t s);
 
 // control.hip
 void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,

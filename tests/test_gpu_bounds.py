@@ -153,11 +153,79 @@ def test_leaf_bounds_rejected_arguments():
                                        ws.numel(), P._stream())
     both = P.B_TRANSPOSED | P.BOUND_FLAT | P.BOUND_SUM
     assert call(0, both) == P.SPAMM_EINVAL
-    assert call(1, P.B_TRANSPOSED | P.BOUND_FLAT) == P.SPAMM_EINVAL
+    assert call(2, P.B_TRANSPOSED | P.BOUND_FLAT) == P.SPAMM_EINVAL
     assert call(0, P.B_TRANSPOSED | P.BOUND_SUM | P.SYNC) == P.SPAMM_OK
-    with pytest.raises(Exception):
-        P.purify(P.BlockSparse.from_host(synth.sys3d(500, 3, 32)), 250, 1e-6, synth.tau_log(32),
-                 homo=-0.1, lumo=0.1, precision="fp32", bound="flat")
+    assert call(1, P.B_TRANSPOSED | P.BOUND_FLAT | P.SYNC) == P.SPAMM_OK
+
+
+@pytest.mark.parametrize("kind", ["flat", "sum"])
+def test_leaf_bounds_tier_mode(kind):
+    """Tier mode (skip p < tau0, c p from tau0 up to sigma_m) against the
+    oracle's, for the FP32 and split-BF16 constants and several tau0."""
+    X = sym_x(1500, 32, 2)
+    tl = synth.tau_log(32)
+    M = P.BlockSparse.from_host(X)
+    P.build_norms(M)
+    for prec in (1, 2):
+        c = oracle.tier_constant(prec, 32)
+        for t0 in (tl[10], tl[14], tl[20]):
+            bound, idx, tau = P.sweep_tau(M, M, tl, 1e-7, b_transposed=True, mode=1, tau0=t0, c_low=c,
+                                          bound=kind)
+            f, sm = oracle.cse_flat_sum(X, X, tl, mode=1, tau0=t0, c_low=c)
+            want = f if kind == "flat" else sm
+            tol = check_bounds(bound.cpu().numpy(), want, kind, X, X)
+            for budget in budgets_between(want, tol):
+                _, idx, tau = P.sweep_tau(M, M, tl, budget, b_transposed=True, mode=1, tau0=t0, c_low=c,
+                                          bound=kind)
+                oi, ot = oracle.select(want, tl, budget)
+                assert int(idx.item()) == oi and float(tau.item()) == ot
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_tiers_with_leaf_bound_teacher_forced(precision):
+    """Precision tiers selecting with B_flat, every step on the GPU's own
+    iterate: tau, sigma and the kept / low-tier pair counts equal the
+    oracle's wherever the budgets lie outside the bounds' rounding bands;
+    the run converges."""
+    n, b = 2048, 64
+    Fm = synth.sys3d(n, 12, b)
+    F = oracle.BSM.of(Fm)
+    w, Uv = np.linalg.eigh(F.to_dense())
+    n_occ = n // 2
+    taus = synth.tau_log(32)
+    prec = P.PRECISIONS[precision]
+    p = oracle.SP2Params(n_occ=n_occ, eps=1e-6, taus=taus, homo=w[n_occ - 1], lumo=w[n_occ], precision=prec,
+                         bound="flat")
+    G = P.BlockSparse.from_host(Fm)
+    res = P.purify(G, n_occ, 1e-6, taus, homo=w[n_occ - 1], lumo=w[n_occ], keep_tape=True, precision=precision,
+                   bound="flat")
+    c = oracle.tier_constant(prec, b)
+    steps = [lg for lg in res.logs if lg["branch"] >= 0]
+    checked, nlow = 0, 0
+    for t, lg in enumerate(steps):
+        X = to_oracle(res.tape(t))
+        nu = oracle.norms(X)[1]
+        tol = tol_for("flat", X, X)
+        budget = lg["delta"] / 2.0
+        f0, _ = oracle.cse_flat_sum(X, X, taus, nu, nu)
+        if np.any(np.abs(f0 - p.tier_split * budget) <= 2 * tol * f0):
+            continue
+        idx, tau = oracle.select(f0, taus, p.tier_split * budget)
+        assert lg["idx"] == idx and lg["tau"] == tau
+        f1, _ = oracle.cse_flat_sum(X, X, taus, nu, nu, mode=1, tau0=tau, c_low=c)
+        if np.any(np.abs(f1 - budget) <= 2 * tol * f1):
+            continue
+        sidx, sigma = oracle.select(f1, taus, budget)
+        assert lg["sidx"] == sidx and lg["sigma"] == sigma
+        K = oracle.kept(X, X, tau, True, nu, nu)
+        assert lg["npairs"] == K.npairs
+        low = K.npairs - oracle.kept(X, X, max(sigma, tau), True, nu, nu).npairs if sigma > tau else 0
+        assert lg["npairs_low"] == low
+        nlow += low
+        checked += 1
+    assert checked >= len(steps) - 2 and nlow > 0
+    Dref = Uv[:, :n_occ] @ Uv[:, :n_occ].T
+    assert np.linalg.norm(to_oracle(res.D).to_dense() - Dref) < 1e-6
 
 
 @pytest.mark.parametrize("kind", ["flat", "sum"])
