@@ -499,12 +499,19 @@ def map_gap(x: float, branch: int) -> float:
 
 def should_stop(e_hist: list, e_tol: float) -> bool:
     """Stop when |e| <= e_tol, or once two further steps failed to reduce |e|
-    after it fell below 1e-3 (rounding/truncation noise floor)."""
+    after it fell below 1e-3 (rounding/truncation noise floor), or once two
+    further steps failed to square it after it fell below 1e-8: there one
+    step of each SP2 polynomial takes every eigenvalue's distance d to
+    {0, 1} to at most 4 d^2, so |e_i| > 4 e_{i-2}^2 means the iterate is at
+    the noise floor (the quadratic-convergence test of parameterless
+    stopping criteria)."""
     if not e_hist:
         return False
     if abs(e_hist[-1]) <= e_tol:
         return True
     if len(e_hist) >= 3 and abs(e_hist[-3]) < 1e-3 and abs(e_hist[-1]) >= abs(e_hist[-3]):
+        return True
+    if len(e_hist) >= 3 and abs(e_hist[-3]) < 1e-8 and abs(e_hist[-1]) > 4.0 * e_hist[-3] * e_hist[-3]:
         return True
     return False
 
