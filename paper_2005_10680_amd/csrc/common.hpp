@@ -153,11 +153,15 @@ SPAMM_HD int sp2_choose_branch(double t1, double t2, int64_t n_occ) {
 }
 SPAMM_HD double sp2_map_gap(double x, int br) { return br == 0 ? x * x : 2.0 * x - x * x; }
 // stop when |e_i| <= e_tol, or at the noise floor: |e_i| >= |e_{i-2}| once
-// |e_{i-2}| < 1e-3.  e: the last n_e values, most recent first (n_e <= 3).
+// |e_{i-2}| < 1e-3, or |e_i| > 4 e_{i-2}^2 once |e_{i-2}| < 1e-8.
+// e: the last n_e values, most recent first (n_e <= 3).
 SPAMM_HD bool sp2_should_stop(const double* e, int n_e, double e_tol) {
     if (n_e < 1) return false;
     if (fabs(e[0]) <= e_tol) return true;
     if (n_e >= 3 && fabs(e[2]) < 1e-3 && fabs(e[0]) >= fabs(e[2])) return true;
+    // deep in the quadratic regime a step of each polynomial takes every
+    // eigenvalue's distance d to {0, 1} to at most 4 d^2: more is noise
+    if (n_e >= 3 && fabs(e[2]) < 1e-8 && fabs(e[0]) > 4.0 * e[2] * e[2]) return true;
     return false;
 }
 // RN(a - b) for double-doubles a = ahi + alo, b = bhi + blo
