@@ -404,6 +404,9 @@ struct Sp2Ws {
     sp2_iter_log* dlog;  // [kMaxLog] records written by the device control (graph mode)
 };
 
+// product groups of a batch: (leaf size, tier) pairs; leaf 32, 64, 128 in
+// FP64, leaf 32 and 64 in the two tiers
+constexpr int kBatchGroups = 7;
 constexpr int kMaxLog = 10002;  // n_max <= 10000, plus the stop record
 
 // x1_outside: the second iterate buffer X[1] is not carved (the batched
@@ -1316,8 +1319,8 @@ size_t purify_sp2_batched_workspace_bytes(int32_t nsys, const spamm_bsm* F, cons
         carve_sp2(c, F[q].nb, F[q].b, p[q].N, cap_blocks[q], max_pairs[q], 0, w, p[q].precision, true);
     }
     c.take<GemmArgs>(2 * (size_t)nsys);        // descriptors, two parities
-    c.take<int64_t>(2 * (size_t)(nsys + 1) * 5);  // out_off / pair_off per group (<= 5 groups)
-    c.take<int32_t>(16 * 5);                     // work counters per group
+    c.take<int64_t>(2 * (size_t)(nsys + 1) * kBatchGroups);  // out_off / pair_off per group
+    c.take<int32_t>(16 * kBatchGroups);                     // work counters per group
     c.take<Sp2Ctl*>(nsys);
     c.take<int32_t>(4);
     return c.off + 256;
@@ -1365,8 +1368,8 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
         W[q].X[1].n = (int64_t)F[q].nb * F[q].b;
     }
     GemmArgs* descs_dev = c.take<GemmArgs>(2 * (size_t)nsys);
-    int64_t* offs = c.take<int64_t>(2 * (size_t)(nsys + 1) * 5);
-    int32_t* counters = c.take<int32_t>(16 * 5);
+    int64_t* offs = c.take<int64_t>(2 * (size_t)(nsys + 1) * kBatchGroups);
+    int32_t* counters = c.take<int32_t>(16 * kBatchGroups);
     Sp2Ctl** ctls_dev = c.take<Sp2Ctl*>(nsys);
     int32_t* all_done = c.take<int32_t>(4);
     if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
@@ -1389,6 +1392,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
         }
         groups[gi].sys.push_back(q);
     }
+    if ((int)groups.size() > kBatchGroups) return fail(SPAMM_EINVAL, "more than %d product groups", kBatchGroups);
 
     // prologue of every system: X_0, its norms, the Gerschgorin bounds
     std::vector<int32_t> nf(nsys);

@@ -86,3 +86,23 @@ def test_batch_isolates_a_failing_system():
         single = P.purify(Fs[q], d[1], 1e-6, d[2], homo=d[3], lumo=d[4])
         same_logs(single.logs, res.logs[q])
         same_matrix(single.D, res.D[q])
+
+
+def test_batch_all_product_groups():
+    """Seven systems, one in each product group (leaf 32, 64, 128 in FP64;
+    leaf 32 and 64 in the FP32 and split-BF16 tiers): every system equals
+    its own single run."""
+    specs = [(32, "fp64"), (64, "fp64"), (128, "fp64"), (32, "fp32"), (64, "fp32"), (32, "bf16x3"), (64, "bf16x3")]
+    data, Fs, precs = [], [], []
+    for t, (b, prec) in enumerate(specs):
+        d = make("sys3d", 900 + 37 * t, b, 40 + t)
+        data.append(d)
+        Fs.append(P.BlockSparse.from_host(d[0]))
+        precs.append(prec)
+    res = P.purify_batched(Fs, [d[1] for d in data], 1e-6, [d[2] for d in data], [d[3] for d in data],
+                           [d[4] for d in data], precision=precs, graph_steps=4)
+    assert res.rc == P.SPAMM_OK
+    for q, (d, F) in enumerate(zip(data, Fs)):
+        single = P.purify(F, d[1], 1e-6, d[2], homo=d[3], lumo=d[4], precision=precs[q])
+        same_logs(single.logs, res.logs[q])
+        same_matrix(single.D, res.D[q])

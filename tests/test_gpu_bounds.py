@@ -271,28 +271,32 @@ def test_purify_leaf_bound_teacher_forced(kind):
 
 def test_leaf_bound_graph_and_batch_match_host_loop():
     """The graph-captured loop and the batched driver take the same
-    decisions with a leaf-level bound as the host loop does."""
-    cases = [(synth.sys3d(1500, 21, 64), "flat"), (synth.chain1d(1024, 4, 32), "sum"),
-             (synth.sys3d(1200, 22, 32), "tree")]
+    decisions with a leaf-level bound as the host loop does, also with a
+    precision tier (sigma selected with the same bound)."""
+    cases = [(synth.sys3d(1500, 21, 64), "flat", "fp64"), (synth.chain1d(1024, 4, 32), "sum", "fp64"),
+             (synth.sys3d(1200, 22, 32), "tree", "fp64"), (synth.sys3d(1400, 23, 64), "flat", "bf16x3"),
+             (synth.sys3d(1100, 24, 32), "sum", "fp32")]
     Fs, data = [], []
-    for Fm, kind in cases:
+    for Fm, kind, prec in cases:
         w = np.linalg.eigvalsh(oracle.BSM.of(Fm).to_dense())
         n = Fm.n
         Fs.append(P.BlockSparse.from_host(Fm))
-        data.append((n // 2, w[n // 2 - 1], w[n // 2], kind))
+        data.append((n // 2, w[n // 2 - 1], w[n // 2], kind, prec))
     taus = synth.tau_log(32)
-    singles = [P.purify(F, d[0], 1e-6, taus, homo=d[1], lumo=d[2], bound=d[3]) for F, d in zip(Fs, data)]
+    singles = [P.purify(F, d[0], 1e-6, taus, homo=d[1], lumo=d[2], bound=d[3], precision=d[4])
+               for F, d in zip(Fs, data)]
     for F, d, s in zip(Fs, data, singles):
-        g = P.purify(F, d[0], 1e-6, taus, homo=d[1], lumo=d[2], bound=d[3], graph_steps=4)
-        assert [lg["tau"] for lg in g.logs] == [lg["tau"] for lg in s.logs]
-        assert [lg["npairs"] for lg in g.logs] == [lg["npairs"] for lg in s.logs]
+        g = P.purify(F, d[0], 1e-6, taus, homo=d[1], lumo=d[2], bound=d[3], precision=d[4], graph_steps=4)
+        for f in ("tau", "sigma", "npairs", "npairs_low"):
+            assert [lg[f] for lg in g.logs] == [lg[f] for lg in s.logs], f
         assert np.array_equal(g.D.live()[2], s.D.live()[2])
+    assert sum(lg["npairs_low"] for lg in singles[3].logs) > 0
     res = P.purify_batched(Fs, [d[0] for d in data], 1e-6, taus, [d[1] for d in data], [d[2] for d in data],
-                           bound=[d[3] for d in data], graph_steps=4)
+                           bound=[d[3] for d in data], precision=[d[4] for d in data], graph_steps=4)
     assert res.rc == P.SPAMM_OK
     for q, s in enumerate(singles):
-        assert [lg["tau"] for lg in res.logs[q]] == [lg["tau"] for lg in s.logs]
-        assert [lg["npairs"] for lg in res.logs[q]] == [lg["npairs"] for lg in s.logs]
+        for f in ("tau", "sigma", "npairs", "npairs_low"):
+            assert [lg[f] for lg in res.logs[q]] == [lg[f] for lg in s.logs], (q, f)
         assert np.array_equal(res.D[q].live()[2], s.D.live()[2])
     # the leaf-level bounds admit larger thresholds than the recursive one
     t_flat = P.purify(Fs[0], data[0][0], 1e-6, taus, homo=data[0][1], lumo=data[0][2], bound="flat")
