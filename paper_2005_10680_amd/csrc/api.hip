@@ -722,8 +722,9 @@ int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* 
         launch_to_bf16x2(A->b, A->nslot, A->cap, A->brow, A->val, a16, ea, nullptr, s);
         launch_to_bf16x2(B->b, B->nslot, B->cap, B->brow, B->val, b16, eb, nullptr, s);
     } else {
-        launch_to_f32(A->b, A->nslot, A->cap, A->brow, A->val, a32, nullptr, s);
-        launch_to_f32(B->b, B->nslot, B->cap, B->brow, B->val, b32, nullptr, s);
+        // the ring kernel (B given transposed) reads rotated rows, the other path plain blocks
+        launch_to_f32(A->b, A->nslot, A->cap, A->brow, A->val, a32, btrans, nullptr, s);
+        launch_to_f32(B->b, B->nslot, B->cap, B->brow, B->val, b32, btrans, nullptr, s);
     }
     run_pairs(view(A), view(B), btrans, sym, tau_dev, sigma_dev, view(C), nullptr, w, nullptr, nullptr, nullptr, s);
     run_gemm(view(A), view(B), btrans, sym, view(C), nullptr, w, nullptr, nullptr, nullptr, nullptr, s,
@@ -896,7 +897,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                 launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp,
                                  done, st);
             else
-                launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, st);
+                launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, st);
         }
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));
         // kept pairs, output pattern and the leaf products (combined with X)
@@ -1553,7 +1554,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                     launch_to_bf16x2(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32),
                                      w.xexp, done, gg.cs);
                 else
-                    launch_to_f32(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, done, gg.cs);
+                    launch_to_f32(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, gg.cs);
             }
             run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
                       &w.ctl->branch, done, gg.cs);

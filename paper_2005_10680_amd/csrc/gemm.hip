@@ -390,13 +390,23 @@ SPAMM_DEV void dma_chunk(const char* __restrict__ src, char* lds_dst) {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// Row rotation of the split-BF16 LDS tiles: group g of row r sits at
+// position (g + r/4) mod 4 of its 64 B row, so the 16 rows one MFMA operand
+// read touches fall in 16 different bank quads.
+SPAMM_DEV int bf16_rot(int r) { return (r >> 2) & 3; }
+
+// Rotation of row k of an FP32 copy (the ring kernel's layout): element m of
+// row k at position (m + f32_rot(k)) mod b.  A read of four consecutive rows
+// (16 lanes each) then covers four different 16-float bank ranges; only
+// k mod 4 matters.
+template <int B>
+SPAMM_DEV int f32_rot(int k) { return B == 64 ? 16 * (k & 3) : 16 * ((k >> 1) & 1); }
+
 // Copy inner indices 32c .. 32c+31 of one split-BF16 block (hi part, then lo
 // part, each b rows of b bf16, row-major) into LDS: per part b rows of four
-// 16 B groups (8 inner indices each).  Group g of row r sits at position
-// (g + r/4) mod 4 of its row, so the 16 rows one MFMA operand read touches
-// fall in 16 different bank quads.  Every 1 KB piece is 64 lane-contiguous
-// 16 B copies, as the direct-to-LDS copy requires; each lane picks the
-// global source of its LDS position.
+// 16 B groups (8 inner indices each), rotated by bf16_rot.  Every 1 KB piece
+// is 64 lane-contiguous 16 B copies, as the direct-to-LDS copy requires;
+// each lane picks the global source of its LDS position.
 template <int B>
 SPAMM_DEV void dma_bf16_chunk(const char* __restrict__ blk, int chunk, char* lds_dst) {
     using R = RingCfg<B>;
@@ -407,7 +417,7 @@ SPAMM_DEV void dma_bf16_chunk(const char* __restrict__ blk, int chunk, char* lds
         const int piece = w + 4 * q;
         const int part = piece / PPP, pp = piece % PPP;
         const int pos = pp * 64 + lane;
-        const int row = pos >> 2, kg = ((pos & 3) - (row >> 2)) & 3;
+        const int row = pos >> 2, kg = ((pos & 3) - bf16_rot(row)) & 3;
         const char* src = blk + (size_t)part * B * B * 2 + (size_t)row * B * 2 + chunk * 64 + kg * 16;
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
                                          (__attribute__((address_space(3))) void*)(lds_dst + piece * 1024), 16, 0,
@@ -590,12 +600,12 @@ struct RingCtx {
         const char* sl = RingSlot<B, SLOT>::get();
         if (LOWT == 2 && st < nst_low) {
             // split-BF16 stage: 32 inner indices, parts hi and lo of A and B
-            // (swizzled rows of four 16 B groups, see dma_bf16_chunk); the A
+            // (rotated rows of four 16 B groups, see bf16_rot); the A
             // rows go in the order pi(m) = m/4 + 4(m%4) as in the FP32 tier
             const int mrow = ((lane & 15) >> 2) + 4 * (lane & 3);
             const int kg = lane >> 4;
             auto rd = [&](const char* part, int row) -> bf8 {
-                const int pos = row * 4 + ((kg + (row >> 2)) & 3);
+                const int pos = row * 4 + ((kg + bf16_rot(row)) & 3);
                 return *reinterpret_cast<const bf8*>(part + pos * 16);
             };
             const char* Ah = sl;
@@ -644,14 +654,19 @@ struct RingCtx {
             // share one layout, so a finished FP32 pair product adds straight
             // into the FP64 accumulator.
             const int mrow = ((lane & 15) >> 2) + 4 * (lane & 3);
+            // rows of the FP32 copies are rotated (f32_rot) so that the four
+            // k rows one read touches fall in different banks
+            const int rot = f32_rot<B>(lane >> 4);
 #pragma unroll
             for (int ks = 0; ks < R::KC32 / 4; ++ks) {
                 const int kr = ks * 4 + (lane >> 4);
                 float av[R::TM], bv[R::TN];
 #pragma unroll
-                for (int a = 0; a < R::TM; ++a) av[a] = As[kr * B + wm * R::TM * 16 + a * 16 + mrow];
+                for (int a = 0; a < R::TM; ++a)
+                    av[a] = As[kr * B + ((wm * R::TM * 16 + a * 16 + mrow + rot) & (B - 1))];
 #pragma unroll
-                for (int b = 0; b < R::TN; ++b) bv[b] = Bs[kr * B + wn * R::TN * 16 + b * 16 + (lane & 15)];
+                for (int b = 0; b < R::TN; ++b)
+                    bv[b] = Bs[kr * B + ((wn * R::TN * 16 + b * 16 + (lane & 15) + rot) & (B - 1))];
 #pragma unroll
                 for (int a = 0; a < R::TM; ++a)
 #pragma unroll
@@ -1031,11 +1046,13 @@ void launch_to_bf16x2(int b, const int32_t* nslot, int64_t cap, const int32_t* b
     }
 }
 
-// FP32 copies of the live blocks (round to nearest), for the low tier.
+// FP32 copies of the live blocks (round to nearest), for the low tier; with
+// swz the rows (columns of the column-major block, index k) are rotated by
+// f32_rot(k) for the ring kernel, else the copy keeps the block's layout.
 template <int B>
 __global__ __launch_bounds__(256) void k_to_f32(const int32_t* __restrict__ nslot_p, int64_t cap,
                                                const int32_t* __restrict__ brow, const double* __restrict__ val,
-                                               float* __restrict__ out, const int32_t* __restrict__ done) {
+                                               float* __restrict__ out, int swz, const int32_t* __restrict__ done) {
     if (done && *done) return;
     int64_t nslot = *nslot_p;
     if (nslot > cap) nslot = cap;
@@ -1046,18 +1063,24 @@ __global__ __launch_bounds__(256) void k_to_f32(const int32_t* __restrict__ nslo
         float2* dst = reinterpret_cast<float2*>(out + (size_t)s * B * B);
         for (int t = lane; t < B * B / 2; t += 64) {
             const double2 v = src[t];
-            dst[t] = float2{(float)v.x, (float)v.y};
+            int d = t;
+            if (swz) {
+                // element pair (m, m + 1) of row k, m even: stays a pair after the rotation
+                const int k = (2 * t) / B, m = (2 * t) % B;
+                d = (k * B + ((m + f32_rot<B>(k)) & (B - 1))) / 2;
+            }
+            dst[d] = float2{(float)v.x, (float)v.y};
         }
     }
 }
 
 void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
-                   const int32_t* done, hipStream_t s) {
+                   int swz, const int32_t* done, hipStream_t s) {
     const int grid = grid_for(cap, 4, 4096);
     switch (b) {
-        case 32: hipLaunchKernelGGL(k_to_f32<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, done); break;
-        case 64: hipLaunchKernelGGL(k_to_f32<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, done); break;
-        case 128: hipLaunchKernelGGL(k_to_f32<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, done); break;
+        case 32: hipLaunchKernelGGL(k_to_f32<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, swz, done); break;
+        case 64: hipLaunchKernelGGL(k_to_f32<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, swz, done); break;
+        case 128: hipLaunchKernelGGL(k_to_f32<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, 0, done); break;
     }
 }
 

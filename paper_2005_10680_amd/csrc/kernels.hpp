@@ -147,8 +147,9 @@ void launch_gemm_batch(int b, int low, const GemmArgs* descs_dev, int nsys, int6
 // in [1, 2), hi = RN_bf16, lo = RN_bf16(x 2^-e - hi); row-major per slot
 void launch_to_bf16x2(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, uint16_t* out,
                       int32_t* expo, const int32_t* done, hipStream_t s);
+// FP32 copies; swz = 1: rows rotated for the ring kernel (leaf 32 and 64), 0: the block's own layout
 void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
-                   const int32_t* done, hipStream_t s);
+                   int swz, const int32_t* done, hipStream_t s);
 
 // adjoint.hip
 void launch_sym_half(const MatView& D, const double* dval, double* gval, hipStream_t s);
