@@ -535,7 +535,8 @@ def protocol_leg(P, torch, D, taus, deltas=(1e-6, 1e-8, 1e-10), reps=3):
 
 def big_leg(P, torch, synth, reps=1):
     """The 65536 workload (3D system, seed 3, leaf 64): time to D~ in FP64
-    and with the FP32 and split-BF16 leaf-product tiers, each D~ compared
+    and with the FP32 and split-BF16 leaf-product tiers (Algorithm 3's
+    bound), and in FP64 and split BF16 selecting with B_flat, each D~ compared
     with a reference run of the FP64 path at a 100 times smaller per-step
     delta (no dense eigensolver at this size; the per-step delta is a
     constant, 1e-9)."""
@@ -549,8 +550,8 @@ def big_leg(P, torch, synth, reps=1):
     nb = F.nb
     n_occ = n // 2
 
-    def run(precision, dconst):
-        return P.purify(F, n_occ, 1e-6, taus, delta_const=dconst, cap=nb * nb, precision=precision)
+    def run(precision, dconst, bound="tree"):
+        return P.purify(F, n_occ, 1e-6, taus, delta_const=dconst, cap=nb * nb, precision=precision, bound=bound)
 
     def keep_d(res):
         """A compact device copy of the result (only its live slots)."""
@@ -574,21 +575,23 @@ def big_leg(P, torch, synth, reps=1):
            "reference": {"delta_const": 1e-11, "iterations": len(rsteps),
                          "kept_pairs": int(sum(lg["npairs"] for lg in rsteps))}}
     base_t = None
-    for prec in ("fp64", "fp32", "bf16x3"):
-        run(prec, 1e-9)                         # warm-up
-        t, r = timed(lambda: run(prec, 1e-9), torch, reps)
+    for prec, bound in (("fp64", "tree"), ("fp32", "tree"), ("bf16x3", "tree"), ("fp64", "flat"),
+                        ("bf16x3", "flat")):
+        key = prec if bound == "tree" else f"{prec}_flat"
+        run(prec, 1e-9, bound)                  # warm-up
+        t, r = timed(lambda: run(prec, 1e-9, bound), torch, reps)
         st = [lg for lg in r.logs if lg["branch"] >= 0]
         pairs = sum(lg["npairs"] for lg in st)
         low = sum(lg["npairs_low"] for lg in st)
         err = fro_diff(r.D, Dref, torch)
-        base_t = t if prec == "fp64" else base_t
-        out[prec] = {"sp2_time_s": round(t, 4), "iterations": len(st), "kept_pairs": int(pairs),
+        base_t = t if key == "fp64" else base_t
+        out[key] = {"bound": bound, "sp2_time_s": round(t, 4), "iterations": len(st), "kept_pairs": int(pairs),
                      "low_tier_pairs": int(low), "kept_TFLOP_per_s": round(pairs * 2.0 * b ** 3 / t / 1e12, 3),
                      "fro_err_vs_reference": err, "peak_blocks": int(max(lg["nslot_hat"] for lg in st)),
                      "speedup_vs_fp64": round(base_t / t, 4),
                      "phase_ms": {k: round(sum(lg[k] for lg in st), 2)
                                   for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc")}}
-        log(f"big {prec}: {t:.3f} s, {len(st)} iterations, low-tier {low}/{pairs}, err vs reference {err:.3e}")
+        log(f"big {key}: {t:.3f} s, {len(st)} iterations, low-tier {low}/{pairs}, err vs reference {err:.3e}")
         del r
         torch.cuda.empty_cache()
     del Dref, F

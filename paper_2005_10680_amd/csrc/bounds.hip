@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_bound_final(const double* __restrict__ 
 int64_t bound_part_waves(int nb) {
     const int64_t nout = (int64_t)nb * nb;
     int64_t blocks = (nout + 3) / 4;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 2048) blocks = 2048;
     return blocks * 4;
 }
 
