@@ -51,6 +51,13 @@ int num_cus() {
     return cached;
 }
 
+// Pair lists use 32-bit offsets: a capacity derived from the workspace is
+// capped below 2^31, so that a longer list reports SPAMM_ECAPACITY.
+int64_t clamp_pairs(int64_t max_pairs) {
+    const int64_t lim = ((int64_t)1 << 31) - 1;
+    return max_pairs < lim ? max_pairs : lim;
+}
+
 int check_bsm(const spamm_bsm* X, const char* name, bool need_norms) {
     if (!X) return fail(SPAMM_EINVAL, "%s is NULL", name);
     if (X->n <= 0) return fail(SPAMM_EINVAL, "%s: n must be positive", name);
@@ -647,7 +654,7 @@ int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev
     if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "multiply needs at least %zu workspace bytes", base);
     // pair capacity: what the workspace holds beyond the base (512 bytes slack
     // cover the alignment of the carved arrays)
-    const int64_t max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
+    const int64_t max_pairs = ws_bytes > base + 512 ? clamp_pairs((int64_t)((ws_bytes - base - 512) / sizeof(int2))) : 0;
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     MulWs w;
@@ -705,7 +712,7 @@ int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* 
     if (bf16 && !btrans) return fail(SPAMM_ENOTSUP, "the split-BF16 tier needs SPAMM_B_TRANSPOSED");
     const size_t base = spamm_multiply_tiered_workspace_bytes(A->nb, A->cap, B->cap, A->b, 0);
     if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "tiered multiply needs at least %zu bytes", base);
-    const int64_t max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
+    const int64_t max_pairs = ws_bytes > base + 512 ? clamp_pairs((int64_t)((ws_bytes - base - 512) / sizeof(int2))) : 0;
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     float* a32 = c.take<float>((size_t)A->cap * A->b * A->b);
@@ -812,7 +819,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     {
         size_t base = purify_sp2_workspace_bytes(nb, b, p->N, cap, 0, tape_steps, p->precision);
         if (!ws || ws_bytes < base) return fail(SPAMM_EWORKSPACE, "purify needs at least %zu workspace bytes", base);
-        max_pairs = ws_bytes > base + 512 ? (int64_t)((ws_bytes - base - 512) / sizeof(int2)) : 0;
+        max_pairs = ws_bytes > base + 512 ? clamp_pairs((int64_t)((ws_bytes - base - 512) / sizeof(int2))) : 0;
     }
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
@@ -1122,8 +1129,7 @@ int spamm_adjoint_step(const spamm_bsm* X, const spamm_bsm* G, double tau, int32
     const int64_t cap = X->cap;
     const size_t base = spamm_adjoint_step_workspace_bytes(X->nb, cap, 0);
     if (!ws || ws_bytes < base + 512) return fail(SPAMM_EWORKSPACE, "adjoint step needs more than %zu workspace bytes", base);
-    const int64_t max_pairs = (int64_t)((ws_bytes - base - 512) / sizeof(int2));
-    if (max_pairs >= ((int64_t)1 << 31)) return fail(SPAMM_EINVAL, "pair capacity must stay below 2^31");
+    const int64_t max_pairs = clamp_pairs((int64_t)((ws_bytes - base - 512) / sizeof(int2)));
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     AdjWs w;
@@ -1233,8 +1239,7 @@ int purify_sp2_adjoint(const spamm_bsm* F, const sp2_params* p, const spamm_bsm*
     // the pair lists of the reverse step and (with checkpoints) of the
     // recomputation share what is left of the workspace
     const int64_t per_pair = every > 1 ? 2 * (int64_t)sizeof(int2) : (int64_t)sizeof(int2);
-    const int64_t max_pairs = (int64_t)((ws_bytes - base - 512) / per_pair);
-    if (max_pairs >= ((int64_t)1 << 31)) return fail(SPAMM_EINVAL, "pair capacity must stay below 2^31");
+    const int64_t max_pairs = clamp_pairs((int64_t)((ws_bytes - base - 512) / per_pair));
     hipStream_t s = (hipStream_t)stream;
     Carver c(ws);
     AdjRunWs w;

@@ -100,6 +100,8 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
         if (npairs > cap_pairs) atomicOr(ovf, kOvfPairs);
         if (nout > cap_out) atomicOr(ovf, kOvfOut);
     }
+    // an overflowing list is reported, not filled (its 32-bit offsets may have wrapped)
+    if (npairs > cap_pairs) return;
     for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < PP; z += (int64_t)gridDim.x * blockDim.x) {
         if (cnt[z] == 0) continue;
         uint32_t i, j;
