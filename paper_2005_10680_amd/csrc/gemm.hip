@@ -716,21 +716,30 @@ struct RingCtx {
     }
 };
 
-// Multiply one output block (i, j) from its pairs p0 .. p1 (the first nlow of
-// them FP32-tier) and write it (and its mirror) through the epilogue tile:
-// the combine 2X - C when beta.  d names the output's matrices.
+// One output block (i, j) on the ring, in three parts so that the next
+// output's first copies overlap this output's epilogue:
+//   ring_begin     binds pairs p0 .. p1 (the first nlow low-tier) and issues
+//                  the first NS - 1 stages into ring slots 0 .. NS - 2;
+//   ring_multiply  runs every stage; returns with nothing in flight and all
+//                  waves past their last read of the ring;
+//   ring_epilogue  writes the block (and its mirror) through ring slot NS - 1
+//                  used as a tile of EPC columns: the combine 2X - C when beta.
 template <int B, int LOWT>
-SPAMM_DEV void ring_output(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int j, int p0, int p1, int nlow,
-                           bool beta, double* ldsd) {
+SPAMM_DEV void ring_begin(RingCtx<B, LOWT>& cx, int p0, int p1, int nlow) {
     using R = RingCfg<B>;
-    constexpr int PC = 8;  // epilogue columns per pass
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
     cx.p0 = p0;
     cx.nlow = LOWT ? nlow : 0;
     cx.nst_low = cx.nlow * R::CH32;
     cx.nst = cx.nst_low + (p1 - p0 - cx.nlow) * R::CH64;
     const int nst = cx.nst;
+    if (0 < nst) cx.template issue<0>(0);
+    if (R::NS > 2 && 1 < nst) cx.template issue<1 % R::NS>(1);
+    if (R::NS > 3 && 2 < nst) cx.template issue<2 % R::NS>(2);
+}
+
+template <int B, int LOWT>
+SPAMM_DEV void ring_multiply(RingCtx<B, LOWT>& cx) {
+    using R = RingCfg<B>;
 #pragma unroll
     for (int a = 0; a < R::TM; ++a)
 #pragma unroll
@@ -738,10 +747,7 @@ SPAMM_DEV void ring_output(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int j
             cx.acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
             if constexpr (LOWT != 0) cx.acc32[a][b] = f4{0.f, 0.f, 0.f, 0.f};
         }
-    wait_vmcnt<0>();  // nothing of the previous output stays in flight
-    if (0 < nst) cx.template issue<0>(0);
-    if (R::NS > 2 && 1 < nst) cx.template issue<1 % R::NS>(1);
-    if (R::NS > 3 && 2 < nst) cx.template issue<2 % R::NS>(2);
+    const int nst = cx.nst;
     for (int st = 0; st < nst; st += R::NS) {
         cx.template step<0>(st);
         if (st + 1 < nst) cx.template step<1 % R::NS>(st + 1);
@@ -750,8 +756,16 @@ SPAMM_DEV void ring_output(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int j
     }
     wait_vmcnt<0>();
     __syncthreads();
+}
 
-    // ---------------- epilogue through the LDS tile ----------------
+template <int B, int LOWT>
+SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int j, bool beta) {
+    using R = RingCfg<B>;
+    constexpr int PC = 16;  // epilogue columns per pass
+    static_assert(PC * R::LDT * 8 <= R::STAGE && B % PC == 0, "epilogue tile fits one ring slot");
+    double* ldsd = reinterpret_cast<double*>(RingSlot<B, R::NS - 1>::get());
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
     const int sh = d.map_out[(size_t)i * d.nb + j];
     const int sht = (d.sym && i != j) ? d.map_out[(size_t)j * d.nb + i] : -1;
     const int sx = beta ? d.mapX[(size_t)i * d.nb + j] : -1;
@@ -812,7 +826,6 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void k_gemm_ring(GemmArgs g) {
     using R = RingCfg<B>;
     static_assert(R::NS >= 2 && R::NS <= 4, "ring depth");
-    __shared__ double ldsd[8 * R::LDT];
     __shared__ int s_o, s_lo, s_hi;
     if (g.done && *g.done) return;
     if (g.ovf && *g.ovf) return;
@@ -830,18 +843,34 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
     const bool beta = g.mapX && g.branch && (*g.branch == 1);
     RingCtx<B, LOWT> cx;
     cx.bind(g);
-    while (true) {
+    // next output of this XCD's range (wave-uniform, in scalar registers, so
+    // the pair list is read with scalar loads that never wait behind the
+    // copies in flight)
+    auto fetch = [&]() -> int {
         if (tid == 0) s_o = lo + atomicAdd(&g.counters[xcd], 1);
         __syncthreads();
-        // wave-uniform values in scalar registers, so the pair list is read
-        // with scalar loads that never wait behind the copies in flight
         const int o = __builtin_amdgcn_readfirstlane(s_o);
         __syncthreads();
-        if (o >= hi) break;
-        const int i = const_ld(g.oi, o), j = const_ld(g.oj, o);
-        const int p0 = const_ld(g.optr, o), p1 = const_ld(g.optr, o + 1);
-        const int nlow = LOWT ? const_ld(g.olow, o) : 0;
-        ring_output<B, LOWT>(cx, g, i, j, p0, p1, nlow, beta, ldsd);
+        return o;
+    };
+    int o = fetch();
+    if (o >= hi) return;
+    int i = const_ld(g.oi, o), j = const_ld(g.oj, o);
+    ring_begin<B, LOWT>(cx, const_ld(g.optr, o), const_ld(g.optr, o + 1), LOWT ? const_ld(g.olow, o) : 0);
+    while (true) {
+        ring_multiply<B, LOWT>(cx);
+        const int on = fetch();
+        int in = 0, jn = 0;
+        if (on < hi) {
+            in = const_ld(g.oi, on);
+            jn = const_ld(g.oj, on);
+            ring_begin<B, LOWT>(cx, const_ld(g.optr, on), const_ld(g.optr, on + 1), LOWT ? const_ld(g.olow, on) : 0);
+        }
+        ring_epilogue<B, LOWT>(cx, g, i, j, beta);
+        wait_vmcnt<0>();  // the epilogue's accesses and the next output's first copies
+        if (on >= hi) break;
+        i = in;
+        j = jn;
     }
 }
 
@@ -854,8 +883,6 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void k_gemm_ring_batch(
     const GemmArgs* __restrict__ descs, int nsys, const int64_t* __restrict__ out_off,
     const int64_t* __restrict__ pair_off, int32_t* __restrict__ counters) {
-    using R = RingCfg<B>;
-    __shared__ double ldsd[8 * R::LDT];
     __shared__ int s_o, s_lo, s_hi;
     const int tid = threadIdx.x;
     const int64_t nout = out_off[nsys];
@@ -881,21 +908,42 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
     __syncthreads();
     const int lo = __builtin_amdgcn_readfirstlane(s_lo), hi = __builtin_amdgcn_readfirstlane(s_hi);
     RingCtx<B, LOWT> cx;
-    while (true) {
+    auto fetch = [&]() -> int {
         if (tid == 0) s_o = lo + atomicAdd(&counters[xcd], 1);
         __syncthreads();
         const int o = __builtin_amdgcn_readfirstlane(s_o);
         __syncthreads();
-        if (o >= hi) break;
+        return o;
+    };
+    // bind output o (its system's descriptor) and issue its first stages
+    auto begin = [&](int o, const GemmArgs*& dp, int& i, int& j) {
         const int sy = __builtin_amdgcn_readfirstlane(sys_of(o));
-        const GemmArgs& d = descs[sy];
+        dp = &descs[sy];
+        const GemmArgs& d = *dp;
         const int ol = o - (int)out_off[sy];
-        const int i = const_ld(d.oi, ol), j = const_ld(d.oj, ol);
-        const int p0 = const_ld(d.optr, ol), p1 = const_ld(d.optr, ol + 1);
-        const int nlow = LOWT ? const_ld(d.olow, ol) : 0;
-        const bool beta = d.mapX && d.branch && (*d.branch == 1);
+        i = const_ld(d.oi, ol);
+        j = const_ld(d.oj, ol);
         cx.bind(d);
-        ring_output<B, LOWT>(cx, d, i, j, p0, p1, nlow, beta, ldsd);
+        ring_begin<B, LOWT>(cx, const_ld(d.optr, ol), const_ld(d.optr, ol + 1), LOWT ? const_ld(d.olow, ol) : 0);
+    };
+    int o = fetch();
+    if (o >= hi) return;
+    const GemmArgs* dc = nullptr;
+    int i = 0, j = 0;
+    begin(o, dc, i, j);
+    while (true) {
+        ring_multiply<B, LOWT>(cx);
+        const int on = fetch();
+        const GemmArgs* dn = nullptr;
+        int in = 0, jn = 0;
+        if (on < hi) begin(on, dn, in, jn);
+        const bool beta = dc->mapX && dc->branch && (*dc->branch == 1);
+        ring_epilogue<B, LOWT>(cx, *dc, i, j, beta);
+        wait_vmcnt<0>();  // the epilogue's accesses and the next output's first copies
+        if (on >= hi) break;
+        dc = dn;
+        i = in;
+        j = jn;
     }
 }
 
