@@ -10,8 +10,9 @@ and uses only what the oracle computes quickly at any size:
   selected candidate and the kept-pair counts equal the oracle's; sampled
   blocks of the next iterate equal the oracle's products combined with the
   step polynomial within a rounding bound; blocks the truncation removed
-  are below its budget; the result has trace n_occ, is idempotent and
-  commutes with F.
+  are below its budget; a mid-run iterate truncated by the library and by
+  the oracle loses exactly the same blocks; the result has trace n_occ, is
+  idempotent and commutes with F.
 * 3D system n = 65536, leaf 64, seed 3, FP64 and both precision tiers:
   the first step, with the same checks; in the tiers the sampled
   blocks are within the per-block tier bound (c times the sum of the norm
@@ -144,6 +145,21 @@ def test_sys3d_16384_fp64_full_run():
             X, nu_g = to_oracle(res.tape(t))
             check_step(X, nu_g, lg, xh, xl, p, res.tape(t + 1), rng)
         xh, xl = oracle.map_gap(xh, lg["branch"]), oracle.map_gap(xl, lg["branch"])
+    # truncation at full size: a mid-run iterate truncated by the library and
+    # by the oracle at several budgets removes exactly the same blocks
+    mid = len(steps) // 2
+    Xm, _ = to_oracle(res.tape(mid))
+    tot = float(np.sqrt(np.sum(oracle.norms(Xm)[0])))
+    for delta in (tot * 1e-9, tot * 1e-6, tot * 1e-3):
+        M = P.BlockSparse.from_host(Xm)
+        P.build_norms(M)
+        out = P.truncate(M, delta)
+        Ot, info = oracle.truncate(Xm, delta)
+        Mo, _ = to_oracle(M)
+        assert np.array_equal(Mo.keys(), Ot.sorted().keys())
+        assert int(out[0].item()) == info.removed_keys.shape[0]
+        del M
+    del Xm
     # properties of the result at any size: trace, idempotency, commutation with F
     D = res.D
     Do, _ = to_oracle(D)
