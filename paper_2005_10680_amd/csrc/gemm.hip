@@ -363,7 +363,7 @@ struct RingCfg {
     // waves per SIMD the register allocation aims for (LDS allows 3
     // workgroups per CU at leaf 64)
     template <int LOWT>
-    static constexpr int waves() { return B == 32 ? 4 : (B == 64 ? (LOWT ? 2 : 3) : 1); }
+    static constexpr int waves() { return B == 32 ? 4 : (B == 64 ? 3 : 1); }
 };
 
 template <int V>
@@ -689,8 +689,7 @@ struct RingCtx {
             const uint32_t lbase = lds_addr(sl);
             const uint32_t a0 = lbase + 8u * (uint32_t)((lane >> 4) * B + wm * R::TM * 16 + (lane & 15));
             const uint32_t b0 = lbase + R::OPB + 8u * (uint32_t)((lane >> 4) * B + wn * R::TN * 16 + (lane & 15));
-#pragma unroll
-            for (int ks = 0; ks < R::KC64 / 4; ++ks) {
+            auto kstep = [&](int ks) {
                 double av[R::TM], bv[R::TN];
                 lds_read_tiles<R::TM>(a0 + (uint32_t)(ks * 4 * B * 8), b0 + (uint32_t)(ks * 4 * B * 8), av, bv);
 #pragma unroll
@@ -698,6 +697,15 @@ struct RingCtx {
 #pragma unroll
                     for (int b = 0; b < R::TN; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+            };
+            if constexpr (LOWT == 0) {
+#pragma unroll
+                for (int ks = 0; ks < R::KC64 / 4; ++ks) kstep(ks);
+            } else {
+                // the tier kernels unroll the FP64 stages by two so that their
+                // registers fit three waves per SIMD
+#pragma unroll 2
+                for (int ks = 0; ks < R::KC64 / 4; ++ks) kstep(ks);
             }
         }
     }
