@@ -287,6 +287,7 @@ def main():
 
     if not args.no_protocol:
         out["protocol"] = protocol_leg(P, torch, res.D, taus)
+        out["chain1024"] = chain_leg(P, torch, synth)
 
     if args.batch > 0:
         out["batched"] = batch_leg(args, dev, P, synth, batch_mats)
@@ -531,6 +532,32 @@ def protocol_leg(P, torch, D, taus, deltas=(1e-6, 1e-8, 1e-10), reps=3):
     del Cx, Ca, Ct
     torch.cuda.empty_cache()
     return rows
+
+
+def chain_leg(P, torch, synth, reps=20):
+    """The small chain workload (n = 1024, leaf 32, the paper's 350
+    candidates, seed 1): a few hundred kept pairs per step, so the host
+    loop's per-step launches and read-backs dominate; timed with the host
+    loop and with the graph-captured loop (poll every 8 steps), median of
+    reps, with the spectrum's gap from the committed dense eigenvalues."""
+    spec = load_spectrum("chain1d_n1024_s1_b32")
+    Fh = synth.chain1d(1024, 1, 32)
+    F = P.BlockSparse.from_host(Fh)
+    taus = synth.tau_paper()
+    kw = dict(homo=spec["homo"], lumo=spec["lumo"])
+    host = lambda: P.purify(F, 512, 1e-6, taus, **kw)
+    graph = lambda: P.purify(F, 512, 1e-6, taus, graph_steps=8, **kw)
+    host()
+    graph()
+    th, rh = timed(host, torch, reps)
+    tg, rg = timed(graph, torch, reps)
+    st = [lg for lg in rh.logs if lg["branch"] >= 0]
+    same = [lg["npairs"] for lg in rg.logs] == [lg["npairs"] for lg in rh.logs]
+    log(f"chain n=1024: host loop {1e3 * th:.2f} ms, graph loop {1e3 * tg:.2f} ms, {len(st)} iterations")
+    return {"workload": "sp2_hybrid_chain1d_n1024_leaf32_tau350_eps1e-6", "iterations": len(st),
+            "kept_pairs_per_run": int(sum(lg["npairs"] for lg in st)),
+            "host_loop_ms": round(1e3 * th, 3), "graph_loop_ms": round(1e3 * tg, 3),
+            "graph_speedup": round(th / tg, 3), "same_decisions": bool(same)}
 
 
 def big_leg(P, torch, synth, reps=1):
