@@ -388,6 +388,32 @@ SPAMM_DEV void dma_chunk(const char* __restrict__ src, char* lds_dst) {
     }
 }
 
+// Row rotation of the FP64 LDS tiles at leaf 32: row k (32 doubles, one
+// 256 B bank period) holds its source row rotated by 16 doubles when k is
+// odd, so the two k rows that 32 lanes of an operand read touch fall in
+// different bank halves.  Leaf 64 reads two 16-column tiles per row with one
+// ds_read2_b64 and keeps the plain layout.
+SPAMM_DEV int f64_rot32(int k) { return 16 * (k & 1); }
+
+// dma_chunk with the leaf-32 FP64 row rotation: each lane fetches the source
+// 16 bytes that belong at its LDS position
+template <int B>
+SPAMM_DEV void dma_chunk_rot(const char* __restrict__ src, char* lds_dst) {
+    static_assert(B == 32, "the rotation is for leaf 32");
+    using R = RingCfg<B>;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < R::NI; ++q) {
+        const int piece = w + 4 * q;
+        const int pos = piece * 1024 + lane * 16;            // LDS byte offset in the chunk
+        const int r = pos / (B * 8), p = (pos % (B * 8)) / 8;  // row, first of the lane's two doubles
+        const int sp = (p - f64_rot32(r)) & (B - 1);
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void*)(src + (size_t)r * B * 8 + (size_t)sp * 8),
+            (__attribute__((address_space(3))) void*)(lds_dst + piece * 1024), 16, 0, 0);
+    }
+}
+
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // Row rotation of the split-BF16 LDS tiles: group g of row r sits at
@@ -577,6 +603,7 @@ struct RingCtx {
         }
         const char* a0;
         const char* b0;
+        const bool f64 = !(LOWT == 1 && low);
         if (LOWT == 1 && low) {
             a0 = reinterpret_cast<const char*>(valA32 + (size_t)pr.x * B * B + (size_t)chunk * R::KC32 * B);
             b0 = reinterpret_cast<const char*>(valB32 + (size_t)pr.y * B * B + (size_t)chunk * R::KC32 * B);
@@ -588,6 +615,13 @@ struct RingCtx {
             // first operand comes from the B pool, the second from the A pool
             a0 = reinterpret_cast<const char*>(valB + (size_t)(~pr.x) * B * B + (size_t)chunk * R::KC64 * B);
             b0 = reinterpret_cast<const char*>(valA + (size_t)pr.y * B * B + (size_t)chunk * R::KC64 * B);
+        }
+        if constexpr (B == 32) {
+            if (f64) {
+                dma_chunk_rot<B>(a0, dst);
+                dma_chunk_rot<B>(b0, dst + R::OPB);
+                return;
+            }
         }
         dma_chunk<B>(a0, dst);
         dma_chunk<B>(b0, dst + R::OPB);
@@ -687,8 +721,12 @@ struct RingCtx {
         } else {
             // LDS byte addresses of this lane's first A and B element
             const uint32_t lbase = lds_addr(sl);
-            const uint32_t a0 = lbase + 8u * (uint32_t)((lane >> 4) * B + wm * R::TM * 16 + (lane & 15));
-            const uint32_t b0 = lbase + R::OPB + 8u * (uint32_t)((lane >> 4) * B + wn * R::TN * 16 + (lane & 15));
+            // (leaf 32: rows rotated by f64_rot32; k = 4 ks + (lane >> 4) has the parity of lane >> 4)
+            const int rot = B == 32 ? f64_rot32(lane >> 4) : 0;
+            const uint32_t a0 =
+                lbase + 8u * (uint32_t)((lane >> 4) * B + ((wm * R::TM * 16 + (lane & 15) + rot) & (B - 1)));
+            const uint32_t b0 =
+                lbase + R::OPB + 8u * (uint32_t)((lane >> 4) * B + ((wn * R::TN * 16 + (lane & 15) + rot) & (B - 1)));
             auto kstep = [&](int ks) {
                 double av[R::TM], bv[R::TN];
                 lds_read_tiles<R::TM>(a0 + (uint32_t)(ks * 4 * B * 8), b0 + (uint32_t)(ks * 4 * B * 8), av, bv);
