@@ -153,6 +153,11 @@ def main():
         "kept_pairs_per_run": int(sum(l["npairs"] for l in steps)),
         "phase_ms_per_run": {k: round(sum(l[k] for l in steps), 3)
                              for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc", "ms_total")},
+        # the HBM-bound norms pass over every block of X^ (8 b^2 bytes read
+        # per block); its phase also holds the pass-through copy of blocks
+        # no pair lands on, so the rate is a lower bound
+        "hbm_norms": hbm_rate(sum(l["nslot_hat"] for l in steps) * 8.0 * b * b,
+                              sum(l["ms_norms"] for l in steps)),
         "roofline": {"kernel": f"k_gemm_ring<{b},0>", "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
@@ -456,6 +461,12 @@ def fro_diff(A, B, torch):
         if bool(only.any()):
             tot += float((vb[s_b[only]] ** 2).sum().item())
     return math.sqrt(tot)
+
+
+def hbm_rate(nbytes, ms):
+    gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bytes_per_run": nbytes, "ms_per_run": round(ms, 3), "achieved_GB_per_s": round(gbs, 1),
+            "peak_GB_per_s": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def live_blocks(M):
