@@ -260,12 +260,16 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
                       w.ovf, done, s);
 }
 
-// Leaf products of the kept pairs into C's slots (combined with X when given).
-void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatView& C, const uint8_t* fromc,
+// Leaf products of the kept pairs into C's slots (combined with X when given);
+// with no.sq also the norms of the written blocks (the product's work
+// counters, reset before the product, hold the recheck count at [8]).
+// Returns -1 only for norms requested without the transposed-B layout.
+int run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatView& C, const uint8_t* fromc,
               MulWs& w, const int32_t* mapX, const double* valX, const int32_t* branch_dev, const int32_t* done,
               hipStream_t s, const float* valA32 = nullptr, const float* valB32 = nullptr,
               hipEvent_t ev_start = nullptr, hipEvent_t ev_end = nullptr, const uint16_t* valA16 = nullptr,
-              const uint16_t* valB16 = nullptr, const int32_t* expA = nullptr, const int32_t* expB = nullptr) {
+              const uint16_t* valB16 = nullptr, const int32_t* expA = nullptr, const int32_t* expB = nullptr,
+              NormOut no = NormOut()) {
     const int nb = A.nb;
     GemmArgs g;
     g.b = A.b;
@@ -295,8 +299,19 @@ void run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const Mat
     g.expA = expA;
     g.expB = expB;
     g.olow = (valA32 || valA16) ? w.olow : nullptr;
+    if (no.sq) {
+        // block norms in the product's epilogue (the ring kernels of the
+        // transposed-B layout only)
+        if (!btrans) return -1;
+        g.sq_out = no.sq;
+        g.sqlo_out = no.sqlo;
+        g.nrm_out = no.nrm;
+        g.recheck = no.recheck;
+        g.nrecheck = no.nrecheck;
+    }
     launch_gemm_f64(g, num_cus(), s, ev_start, ev_end);
-    if (mapX) launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s);
+    if (mapX) launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s, no);
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -407,6 +422,7 @@ struct Sp2Ws {
     double* bound2; // [N] sweep over the low-precision limit
     float* x32;     // FP32 copy of the current iterate (FP32 tier), or its split-BF16 parts
     int32_t* xexp;  // per-slot exponents of the split-BF16 parts
+    int32_t* recheck;  // [cap] slots whose norm the product kernels left to the norms kernel
     Sp2Ctl* ctl;
     sp2_iter_log* dlog;  // [kMaxLog] records written by the device control (graph mode)
 };
@@ -443,6 +459,7 @@ void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, 
     w.dlog = c.take<sp2_iter_log>(kMaxLog);
     w.x32 = precision ? c.take<float>((size_t)cap * b * b) : nullptr;
     w.xexp = precision == 2 ? c.take<int32_t>(cap) : nullptr;
+    w.recheck = c.take<int32_t>(cap);
 }
 
 // argument checks shared by the single and the batched purification
@@ -907,16 +924,25 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                 launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, st);
         }
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));
-        // kept pairs, output pattern and the leaf products (combined with X)
+        // kept pairs, output pattern and the leaf products (combined with X),
+        // with the block norms of the new iterate
+        NormOut step_norms;
+        step_norms.sq = nv.sq;
+        step_norms.sqlo = nv.sqlo;
+        step_norms.nrm = nv.norm;
+        step_norms.recheck = w.recheck;
+        step_norms.nrecheck = &w.mw.counters[8];
         run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
                   &w.ctl->branch, done, st);
         // evs[2]/evs[3] bracket the product kernel alone
-        run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, done, st,
-                 p->precision == 1 ? w.x32 : nullptr, p->precision == 1 ? w.x32 : nullptr, evs ? evs[2] : nullptr,
-                 evs ? evs[3] : nullptr, p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr,
-                 p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr,
-                 p->precision == 2 ? w.xexp : nullptr, p->precision == 2 ? w.xexp : nullptr);
-        launch_norms(b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, st, done);
+        const uint16_t* x16 = p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr;
+        const float* x32 = p->precision == 1 ? w.x32 : nullptr;
+        const int32_t* xexp = p->precision == 2 ? w.xexp : nullptr;
+        const int rg = run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, done, st, x32, x32,
+                                evs ? evs[2] : nullptr, evs ? evs[3] : nullptr, x16, x16, xexp, xexp, step_norms);
+        if (rg) return fail(SPAMM_EINVAL, "fused block norms need the transposed-B product");
+        launch_norms_listed(b, w.recheck, &w.mw.counters[8], nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, st,
+                            done);
         if (evs) HIP_TRY(hipEventRecord(evs[4], st));
         if (p->variant != 1)
             launch_truncate(nv, &w.ctl->delta, 0.0, tb_scale, w.trunc_tmp, cap, w.tstats, w.mw.ovf, done, st);

@@ -104,6 +104,37 @@ SPAMM_DEV dd dd_wave_sum(dd x) {
     return x;
 }
 
+// Sum of squares of a block's entries, for its exactly rounded norm: each
+// square is split exactly (x*x and fma(x, x, -x*x)) and accumulated in
+// double-double, in any order; the flags mark entries whose square may
+// overflow (special) or lose bits below the normal range (tiny).
+struct SqAcc {
+    dd acc = {0.0, 0.0};
+    bool special = false, tiny = false;
+};
+SPAMM_DEV void sq_add(SqAcc& a, double x) {
+    const double ax = fabs(x);
+    if (!(ax < 0x1p500)) a.special = true;          // huge, inf or NaN
+    if (ax != 0.0 && ax < 0x1p-480) a.tiny = true;   // two-product may be inexact
+    const double p = x * x;
+    const double pe = fma(x, x, -p);
+    a.acc = dd_add(a.acc, dd{p, pe});
+}
+// Whether acc.hi is the exactly rounded sum of squares: acc = hi + lo (the
+// whole block, at most 2^14 terms) is within hi * 2^-80 of the exact sum, so
+// hi is certain when hi + lo lies farther than that from the nearest
+// rounding boundary (hi + ulp/2 above, hi - ulp/2 below).
+SPAMM_DEV bool sq_certified(dd acc, bool special, bool tiny) {
+    if (special) return false;
+    const double eb = acc.hi * 0x1p-80 + (tiny ? 0x1p-1000 : 0.0);
+    if (acc.lo >= 0.0) {
+        const double up = nextafter(acc.hi, INFINITY) - acc.hi;
+        return (up - 2.0 * acc.lo) > 2.0 * eb;
+    }
+    const double dn = acc.hi - nextafter(acc.hi, 0.0);
+    return (dn + 2.0 * acc.lo) > 2.0 * eb;
+}
+
 // ---------------------------------------------------------------------------
 // Device control block of one purification (all decisions stay on device).
 // ---------------------------------------------------------------------------

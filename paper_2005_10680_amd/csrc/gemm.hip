@@ -25,7 +25,8 @@
 // list (Morton order) is cut into 8 contiguous ranges of equal kept-pair
 // count, and the workgroups of XCD x take outputs of range x from an atomic
 // counter, so neighbouring outputs -- which share A rows and B columns --
-// run under the same L2.  Every output is computed by exactly one workgroup
+// run under the same L2; a workgroup whose range is drained goes on with the
+// other ranges' counters, so the XCDs finish together.  Every output is computed by exactly one workgroup
 // in a fixed order: results are bitwise reproducible.
 #include <type_traits>
 
@@ -769,7 +770,8 @@ struct RingCtx {
 //   ring_multiply  runs every stage; returns with nothing in flight and all
 //                  waves past their last read of the ring;
 //   ring_epilogue  writes the block (and its mirror) through ring slot NS - 1
-//                  used as a tile of EPC columns: the combine 2X - C when beta.
+//                  used as a tile of EPC columns: the combine 2X - C when beta,
+//                  and their norm when asked for.
 template <int B, int LOWT>
 SPAMM_DEV void ring_begin(RingCtx<B, LOWT>& cx, int p0, int p1, int nlow) {
     using R = RingCfg<B>;
@@ -804,6 +806,47 @@ SPAMM_DEV void ring_multiply(RingCtx<B, LOWT>& cx) {
     __syncthreads();
 }
 
+// Norm of the block just written (and of its mirror, the same sum): the
+// four waves' double-double partial sums (a, with the flags fl_w: 1 special,
+// 2 tiny) are added in wave order; certified
+// results are stored, the rest listed for the norms kernel.  The partials'
+// LDS is next written in the following output's epilogue, after barriers
+// that thread 0 reaches only when done reading.
+SPAMM_DEV void block_norm_out(dd a, int fl_w, const GemmArgs& d, int sh, int sht) {
+    __shared__ double s_part[4][2];
+    __shared__ int s_flag[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (lane == 0) {
+        s_part[w][0] = a.hi;
+        s_part[w][1] = a.lo;
+        s_flag[w] = fl_w;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        dd t = {s_part[0][0], s_part[0][1]};
+        int fl = s_flag[0];
+        for (int q = 1; q < 4; ++q) {
+            t = dd_add(t, dd{s_part[q][0], s_part[q][1]});
+            fl |= s_flag[q];
+        }
+        if (sq_certified(t, fl & 1, fl & 2)) {
+            const double nv = sqrt(t.hi);
+            d.sq_out[sh] = t.hi;
+            d.sqlo_out[sh] = t.lo;
+            d.nrm_out[sh] = nv;
+            if (sht >= 0) {
+                d.sq_out[sht] = t.hi;
+                d.sqlo_out[sht] = t.lo;
+                d.nrm_out[sht] = nv;
+            }
+        } else {
+            const int q = atomicAdd(d.nrecheck, sht >= 0 ? 2 : 1);
+            d.recheck[q] = sh;
+            if (sht >= 0) d.recheck[q + 1] = sht;
+        }
+    }
+}
+
 template <int B, int LOWT>
 SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int j, bool beta) {
     using R = RingCfg<B>;
@@ -818,7 +861,17 @@ SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int
     double* dst = sh >= 0 ? d.val_out + (size_t)sh * B * B : nullptr;
     double* dstt = sht >= 0 ? d.val_out + (size_t)sht * B * B : nullptr;
     const double* xs = sx >= 0 ? d.valX + (size_t)sx * B * B : nullptr;
+    const bool want_norm = d.sq_out && dst;
+    // each lane's share of the block's sum of squares; in the tier kernels
+    // at leaf 64, whose registers are scarce, its running total waits in
+    // ring slot NS - 1 behind the epilogue tile between passes
+    constexpr bool kLdsSum = LOWT != 0 && B == 64;
+    constexpr int kSumOff = (PC * R::LDT * 8 + 15) / 16 * 16;
+    static_assert(!kLdsSum || kSumOff + 256 * 16 <= R::STAGE, "partial sums fit the ring slot");
+    dd* lsum = reinterpret_cast<dd*>(reinterpret_cast<char*>(ldsd) + kSumOff);
+    SqAcc sa;
     for (int pass = 0; pass < B / PC; ++pass) {
+        if (kLdsSum) sa.acc = dd{0.0, 0.0};
         const int c0 = pass * PC;
 #pragma unroll
         for (int a = 0; a < R::TM; ++a)
@@ -840,6 +893,7 @@ SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int
                 ldsd[cl * R::LDT + row] = v;
             }
             if (dst) dst[(size_t)(c0 + cl) * B + row] = v;
+            if (want_norm) sq_add(sa, v);
         }
         if (dstt) {
             __syncthreads();
@@ -848,7 +902,13 @@ SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int
                 dstt[(size_t)cp * B + c0 + rp] = ldsd[rp * R::LDT + cp];
             }
         }
+        if (kLdsSum && want_norm) lsum[tid] = pass ? dd_add(lsum[tid], sa.acc) : sa.acc;  // own entry
         __syncthreads();
+    }
+    if (want_norm) {
+        if (kLdsSum) sa.acc = lsum[tid];
+        const int fl = (__any(sa.special) ? 1 : 0) | (__any(sa.tiny) ? 2 : 0);
+        block_norm_out(dd_wave_sum(sa.acc), fl, d, sh, sht);
     }
 }
 
@@ -872,49 +932,61 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void k_gemm_ring(GemmArgs g) {
     using R = RingCfg<B>;
     static_assert(R::NS >= 2 && R::NS <= 4, "ring depth");
-    __shared__ int s_o, s_lo, s_hi;
+    __shared__ int s_o, s_cut[9];
     if (g.done && *g.done) return;
     if (g.ovf && *g.ovf) return;
     const int tid = threadIdx.x;
     const int64_t nout = *g.nout;
     const int xcd = blockIdx.x % 8;
-    if (tid == 0) {
+    if (tid < 9) {
         const int64_t np = g.optr[nout];
         auto pb = [&](int64_t o) -> int64_t { return g.optr[o]; };
-        s_lo = (int)xcd_cut(nout, np, xcd, pb);
-        s_hi = (int)xcd_cut(nout, np, xcd + 1, pb);
+        s_cut[tid] = (int)xcd_cut(nout, np, tid, pb);
     }
     __syncthreads();
-    const int lo = __builtin_amdgcn_readfirstlane(s_lo), hi = __builtin_amdgcn_readfirstlane(s_hi);
     const bool beta = g.mapX && g.branch && (*g.branch == 1);
     RingCtx<B, LOWT> cx;
     cx.bind(g);
-    // next output of this XCD's range (wave-uniform, in scalar registers, so
-    // the pair list is read with scalar loads that never wait behind the
-    // copies in flight)
+    // next output (wave-uniform, in scalar registers, so the pair list is
+    // read with scalar loads that never wait behind the copies in flight):
+    // from this XCD's range while it lasts, then from the other ranges in
+    // turn, so that no XCD idles while another still has outputs; -1 once
+    // every range is drained (at most 8 failed claims per workgroup)
+    int r = 0;
     auto fetch = [&]() -> int {
-        if (tid == 0) s_o = lo + atomicAdd(&g.counters[xcd], 1);
+        if (tid == 0) {
+            int on = -1;
+            for (; r < 8; ++r) {
+                const int x = (xcd + r) & 7;
+                const int c = s_cut[x] + atomicAdd(&g.counters[x], 1);
+                if (c < s_cut[x + 1]) {
+                    on = c;
+                    break;
+                }
+            }
+            s_o = on;
+        }
         __syncthreads();
         const int o = __builtin_amdgcn_readfirstlane(s_o);
         __syncthreads();
         return o;
     };
     int o = fetch();
-    if (o >= hi) return;
+    if (o < 0) return;
     int i = const_ld(g.oi, o), j = const_ld(g.oj, o);
     ring_begin<B, LOWT>(cx, const_ld(g.optr, o), const_ld(g.optr, o + 1), LOWT ? const_ld(g.olow, o) : 0);
     while (true) {
         ring_multiply<B, LOWT>(cx);
         const int on = fetch();
         int in = 0, jn = 0;
-        if (on < hi) {
+        if (on >= 0) {
             in = const_ld(g.oi, on);
             jn = const_ld(g.oj, on);
             ring_begin<B, LOWT>(cx, const_ld(g.optr, on), const_ld(g.optr, on + 1), LOWT ? const_ld(g.olow, on) : 0);
         }
         ring_epilogue<B, LOWT>(cx, g, i, j, beta);
         wait_vmcnt<0>();  // the epilogue's accesses and the next output's first copies
-        if (on >= hi) break;
+        if (on < 0) break;
         i = in;
         j = jn;
     }
@@ -929,7 +1001,7 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void k_gemm_ring_batch(
     const GemmArgs* __restrict__ descs, int nsys, const int64_t* __restrict__ out_off,
     const int64_t* __restrict__ pair_off, int32_t* __restrict__ counters) {
-    __shared__ int s_o, s_lo, s_hi;
+    __shared__ int s_o, s_cut[9];
     const int tid = threadIdx.x;
     const int64_t nout = out_off[nsys];
     const int xcd = blockIdx.x % 8;
@@ -941,21 +1013,33 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
         }
         return a;
     };
-    if (tid == 0) {
+    if (tid < 9) {
         const int64_t np = pair_off[nsys];
         auto pb = [&](int64_t o) -> int64_t {
             if (o >= nout) return np;
             const int sy = sys_of(o);
             return pair_off[sy] + descs[sy].optr[o - out_off[sy]];
         };
-        s_lo = (int)xcd_cut(nout, np, xcd, pb);
-        s_hi = (int)xcd_cut(nout, np, xcd + 1, pb);
+        s_cut[tid] = (int)xcd_cut(nout, np, tid, pb);
     }
     __syncthreads();
-    const int lo = __builtin_amdgcn_readfirstlane(s_lo), hi = __builtin_amdgcn_readfirstlane(s_hi);
     RingCtx<B, LOWT> cx;
+    // next output: this XCD's range first, then the other ranges (as in
+    // k_gemm_ring); -1 once all are drained
+    int r = 0;
     auto fetch = [&]() -> int {
-        if (tid == 0) s_o = lo + atomicAdd(&counters[xcd], 1);
+        if (tid == 0) {
+            int on = -1;
+            for (; r < 8; ++r) {
+                const int x = (xcd + r) & 7;
+                const int c = s_cut[x] + atomicAdd(&counters[x], 1);
+                if (c < s_cut[x + 1]) {
+                    on = c;
+                    break;
+                }
+            }
+            s_o = on;
+        }
         __syncthreads();
         const int o = __builtin_amdgcn_readfirstlane(s_o);
         __syncthreads();
@@ -973,7 +1057,7 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
         ring_begin<B, LOWT>(cx, const_ld(d.optr, ol), const_ld(d.optr, ol + 1), LOWT ? const_ld(d.olow, ol) : 0);
     };
     int o = fetch();
-    if (o >= hi) return;
+    if (o < 0) return;
     const GemmArgs* dc = nullptr;
     int i = 0, j = 0;
     begin(o, dc, i, j);
@@ -982,11 +1066,11 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
         const int on = fetch();
         const GemmArgs* dn = nullptr;
         int in = 0, jn = 0;
-        if (on < hi) begin(on, dn, in, jn);
+        if (on >= 0) begin(on, dn, in, jn);
         const bool beta = dc->mapX && dc->branch && (*dc->branch == 1);
         ring_epilogue<B, LOWT>(cx, *dc, i, j, beta);
         wait_vmcnt<0>();  // the epilogue's accesses and the next output's first copies
-        if (on >= hi) break;
+        if (on < 0) break;
         dc = dn;
         i = in;
         j = jn;

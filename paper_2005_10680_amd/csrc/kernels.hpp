@@ -24,6 +24,10 @@ struct MatView {
 // norms.hip
 void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, double* sq,
                   double* sqlo, double* nrm, hipStream_t s, const int32_t* done = nullptr);
+// norms of the *nlist slots in list (the blocks a producer could not certify)
+void launch_norms_listed(int b, const int32_t* list, const int32_t* nlist, int64_t cap, const int32_t* brow,
+                         const double* val, double* sq, double* sqlo, double* nrm, hipStream_t s,
+                         const int32_t* done = nullptr);
 size_t traces_temp_bytes();
 void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
                    const double* val, const double* sq, const double* sqlo, double* temp, double* out,
@@ -71,9 +75,18 @@ void launch_hat_flags(int nb, int P, const int32_t* cnt, int sym, const int32_t*
 void launch_hat_assign(int nb, int P, const int32_t* cnt, int sym, const int32_t* flag, const int32_t* slot,
                        const int64_t* nslot_total, int64_t cap, int32_t* map, int32_t* brow, int32_t* bcol,
                        int32_t* nslot, uint8_t* fromc, int32_t* ovf, const int32_t* done, hipStream_t s);
+// Block norm outputs of a kernel that writes blocks (all null: none); a
+// slot whose rounding cannot be certified goes to recheck[(*nrecheck)++].
+struct NormOut {
+    double* sq = nullptr;
+    double* sqlo = nullptr;
+    double* nrm = nullptr;
+    int32_t* recheck = nullptr;
+    int32_t* nrecheck = nullptr;
+};
 void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t* brow, const int32_t* bcol,
                  const uint8_t* fromc, int nb, const int32_t* mapX, const double* valX, double* valH,
-                 const int32_t* branch, const int32_t* done, hipStream_t s);
+                 const int32_t* branch, const int32_t* done, hipStream_t s, NormOut no = NormOut());
 
 // cse.hip
 size_t cse_cube_cap(int nb);
@@ -132,6 +145,16 @@ struct GemmArgs {
     const uint16_t* valB16 = nullptr;
     const int32_t* expA = nullptr;
     const int32_t* expB = nullptr;
+    // block norms of the written blocks (null when not wanted; ring kernels
+    // only): sq, sqlo and norm of each slot written, as the norms kernel
+    // defines them; a slot whose rounding cannot be certified from the
+    // double-double sum is appended to recheck (count in *nrecheck) for the
+    // norms kernel's listed mode
+    double* sq_out = nullptr;
+    double* sqlo_out = nullptr;
+    double* nrm_out = nullptr;
+    int32_t* recheck = nullptr;
+    int32_t* nrecheck = nullptr;
 };
 // ev_start/ev_end (optional) are recorded right around the product kernel.
 void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start = nullptr,

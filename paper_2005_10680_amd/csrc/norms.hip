@@ -104,79 +104,78 @@ SPAMM_DEV double exact_sumsq_lane(const double* v, int len, uint32_t* L) {
     return limbs_round(L);
 }
 
+// Exactly rounded sum of squares of slot s (one wave): double-double
+// accumulation, certified, else lane 0 computes it exactly.
+template <int B>
+SPAMM_DEV void norm_slot(int64_t s, const double* __restrict__ val, double* __restrict__ sq,
+                         double* __restrict__ sqlo, double* __restrict__ nrm, uint32_t* slow) {
+    const int lane = threadIdx.x & 63;
+    const double2* v = reinterpret_cast<const double2*>(val + (size_t)s * B * B);
+    SqAcc a;
+#pragma unroll 4
+    for (int it = 0; it < B * B / 128; ++it) {
+        const double2 x2 = v[it * 64 + lane];
+        sq_add(a, x2.x);
+        sq_add(a, x2.y);
+    }
+    const dd acc = dd_wave_sum(a.acc);
+    const bool ok = sq_certified(acc, __any(a.special), __any(a.tiny));
+    double sres = acc.hi, slo = acc.lo;
+    if (!ok) {
+        if (lane == 0) {
+            const double ex = exact_sumsq_lane(val + (size_t)s * B * B, B * B, slow);
+            slo = (acc.hi - ex) + acc.lo;
+            sres = ex;
+        }
+        sres = __shfl(sres, 0);
+        slo = __shfl(slo, 0);
+    }
+    if (lane == 0) {
+        sq[s] = sres;
+        sqlo[s] = slo;
+        nrm[s] = sqrt(sres);
+    }
+}
+
+// Norms of every live slot, or (list != null) of the *nlist slots listed:
+// the blocks whose norm a producing kernel could not certify.
 template <int B>
 __global__ __launch_bounds__(256) void k_norms(const int32_t* __restrict__ nslot_p, int64_t cap,
                                               const int32_t* __restrict__ brow, const double* __restrict__ val,
                                               double* __restrict__ sq, double* __restrict__ sqlo,
-                                              double* __restrict__ nrm, const int32_t* __restrict__ done) {
+                                              double* __restrict__ nrm, const int32_t* __restrict__ done,
+                                              const int32_t* __restrict__ list, const int32_t* __restrict__ nlist) {
     __shared__ uint32_t slow[4][kLimbs];
     if (done && *done) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int64_t nslot = *nslot_p;
+    const int wv = threadIdx.x >> 6;
+    int64_t nslot = list ? (int64_t)*nlist : *nslot_p;
     if (nslot > cap) nslot = cap;
-    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < nslot; s += (int64_t)gridDim.x * 4) {
+    for (int64_t q = (int64_t)blockIdx.x * 4 + wv; q < nslot; q += (int64_t)gridDim.x * 4) {
+        const int64_t s = list ? (int64_t)list[q] : q;
         if (brow[s] < 0) continue;  // hole (wave-uniform)
-        const double2* v = reinterpret_cast<const double2*>(val + (size_t)s * B * B);
-        dd acc = {0.0, 0.0};
-        bool special = false, tiny = false;
-#pragma unroll 4
-        for (int it = 0; it < B * B / 128; ++it) {
-            double2 x2 = v[it * 64 + lane];
-            double xs[2] = {x2.x, x2.y};
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                double x = xs[q];
-                double ax = fabs(x);
-                if (!(ax < 0x1p500)) special = true;          // huge, inf or NaN
-                if (ax != 0.0 && ax < 0x1p-480) tiny = true;   // two-product may be inexact
-                double p = x * x;
-                double pe = fma(x, x, -p);
-                acc = dd_add(acc, dd{p, pe});
-            }
-        }
-        acc = dd_wave_sum(acc);
-        const bool any_special = __any(special);
-        const bool any_tiny = __any(tiny);
-        // certificate: distance from hi+lo to the nearest rounding boundary
-        // must exceed the accumulated error bound
-        const double eb = acc.hi * 0x1p-80 + (any_tiny ? 0x1p-1000 : 0.0);
-        bool ok;
-        if (any_special) {
-            ok = false;
-        } else if (acc.lo >= 0.0) {
-            // boundary above: hi + up/2
-            double up = nextafter(acc.hi, INFINITY) - acc.hi;
-            ok = (up - 2.0 * acc.lo) > 2.0 * eb;
-        } else {
-            // boundary below: hi - dn/2
-            double dn = acc.hi - nextafter(acc.hi, 0.0);
-            ok = (dn + 2.0 * acc.lo) > 2.0 * eb;
-        }
-        double sres = acc.hi, slo = acc.lo;
-        if (!ok) {
-            if (lane == 0) {
-                double ex = exact_sumsq_lane(val + (size_t)s * B * B, B * B, slow[wv]);
-                slo = (acc.hi - ex) + acc.lo;
-                sres = ex;
-            }
-            sres = __shfl(sres, 0);
-            slo = __shfl(slo, 0);
-        }
-        if (lane == 0) {
-            sq[s] = sres;
-            sqlo[s] = slo;
-            nrm[s] = sqrt(sres);
-        }
+        norm_slot<B>(s, val, sq, sqlo, nrm, slow[wv]);
     }
 }
 
 void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, double* sq,
                   double* sqlo, double* nrm, hipStream_t s, const int32_t* done) {
     int grid = grid_for(cap, 4, 8192);
+    const int32_t* nl = nullptr;
     switch (b) {
-        case 32: hipLaunchKernelGGL(k_norms<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done); break;
-        case 64: hipLaunchKernelGGL(k_norms<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done); break;
-        case 128: hipLaunchKernelGGL(k_norms<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done); break;
+        case 32: hipLaunchKernelGGL(k_norms<32>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done, nl, nl); break;
+        case 64: hipLaunchKernelGGL(k_norms<64>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done, nl, nl); break;
+        case 128: hipLaunchKernelGGL(k_norms<128>, dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, sq, sqlo, nrm, done, nl, nl); break;
+    }
+}
+
+void launch_norms_listed(int b, const int32_t* list, const int32_t* nlist, int64_t cap, const int32_t* brow,
+                         const double* val, double* sq, double* sqlo, double* nrm, hipStream_t s, const int32_t* done) {
+    const int grid = 64;  // the list is empty or short
+    const int32_t* ns = nullptr;
+    switch (b) {
+        case 32: hipLaunchKernelGGL(k_norms<32>, dim3(grid), dim3(256), 0, s, ns, cap, brow, val, sq, sqlo, nrm, done, list, nlist); break;
+        case 64: hipLaunchKernelGGL(k_norms<64>, dim3(grid), dim3(256), 0, s, ns, cap, brow, val, sq, sqlo, nrm, done, list, nlist); break;
+        case 128: hipLaunchKernelGGL(k_norms<128>, dim3(grid), dim3(256), 0, s, ns, cap, brow, val, sq, sqlo, nrm, done, list, nlist); break;
     }
 }
 

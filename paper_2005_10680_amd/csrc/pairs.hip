@@ -218,13 +218,15 @@ void launch_hat_assign(int nb, int P, const int32_t* cnt, int sym, const int32_t
                        nslot_total, cap, map, brow, bcol, nslot, fromc, ovf, done);
 }
 
-// Blocks of 2X - X^2 that no kept pair touches: X^ = 2 X.
+// Blocks of 2X - X^2 that no kept pair touches: X^ = 2 X (with their norms
+// when no.sq is set).
 template <int B>
 __global__ __launch_bounds__(256) void k_rest(const int32_t* __restrict__ nslot_p, int64_t cap,
                                              const int32_t* __restrict__ brow, const int32_t* __restrict__ bcol,
                                              const uint8_t* __restrict__ fromc, int nb, const int32_t* __restrict__ mapX,
                                              const double* __restrict__ valX, double* __restrict__ valH,
-                                             const int32_t* __restrict__ branch, const int32_t* __restrict__ done) {
+                                             const int32_t* __restrict__ branch, const int32_t* __restrict__ done,
+                                             NormOut no) {
     if (done && *done) return;
     if (*branch != 1) return;
     int64_t nslot = *nslot_p;
@@ -237,23 +239,41 @@ __global__ __launch_bounds__(256) void k_rest(const int32_t* __restrict__ nslot_
         if (sx < 0) continue;
         const double2* src = reinterpret_cast<const double2*>(valX + (size_t)sx * B * B);
         double2* dst = reinterpret_cast<double2*>(valH + (size_t)s * B * B);
+        SqAcc a;
         for (int t = lane; t < B * B / 2; t += 64) {
             double2 v = src[t];
             v.x = 2.0 * v.x;
             v.y = 2.0 * v.y;
             dst[t] = v;
+            if (no.sq) {
+                sq_add(a, v.x);
+                sq_add(a, v.y);
+            }
+        }
+        if (no.sq) {
+            const dd acc = dd_wave_sum(a.acc);
+            const bool ok = sq_certified(acc, __any(a.special), __any(a.tiny));
+            if (lane == 0) {
+                if (ok) {
+                    no.sq[s] = acc.hi;
+                    no.sqlo[s] = acc.lo;
+                    no.nrm[s] = sqrt(acc.hi);
+                } else {
+                    no.recheck[atomicAdd(no.nrecheck, 1)] = (int32_t)s;
+                }
+            }
         }
     }
 }
 
 void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t* brow, const int32_t* bcol,
                  const uint8_t* fromc, int nb, const int32_t* mapX, const double* valX, double* valH,
-                 const int32_t* branch, const int32_t* done, hipStream_t s) {
+                 const int32_t* branch, const int32_t* done, hipStream_t s, NormOut no) {
     int grid = grid_for(cap_hat, 4, 4096);
     switch (b) {
-        case 32: hipLaunchKernelGGL(k_rest<32>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done); break;
-        case 64: hipLaunchKernelGGL(k_rest<64>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done); break;
-        case 128: hipLaunchKernelGGL(k_rest<128>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done); break;
+        case 32: hipLaunchKernelGGL(k_rest<32>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no); break;
+        case 64: hipLaunchKernelGGL(k_rest<64>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no); break;
+        case 128: hipLaunchKernelGGL(k_rest<128>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no); break;
     }
 }
 
