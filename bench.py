@@ -153,11 +153,10 @@ def main():
         "kept_pairs_per_run": int(sum(l["npairs"] for l in steps)),
         "phase_ms_per_run": {k: round(sum(l[k] for l in steps), 3)
                              for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc", "ms_total")},
-        # the HBM-bound norms pass over every block of X^ (8 b^2 bytes read
-        # per block); its phase also holds the pass-through copy of blocks
-        # no pair lands on, so the rate is a lower bound
-        "hbm_norms": hbm_rate(sum(l["nslot_hat"] for l in steps) * 8.0 * b * b,
-                              sum(l["ms_norms"] for l in steps)),
+        # the purification takes its block norms from the product epilogue;
+        # the stand-alone norms pass (spamm_build_norms, 8 b^2 bytes read per
+        # block) over the converged D~, for its HBM rate
+        "hbm_norms": norms_rate(res.D, b),
         "roofline": {"kernel": f"k_gemm_ring<{b},0>", "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
@@ -461,6 +460,24 @@ def fro_diff(A, B, torch):
         if bool(only.any()):
             tot += float((vb[s_b[only]] ** 2).sum().item())
     return math.sqrt(tot)
+
+
+def norms_rate(M, b, reps=10):
+    """HBM rate of the stand-alone norms kernel over the live blocks of M
+    (stream events around reps calls on the library's stream)."""
+    import torch
+    import paper_2005_10680_amd as P
+    P.build_norms(M)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.build_norms(M)
+    e1.record()
+    torch.cuda.synchronize()
+    r = hbm_rate(live_blocks(M) * 8.0 * b * b, e0.elapsed_time(e1) / reps)
+    r["blocks"] = live_blocks(M)
+    return r
 
 
 def hbm_rate(nbytes, ms):
