@@ -1524,6 +1524,13 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                     g.expA = low == 2 ? w.xexp : nullptr;
                     g.expB = low == 2 ? w.xexp : nullptr;
                     g.olow = low ? w.mw.olow : nullptr;
+                    // block norms of the new iterate in the epilogue; the
+                    // recheck count is reset in each step before the product
+                    g.sq_out = w.X[1 - par].sq;
+                    g.sqlo_out = w.X[1 - par].sqlo;
+                    g.nrm_out = w.X[1 - par].norm;
+                    g.recheck = w.recheck;
+                    g.nrecheck = &w.mw.counters[8];
                     hd[(size_t)par * nsys + gstart[k] + t] = g;
                 }
     }
@@ -1589,6 +1596,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             }
             run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
                       &w.ctl->branch, done, gg.cs);
+            fill_i32(&w.mw.counters[8], 1, 0, gg.cs);  // recheck count of the epilogue norms
         }
         // one persistent product launch per group over all its systems
         for (size_t k = 0; k < groups.size(); ++k) {
@@ -1605,9 +1613,16 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             const int32_t* done = &w.ctl->done;
             MatView xv = view(&w.X[par]);
             MatView nv = view(&w.X[1 - par]);
+            NormOut no;
+            no.sq = nv.sq;
+            no.sqlo = nv.sqlo;
+            no.nrm = nv.norm;
+            no.recheck = w.recheck;
+            no.nrecheck = &w.mw.counters[8];
             launch_rest(F[q].b, nv.nslot, nv.cap, nv.brow, nv.bcol, w.fromc, F[q].nb, xv.map, xv.val, nv.val,
-                        &w.ctl->branch, done, gg.cs);
-            launch_norms(F[q].b, nv.nslot, nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, gg.cs, done);
+                        &w.ctl->branch, done, gg.cs, no);
+            launch_norms_listed(F[q].b, w.recheck, &w.mw.counters[8], nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo,
+                                nv.norm, gg.cs, done);
             if (pq->variant != 1)
                 launch_truncate(nv, &w.ctl->delta, 0.0, pq->variant == 0 ? 0.5 : 1.0, w.trunc_tmp, caps[q], w.tstats,
                                 w.mw.ovf, done, gg.cs);

@@ -104,6 +104,19 @@ SPAMM_DEV dd dd_wave_sum(dd x) {
     return x;
 }
 
+// dd_add that reports whether it was exact: x + y = r.hi + r.lo exactly when
+// neither intermediate sum of the low parts rounded (inexact stays false).
+SPAMM_DEV dd dd_add_checked(dd x, dd y, bool& inexact) {
+    double s, e, t, te, u, ue;
+    two_sum(x.hi, y.hi, s, e);
+    two_sum(x.lo, y.lo, t, te);
+    two_sum(e, t, u, ue);
+    if (te != 0.0 || ue != 0.0) inexact = true;
+    dd r;
+    two_sum(s, u, r.hi, r.lo);
+    return r;
+}
+
 // Sum of squares of a block's entries, for its exactly rounded norm: each
 // square is split exactly (x*x and fma(x, x, -x*x)) and accumulated in
 // double-double, in any order; the flags mark entries whose square may

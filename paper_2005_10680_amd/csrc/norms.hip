@@ -105,7 +105,10 @@ SPAMM_DEV double exact_sumsq_lane(const double* v, int len, uint32_t* L) {
 }
 
 // Exactly rounded sum of squares of slot s (one wave): double-double
-// accumulation, certified, else lane 0 computes it exactly.
+// accumulation, certified; else (typically an exact tie, as with entries of
+// few significant bits) the same sum again with every addition checked for
+// rounding: when none rounded, the sum is exact and its leading part is the
+// rounded result; else lane 0 computes it exactly.
 template <int B>
 SPAMM_DEV void norm_slot(int64_t s, const double* __restrict__ val, double* __restrict__ sq,
                          double* __restrict__ sqlo, double* __restrict__ nrm, uint32_t* slow) {
@@ -119,8 +122,28 @@ SPAMM_DEV void norm_slot(int64_t s, const double* __restrict__ val, double* __re
         sq_add(a, x2.y);
     }
     const dd acc = dd_wave_sum(a.acc);
-    const bool ok = sq_certified(acc, __any(a.special), __any(a.tiny));
+    const bool special = __any(a.special), tiny = __any(a.tiny);
+    bool ok = sq_certified(acc, special, tiny);
     double sres = acc.hi, slo = acc.lo;
+    if (!ok && !special && !tiny) {
+        // squares are split exactly (no entry is tiny), so only additions can round
+        dd t = {0.0, 0.0};
+        bool inexact = false;
+        for (int it = 0; it < B * B / 128; ++it) {
+            const double2 x2 = v[it * 64 + lane];
+            const double xs[2] = {x2.x, x2.y};
+            for (int q = 0; q < 2; ++q) {
+                const double p = xs[q] * xs[q];
+                t = dd_add_checked(t, dd{p, fma(xs[q], xs[q], -p)}, inexact);
+            }
+        }
+        for (int m = 32; m >= 1; m >>= 1) t = dd_add_checked(t, dd_shfl_xor(t, m), inexact);
+        if (!__any(inexact)) {
+            ok = true;
+            sres = t.hi;
+            slo = t.lo;
+        }
+    }
     if (!ok) {
         if (lane == 0) {
             const double ex = exact_sumsq_lane(val + (size_t)s * B * B, B * B, slow);

@@ -47,6 +47,28 @@ def sym_x(n, b, seed):
 # K1 norms
 # ---------------------------------------------------------------------------
 
+def tie_block(rng, b, scale_exp):
+    """A b x b block of integers times 2^scale_exp whose exact sum of squares
+    has 55 significant bits ending in binary 10: a rounding tie.  The sum of
+    squares is 2 mod 4 when the count of odd entries is.  The last entry is
+    zero."""
+    amp = {32: 2.0 ** 22, 64: 2.0 ** 21, 128: 2.0 ** 20}[b]
+    while True:
+        a = np.round(rng.standard_normal((b, b)) * amp)
+        a[b - 1, b - 1] = 0.0
+        odd = int(np.sum(np.abs(a) % 2 == 1))
+        k = 0
+        while odd % 4 != 2:
+            i, j = divmod(k, b)
+            k += 1
+            if a[i, j] % 2 == 0:
+                a[i, j] += 1
+                odd += 1
+        S = sum(int(x) ** 2 for x in a.ravel())
+        if 2 ** 54 <= S < 2 ** 55:
+            return a * 2.0 ** scale_exp
+
+
 @pytest.mark.parametrize("b", [32, 64, 128])
 def test_norms_bitwise(b):
     rng = np.random.default_rng(b)
@@ -64,6 +86,15 @@ def test_norms_bitwise(b):
     vals[4][6, 7] = 1e-310
     vals[5] *= 1e-170                # squares below the normal range
     vals[6] = 1e-300
+    vals[7] = 0.0
+    vals[7][0, 0] = 1.0
+    vals[7][0, 1] = 2.0 ** -27
+    vals[7][0, 2] = 2.0 ** -27
+    vals[7][0, 3] = 2.0 ** -200      # above the tie by 2^-400: no double-double holds the sum
+    for q in range(8, 12):           # integer entries whose exact sum of squares is a tie
+        vals[q] = tie_block(rng, b, -30 - 4 * q)
+    vals[12] = vals[8]
+    vals[12][b - 1, b - 1] = 2.0 ** -200   # the same tie plus 2^-400: rounds upward
     brow = np.arange(nblk, dtype=np.int32) % 7
     bcol = np.arange(nblk, dtype=np.int32) // 7
     M = P.BlockSparse.from_blocks(7 * b, b, brow, bcol, vals)
