@@ -1168,56 +1168,59 @@ SPAMM_DEV uint16_t bf16_bits(double v) { return (uint16_t)(__float_as_uint((floa
 // Split-BF16 copies of the live blocks: the block is scaled by 2^-e so that
 // its largest |x| lies in [1, 2) (exact), then hi = RN_bf16(x'), lo =
 // RN_bf16(x' - hi); both parts row-major, hi then lo per slot; expo = e.
-// The block passes through a padded LDS tile so that the column-major read
-// and the row-major writes are both coalesced.
+// One wave per block: lane l holds the CPL entries of row l % B in columns
+// CPL (l / B) onwards in registers (each column read is one coalesced load),
+// the wave takes the block's largest |x|, and each lane writes its row
+// segment of both parts with 16-byte stores.
 template <int B>
 __global__ __launch_bounds__(256) void k_to_bf16x2(const int32_t* __restrict__ nslot_p, int64_t cap,
                                                   const int32_t* __restrict__ brow, const double* __restrict__ val,
                                                   uint16_t* __restrict__ out, int32_t* __restrict__ expo,
                                                   const int32_t* __restrict__ done) {
-    __shared__ double t[B * (B + 1)];
-    __shared__ double red[256];
+    constexpr int CPL = B * B / 64;  // entries per lane: 16 at leaf 32, 64 at leaf 64
+    static_assert(CPL % 8 == 0, "16-byte row segments");
     if (done && *done) return;
     int64_t nslot = *nslot_p;
     if (nslot > cap) nslot = cap;
-    const int tid = threadIdx.x;
-    for (int64_t s = blockIdx.x; s < nslot; s += gridDim.x) {
-        if (brow[s] < 0) continue;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int row = lane % B, c0 = CPL * (lane / B);
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < nslot; s += (int64_t)gridDim.x * 4) {
+        if (brow[s] < 0) continue;  // hole (wave-uniform)
         const double* v = val + (size_t)s * B * B;
+        double x[CPL];
         double m = 0.0;
-        for (int e = tid; e < B * B; e += 256) {
-            const int c = e / B, r = e % B;  // column-major source
-            const double x = v[e];
-            t[r * (B + 1) + c] = x;
-            m = fmax(m, fabs(x));
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            x[c] = v[(size_t)(c0 + c) * B + row];  // column-major source
+            m = fmax(m, fabs(x[c]));
         }
-        red[tid] = m;
-        __syncthreads();
-        for (int st = 128; st > 0; st >>= 1) {
-            if (tid < st) red[tid] = fmax(red[tid], red[tid + st]);
-            __syncthreads();
-        }
+#pragma unroll
+        for (int k = 32; k >= 1; k >>= 1) m = fmax(m, __shfl_xor(m, k));
         int ex = 0;
-        if (red[0] > 0.0) frexp(red[0], &ex);
+        if (m > 0.0) frexp(m, &ex);
         const int sc = 1 - ex;  // x' = x 2^sc has its largest |x'| in [1, 2)
-        uint16_t* hi = out + (size_t)s * 2 * B * B;
+        uint16_t* hi = out + (size_t)s * 2 * B * B + (size_t)row * B + c0;  // row-major destination
         uint16_t* lo = hi + B * B;
-        for (int e = tid; e < B * B; e += 256) {
-            const int r = e / B, c = e % B;  // row-major destination
-            const double x = ldexp(t[r * (B + 1) + c], sc);
-            const double h = rn_bf16(x);
-            const double l = rn_bf16(x - h);
-            hi[e] = bf16_bits(h);
-            lo[e] = bf16_bits(l);
+#pragma unroll
+        for (int g = 0; g < CPL / 8; ++g) {
+            uint32_t hw[4], lw[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double x0 = ldexp(x[8 * g + 2 * q], sc), x1 = ldexp(x[8 * g + 2 * q + 1], sc);
+                const double h0 = rn_bf16(x0), h1 = rn_bf16(x1);
+                hw[q] = (uint32_t)bf16_bits(h0) | ((uint32_t)bf16_bits(h1) << 16);
+                lw[q] = (uint32_t)bf16_bits(rn_bf16(x0 - h0)) | ((uint32_t)bf16_bits(rn_bf16(x1 - h1)) << 16);
+            }
+            reinterpret_cast<uint4*>(hi)[g] = uint4{hw[0], hw[1], hw[2], hw[3]};
+            reinterpret_cast<uint4*>(lo)[g] = uint4{lw[0], lw[1], lw[2], lw[3]};
         }
-        if (tid == 0) expo[s] = -sc;
-        __syncthreads();
+        if (lane == 0) expo[s] = -sc;
     }
 }
 
 void launch_to_bf16x2(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, uint16_t* out,
                       int32_t* expo, const int32_t* done, hipStream_t s) {
-    const int grid = grid_for(cap, 1, 8192);
+    const int grid = grid_for(cap, 4, 8192);
     switch (b) {
         case 32: hipLaunchKernelGGL((k_to_bf16x2<32>), dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, expo, done); break;
         case 64: hipLaunchKernelGGL((k_to_bf16x2<64>), dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, expo, done); break;
@@ -1239,15 +1242,24 @@ __global__ __launch_bounds__(256) void k_to_f32(const int32_t* __restrict__ nslo
         if (brow[s] < 0) continue;
         const double2* src = reinterpret_cast<const double2*>(val + (size_t)s * B * B);
         float2* dst = reinterpret_cast<float2*>(out + (size_t)s * B * B);
-        for (int t = lane; t < B * B / 2; t += 64) {
-            const double2 v = src[t];
-            int d = t;
-            if (swz) {
-                // element pair (m, m + 1) of row k, m even: stays a pair after the rotation
-                const int k = (2 * t) / B, m = (2 * t) % B;
-                d = (k * B + ((m + f32_rot<B>(k)) & (B - 1))) / 2;
+        // eight loads in flight per lane before their stores
+        constexpr int IT = B * B / 128, U = IT < 8 ? IT : 8;
+#pragma unroll 1
+        for (int u0 = 0; u0 < IT; u0 += U) {
+            double2 v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = src[(u0 + u) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = (u0 + u) * 64 + lane;
+                int d = t;
+                if (swz) {
+                    // element pair (m, m + 1) of row k, m even: stays a pair after the rotation
+                    const int k = (2 * t) / B, m = (2 * t) % B;
+                    d = (k * B + ((m + f32_rot<B>(k)) & (B - 1))) / 2;
+                }
+                dst[d] = float2{(float)v[u].x, (float)v[u].y};
             }
-            dst[d] = float2{(float)v.x, (float)v.y};
         }
     }
 }
