@@ -36,10 +36,21 @@ def same_logs(la, lb):
 
 
 def same_matrix(A, B):
-    b1, c1, v1, _, _, _ = A.live()
-    b2, c2, v2, _, _, _ = B.live()
+    b1, c1, v1, n1, s1, _ = A.live()
+    b2, c2, v2, n2, s2, _ = B.live()
     assert np.array_equal(b1, b2) and np.array_equal(c1, c2)
     assert np.array_equal(v1, v2)
+    assert np.array_equal(n1.view(np.uint64), n2.view(np.uint64))
+    assert np.array_equal(s1.view(np.uint64), s2.view(np.uint64))
+
+
+def exact_norms(M):
+    """The block norms M holds (taken in the product epilogue) are the
+    exactly rounded norms of its values."""
+    brow, bcol, vals, nrm, sq, _ = M.live()
+    osq, onu = oracle.norms(oracle.BSM(M.n, M.b, brow, bcol, vals))
+    assert np.array_equal(sq.view(np.uint64), osq.view(np.uint64))
+    assert np.array_equal(nrm.view(np.uint64), onu.view(np.uint64))
 
 
 SYSTEMS = [("sys3d", 1000, 64, 11, "hybrid", "fp64"), ("sys3d", 2048, 64, 12, "hybrid", "fp64"),
@@ -60,6 +71,7 @@ def test_batch_matches_single_runs():
         single = P.purify(F, d[1], 1e-6, d[2], homo=d[3], lumo=d[4], variant=variants[q], precision=precs[q])
         same_logs(single.logs, res.logs[q])
         same_matrix(single.D, res.D[q])
+        exact_norms(res.D[q])
         iters.append(len(res.logs[q]))
     assert len(set(iters)) > 1          # the systems stop at different iterations
     # converged against the dense eigensolver

@@ -125,7 +125,16 @@ def test_purify_tier_teacher_forced(tier):
     xh, xl, e_hist = st.xh, st.xl, []
     low_total = 0
     for t, lg in enumerate(steps):
-        Xprev = to_oracle(res.tape(t))
+        T = res.tape(t)
+        Xprev = to_oracle(T)
+        if t > 0:
+            # norms of a product iterate, taken in the product's epilogue (and
+            # the norms kernel for sums it could not certify: exact ties are
+            # common among the low tier's few-bit entries): exactly rounded
+            _, _, _, nrm, sq, _ = T.live()
+            osq, onu = oracle.norms(Xprev)
+            assert np.array_equal(sq.view(np.uint64), osq.view(np.uint64))
+            assert np.array_equal(nrm.view(np.uint64), onu.view(np.uint64))
         Xn, Xh, log, st2 = oracle.sp2_step(Xprev, oracle.SP2State(t + 1, xh, xl, list(e_hist)), p)
         assert lg["branch"] == log.branch
         assert lg["idx"] == log.idx and lg["tau"] == log.tau

@@ -296,7 +296,14 @@ def test_purify_teacher_forced_steps():
         assert lg["branch"] == log.branch
         assert lg["idx"] == log.idx and lg["tau"] == log.tau
         assert lg["npairs"] == log.npairs and lg["nout"] == log.nout
-        Xg = to_oracle(res.tape(t + 1))
+        T = res.tape(t + 1)
+        Xg = to_oracle(T)
         assert np.array_equal(Xg.keys(), Xn.keys())
         assert rel_fro(Xg.vals, Xn.vals) <= 1e-12
+        # the iterate's norms (from the product epilogue) are the exactly
+        # rounded norms of its own values
+        _, _, _, nrm, sq, _ = T.live()
+        osq, onu = oracle.norms(Xg)
+        assert np.array_equal(sq.view(np.uint64), osq.view(np.uint64))
+        assert np.array_equal(nrm.view(np.uint64), onu.view(np.uint64))
         xh, xl, e_hist = ost2.xh, ost2.xl, ost2.e_hist
