@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -1032,6 +1033,16 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
         cur = (nlog - 1) & 1;
     } else {
         std::vector<double> e_hist;
+        // the step's read-back lands in host-mapped memory, gathered by one kernel
+        struct PinnedStatus {
+            Sp2HostStatus* h = nullptr;
+            ~PinnedStatus() {
+                if (h) (void)hipHostFree(h);
+            }
+        } ps;
+        HIP_TRY(hipHostMalloc((void**)&ps.h, sizeof(Sp2HostStatus), hipHostMallocMapped | hipHostMallocCoherent));
+        Sp2HostStatus* hs_dev = nullptr;
+        HIP_TRY(hipHostGetDevicePointer((void**)&hs_dev, ps.h, 0));
         for (int it = 1;; ++it) {
             spamm_bsm* Xc = full_tape ? &w.tape[it - 1] : &w.X[cur];
             spamm_bsm* Xn = full_tape ? (it <= tape_steps ? &w.tape[it] : nullptr) : &w.X[1 - cur];
@@ -1042,15 +1053,15 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             int64_t msc[4], ts[2];
             int32_t ovf[2];
             Sp2Ctl cs;
-            HIP_TRY(hipMemcpyAsync(tr, w.trace_out, sizeof(tr), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(msc, w.mw.sc, sizeof(msc), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(ts, w.tstats, sizeof(ts), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(&ovf[0], w.mw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(&ovf[1], w.sw.ovf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(&cs, w.ctl, sizeof(cs), hipMemcpyDeviceToHost, s));
-            int32_t nsl = 0;
-            HIP_TRY(hipMemcpyAsync(&nsl, xv.nslot, sizeof(nsl), hipMemcpyDeviceToHost, s));
+            launch_host_status(w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, w.ctl, xv.nslot, hs_dev, s);
+            HIP_TRY(hipGetLastError());
             HIP_TRY(hipStreamSynchronize(s));
+            memcpy(tr, ps.h->tr, sizeof(tr));
+            memcpy(msc, ps.h->msc, sizeof(msc));
+            memcpy(ts, ps.h->ts, sizeof(ts));
+            memcpy(ovf, ps.h->ovf, sizeof(ovf));
+            memcpy(&cs, &ps.h->ctl, sizeof(cs));
+            const int32_t nsl = ps.h->nslot;
             if (ovf[0] || ovf[1]) {
                 status = fail(SPAMM_ECAPACITY, "capacity exceeded in iteration %d (flags %d/%d; pairs %lld of %lld)",
                               it - 1, ovf[0], ovf[1], (long long)msc[0], (long long)max_pairs);
@@ -1109,7 +1120,9 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             hc.idx = p->N;
             hc.sigma = 0.0;
             hc.sidx = p->N;
-            HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+            ps.h->ctl_in = hc;  // read by the upload kernel, launched after this store
+            std::atomic_thread_fence(std::memory_order_seq_cst);
+            launch_ctl_upload(&hs_dev->ctl_in, w.ctl, s);
             const int rc_step = enqueue_step(xv, view(Xn), nullptr, ev, s);
             if (rc_step != SPAMM_OK) return rc_step;
             if (every > 1 && it % every == 0 && it / every <= tape_steps) {

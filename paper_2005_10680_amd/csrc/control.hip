@@ -82,6 +82,38 @@ __global__ void k_sp2_control(Sp2Ctl* __restrict__ ctl, const double* __restrict
     ctl->sidx = ctl->N;
 }
 
+__global__ void k_host_status(const double* __restrict__ tr, const int64_t* __restrict__ msc,
+                              const int64_t* __restrict__ ts, const int32_t* __restrict__ ovf_mul,
+                              const int32_t* __restrict__ ovf_sweep, const Sp2Ctl* __restrict__ ctl,
+                              const int32_t* __restrict__ nslot, Sp2HostStatus* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int q = 0; q < 4; ++q) {
+        out->tr[q] = tr[q];
+        out->msc[q] = msc[q];
+    }
+    out->ts[0] = ts[0];
+    out->ts[1] = ts[1];
+    out->ovf[0] = *ovf_mul;
+    out->ovf[1] = *ovf_sweep;
+    out->nslot = *nslot;
+    out->ctl = *ctl;
+    __threadfence_system();
+}
+
+void launch_host_status(const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
+                        const int32_t* ovf_sweep, const Sp2Ctl* ctl, const int32_t* nslot, Sp2HostStatus* out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_host_status, dim3(1), dim3(64), 0, s, tr, msc, ts, ovf_mul, ovf_sweep, ctl, nslot, out);
+}
+
+__global__ void k_ctl_upload(const Sp2Ctl* __restrict__ src, Sp2Ctl* __restrict__ ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *ctl = *src;
+}
+
+void launch_ctl_upload(const Sp2Ctl* src, Sp2Ctl* ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_upload, dim3(1), dim3(64), 0, s, src, ctl);
+}
+
 void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
                         const int32_t* ovf_sweep, const int32_t* nslot_cur, sp2_iter_log* logs, int max_records,
                         hipStream_t s) {

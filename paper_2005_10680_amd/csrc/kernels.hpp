@@ -197,6 +197,23 @@ void launch_bound_leaf(int nb, int nw, const uint32_t* bitsA, const uint32_t* bi
                        const int32_t* done, hipStream_t s);
 
 // control.hip
+// What the host loop reads back after each step, gathered by one thread into
+// host-mapped (pinned, coherent) memory in place of separate small copies.
+struct Sp2HostStatus {
+    double tr[4];      // traces of the current iterate (double-double t1, t2)
+    int64_t msc[4];    // kept pairs, outputs, slots of X^, low-tier pairs
+    int64_t ts[2];     // truncation: removed units, removed key sum
+    int32_t ovf[2];    // capacity flags of the product and of the sweep
+    int32_t nslot;     // slots of the current iterate
+    int32_t pad;
+    Sp2Ctl ctl;
+    Sp2Ctl ctl_in;     // the host's decisions for the next step (uploaded by a kernel)
+};
+// *ctl = *src, src in host-mapped memory
+void launch_ctl_upload(const Sp2Ctl* src, Sp2Ctl* ctl, hipStream_t s);
+void launch_host_status(const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
+                        const int32_t* ovf_sweep, const Sp2Ctl* ctl, const int32_t* nslot, Sp2HostStatus* out,
+                        hipStream_t s);
 void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
                         const int32_t* ovf_sweep, const int32_t* nslot_cur, ::sp2_iter_log* logs, int max_records,
                         hipStream_t s);
