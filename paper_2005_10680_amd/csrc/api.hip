@@ -181,8 +181,12 @@ void run_sweep(const MatView& A, const MatView& B, int btrans, const double* tau
     launch_cube_list(T, w.flag, w.idx, w.keys[0], &w.cnt[0], w.ncap, w.ovf, done, s);
     launch_cube_eval(mode, w.l0, A.nb, w.keys[0], &w.cnt[0], w.ncap, A.map, A.norm, B.map, B.norm, btrans, tau, N,
                      tau0, c_low, w.vals[0], done, s);
+    // levels whose children may number more than kTopNodes (8^4) run as
+    // separate device-wide passes; the rest, and the selection, in one
+    // workgroup
+    const int top = std::max(w.l0 + 1, w.L - 3);
     int cur = 0;
-    for (int lev = w.l0 + 1; lev <= w.L; ++lev) {
+    for (int lev = w.l0 + 1; lev < top; ++lev) {
         int64_t* nc = &w.cnt[cur];
         int64_t* np = &w.cnt[1 - cur];
         launch_level_flags(w.keys[cur], nc, w.ncap, w.lflag, done, s);
@@ -191,7 +195,8 @@ void run_sweep(const MatView& A, const MatView& B, int btrans, const double* tau
         launch_level_eval(w.keys[cur], w.vals[cur], w.pstart, np, w.ncap, N, w.vals[1 - cur], done, s);
         cur = 1 - cur;
     }
-    launch_select(w.vals[cur], &w.cnt[cur], tau, N, budget_dev, budget_host, bound_out, idx_out, tau_out, done, s);
+    launch_levels_top(w.keys[cur], &w.cnt[cur], w.vals[cur], w.vals[1 - cur], std::max(0, w.L - top + 1), N, tau,
+                      budget_dev, budget_host, bound_out, idx_out, tau_out, done, s);
 }
 
 // ---------------------------------------------------------------------------

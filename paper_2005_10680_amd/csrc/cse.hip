@@ -242,6 +242,32 @@ void launch_level_build(const uint32_t* keys, const int64_t* n, int64_t cap, con
                        nparent, pkeys, pstart, done);
 }
 
+// Error value of one octree node for candidate m from its present children
+// c0 .. c1 - 1 (octant = key & 7, absent children count as zero): the
+// combination of Algorithm 3, a (row half of C) outer, c (column half)
+// inner, t = E(a, k=0, c) + E(a, k=1, c), acc += t^2, then the root.
+SPAMM_DEV double node_eval(const uint32_t* ckeys, const double* __restrict__ cvals, int c0, int c1, int m, int N) {
+    double e[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        const uint32_t o = ckeys[c] & 7u;
+        const double v = cvals[(size_t)c * N + m];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = (o == (uint32_t)q) ? v : e[q];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            double t = e[(a << 2) | c] + e[(a << 2) | 2 | c];
+            double t2 = t * t;
+            acc = acc + t2;
+        }
+    return sqrt(acc);
+}
+
 __global__ void k_level_eval(const uint32_t* __restrict__ ckeys, const double* __restrict__ cvals,
                              const int32_t* __restrict__ pstart, const int64_t* __restrict__ np_p, int64_t cap, int N,
                              double* __restrict__ pvals, const int32_t* __restrict__ done) {
@@ -253,26 +279,92 @@ __global__ void k_level_eval(const uint32_t* __restrict__ ckeys, const double* _
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t p = idx / N;
         const int m = (int)(idx - p * N);
-        double e[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) e[q] = 0.0;
-        for (int c = pstart[p]; c < pstart[p + 1]; ++c) {
-            const uint32_t o = ckeys[c] & 7u;
-            const double v = cvals[(size_t)c * N + m];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) e[q] = (o == (uint32_t)q) ? v : e[q];
-        }
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                double t = e[(a << 2) | c] + e[(a << 2) | 2 | c];
-                double t2 = t * t;
-                acc = acc + t2;
-            }
-        pvals[(size_t)p * N + m] = sqrt(acc);
+        pvals[(size_t)p * N + m] = node_eval(ckeys, cvals, pstart[p], pstart[p + 1], m, N);
     }
+}
+
+// The top levels of the octree in one workgroup: from the n <= kTopNodes
+// sorted nodes of one level (keys_in, values va) up to the root, level by
+// level exactly as k_level_flags / scan / build / eval do, with the node
+// lists in LDS and the values alternating between va and vb; then the
+// selection (as k_select).  Replaces six launches per level and the
+// selection's launch.
+constexpr int kTopThreads = 1024;
+__global__ __launch_bounds__(kTopThreads) void k_levels_top(const uint32_t* __restrict__ keys_in,
+                                                          const int64_t* __restrict__ n_in, double* va, double* vb,
+                                                          int nlev, int N, const double* __restrict__ tau,
+                                                          const double* __restrict__ budget_dev, double budget_host,
+                                                          double* __restrict__ bound_out,
+                                                          int32_t* __restrict__ idx_out, double* __restrict__ tau_out,
+                                                          const int32_t* __restrict__ done) {
+    __shared__ uint32_t keys[2][kTopNodes];
+    __shared__ int32_t pstart[kTopNodes + 1];
+    __shared__ int32_t wsum[kTopThreads / 64];
+    __shared__ int best;
+    if (done && *done) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int n = (int)(*n_in < (int64_t)kTopNodes ? *n_in : (int64_t)kTopNodes);
+    for (int c = tid; c < n; c += kTopThreads) keys[0][c] = keys_in[c];
+    __syncthreads();
+    int cur = 0;
+    const double* cv = va;
+    double* pv = vb;
+    for (int lev = 0; lev < nlev; ++lev) {
+        // parents: the first child of each run of equal key >> 3 starts a parent
+        int np = 0;
+        for (int c0 = 0; c0 < n; c0 += kTopThreads) {
+            const int c = c0 + tid;
+            const bool f = c < n && (c == 0 || (keys[cur][c] >> 3) != (keys[cur][c - 1] >> 3));
+            const uint64_t bal = __ballot(f);
+            if (lane == 0) wsum[w] = __popcll(bal);
+            __syncthreads();
+            int off = np, tot = 0;
+            for (int q = 0; q < kTopThreads / 64; ++q) {
+                if (q < w) off += wsum[q];
+                tot += wsum[q];
+            }
+            if (f) {
+                const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
+                keys[1 - cur][pos] = keys[cur][c] >> 3;
+                pstart[pos] = c;
+            }
+            np += tot;
+            __syncthreads();
+        }
+        if (tid == 0) pstart[np] = n;
+        __syncthreads();
+        for (int idx = tid; idx < np * N; idx += kTopThreads) {
+            const int p = idx / N, m = idx - p * N;
+            pv[(size_t)p * N + m] = node_eval(keys[cur], cv, pstart[p], pstart[p + 1], m, N);
+        }
+        __syncthreads();
+        cur = 1 - cur;
+        n = np;
+        const double* t = cv;
+        cv = pv;
+        pv = const_cast<double*>(t);
+    }
+    // selection: the first (largest) candidate whose bound is below the budget
+    if (tid == 0) best = N;
+    __syncthreads();
+    const double budget = budget_dev ? *budget_dev : budget_host;
+    for (int m = tid; m < N; m += kTopThreads) {
+        const double bd = n > 0 ? cv[m] : 0.0;
+        if (bound_out) bound_out[m] = bd;
+        if (bd < budget) atomicMin(&best, m);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        *idx_out = best;
+        *tau_out = best < N ? tau[best] : 0.0;
+    }
+}
+
+void launch_levels_top(const uint32_t* keys, const int64_t* n, double* va, double* vb, int nlev, int N,
+                       const double* tau, const double* budget_dev, double budget_host, double* bound_out,
+                       int32_t* idx_out, double* tau_out, const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_levels_top, dim3(1), dim3(kTopThreads), 0, s, keys, n, va, vb, nlev, N, tau, budget_dev,
+                       budget_host, bound_out, idx_out, tau_out, done);
 }
 
 void launch_level_eval(const uint32_t* ckeys, const double* cvals, const int32_t* pstart, const int64_t* nparent,

@@ -106,6 +106,12 @@ void launch_level_build(const uint32_t* keys, const int64_t* n, int64_t cap, con
                         const int32_t* done, hipStream_t s);
 void launch_level_eval(const uint32_t* ckeys, const double* cvals, const int32_t* pstart, const int64_t* nparent,
                        int64_t cap, int N, double* pvals, const int32_t* done, hipStream_t s);
+// the levels above one of at most kTopNodes nodes, and the selection, in one
+// workgroup (nlev levels from the nodes keys / va; vb the other value buffer)
+constexpr int kTopNodes = 4096;
+void launch_levels_top(const uint32_t* keys, const int64_t* n, double* va, double* vb, int nlev, int N,
+                       const double* tau, const double* budget_dev, double budget_host, double* bound_out,
+                       int32_t* idx_out, double* tau_out, const int32_t* done, hipStream_t s);
 void launch_select(const double* root, const int64_t* nroot, const double* tau, int N, const double* budget_dev,
                    double budget_host, double* bound_out, int32_t* idx_out, double* tau_out, const int32_t* done,
                    hipStream_t s);
