@@ -22,7 +22,8 @@ size_t scan_temp_bytes(int64_t n) {
     return (size_t)(nblk + 1) * sizeof(int64_t);
 }
 
-// inclusive scan of one int64 per thread across a 256-thread block
+// inclusive scan of one int64 per thread across a block of THREADS threads
+template <int THREADS = kScanThreads>
 SPAMM_DEV int64_t block_inclusive_scan(int64_t v, int64_t* sh_wave, int64_t& block_total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
@@ -34,7 +35,7 @@ SPAMM_DEV int64_t block_inclusive_scan(int64_t v, int64_t* sh_wave, int64_t& blo
     __syncthreads();
     int64_t off = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < kScanThreads / 64; ++q) {
+    for (int q = 0; q < THREADS / 64; ++q) {
         int64_t t = sh_wave[q];
         if (q < w) off += t;
         tot += t;
@@ -42,6 +43,36 @@ SPAMM_DEV int64_t block_inclusive_scan(int64_t v, int64_t* sh_wave, int64_t& blo
     __syncthreads();
     block_total = tot;
     return v + off;
+}
+
+// Arrays of at most kScanSingle items: the whole scan in one block.
+constexpr int kScanSingleThreads = 1024;
+constexpr int kScanSingle = kScanSingleThreads * kScanItems;  // 8192 items
+
+template <typename TO>
+__global__ __launch_bounds__(kScanSingleThreads) void k_scan_single(const int32_t* __restrict__ in,
+                                                                   TO* __restrict__ out, int64_t n,
+                                                                   const int64_t* __restrict__ n_dev,
+                                                                   int64_t* __restrict__ total) {
+    __shared__ int64_t sh[kScanSingleThreads / 64];
+    int64_t nn = n;
+    if (n_dev && *n_dev < nn) nn = *n_dev;
+    const int64_t base = (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = base + q < nn ? in[base + q] : 0;
+        s += v[q];
+    }
+    int64_t tot;
+    int64_t run = block_inclusive_scan<kScanSingleThreads>(s, sh, tot) - s;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        if (base + q < nn) out[base + q] = (TO)run;
+        run += v[q];
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_up(const int32_t* __restrict__ in, int64_t n,
@@ -111,6 +142,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t* in, T
 template <typename TO>
 static void scan_impl(const int32_t* in, TO* out, int64_t n, const int64_t* n_dev, int64_t* total_dev,
                       void* temp, hipStream_t s) {
+    if (n <= kScanSingle) {
+        hipLaunchKernelGGL(k_scan_single<TO>, dim3(1), dim3(kScanSingleThreads), 0, s, in, out, n, n_dev, total_dev);
+        return;
+    }
     int64_t nblk = (n + kScanTile - 1) / kScanTile;
     if (nblk < 1) nblk = 1;
     if (nblk > kScanMaxBlocks) return;  // callers keep n <= 2048 * 2048
