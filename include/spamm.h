@@ -207,8 +207,9 @@ typedef struct sp2_iter_log {
     int64_t npairs, nout, nslot_hat, nslot_kept, removed_units;
     double removed_fro2;
     /* stream-event times in ms: threshold sweep (and FP32 copies), kept pairs
-       and output pattern, the leaf-product kernel alone, pass-through blocks
-       and block norms, truncation, whole iteration */
+       and output pattern, the leaf-product kernel alone (which also forms
+       the block norms of its outputs), pass-through blocks and the norms the
+       product could not certify, truncation, whole iteration */
     float ms_sweep, ms_pairs, ms_gemm, ms_norms, ms_trunc, ms_total;
     int64_t npairs_low;  /* pairs evaluated in the low-precision tier */
     double sigma;        /* low-precision limit of the step (0: none) */
@@ -223,12 +224,14 @@ typedef struct sp2_iter_log {
  * with delta_i/2 (Algorithm 5), delta_i = eps*g_i/(4*n_max) from the
  * mapped gap g_i, until the stop rule fires.
  *   F     : symmetric input with norms NOT required (computed internally).
- *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise).
+ *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise), with
+ *           its block norms (as spamm_build_norms computes them).
  *   log   : host [n_max + 2] records; nlog_out: records written.
  * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, tape_steps, precision) with
  * tape_steps = n_max (keep_tape = 1), n_max / keep_tape (keep_tape > 1) or 0.
  * Host-driven loop: reads scalars back every iteration (synchronises the
- * stream).  Graph mode (graph_steps > 0): same decisions, same kernels and
+ * stream; the read-back goes through a small pinned host buffer allocated
+ * for the call).  Graph mode (graph_steps > 0): same decisions, same kernels and
  * bit-identical results; the stream is synchronised once per graph_steps
  * iterations.
  */
