@@ -269,13 +269,15 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
 // Leaf products of the kept pairs into C's slots (combined with X when given);
 // with no.sq also the norms of the written blocks (the product's work
 // counters, reset before the product, hold the recheck count at [8]).
-// Returns -1 only for norms requested without the transposed-B layout.
+// With out32 also the FP32 copies of the written blocks (FP32 tier).
+// Returns -1 only for norms or copies requested without the transposed-B
+// layout (copies: without the FP32 tier).
 int run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatView& C, const uint8_t* fromc,
               MulWs& w, const int32_t* mapX, const double* valX, const int32_t* branch_dev, const int32_t* done,
               hipStream_t s, const float* valA32 = nullptr, const float* valB32 = nullptr,
               hipEvent_t ev_start = nullptr, hipEvent_t ev_end = nullptr, const uint16_t* valA16 = nullptr,
               const uint16_t* valB16 = nullptr, const int32_t* expA = nullptr, const int32_t* expB = nullptr,
-              NormOut no = NormOut()) {
+              NormOut no = NormOut(), float* out32 = nullptr) {
     const int nb = A.nb;
     GemmArgs g;
     g.b = A.b;
@@ -315,8 +317,14 @@ int run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatV
         g.recheck = no.recheck;
         g.nrecheck = no.nrecheck;
     }
+    if (out32) {
+        // FP32 copies of the outputs in the epilogue (the FP32-tier ring kernels)
+        if (!btrans || !valA32) return -1;
+        g.out32 = out32;
+    }
     launch_gemm_f64(g, num_cus(), s, ev_start, ev_end);
-    if (mapX) launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s, no);
+    if (mapX)
+        launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s, no, out32);
     return 0;
 }
 
@@ -429,6 +437,7 @@ struct Sp2Ws {
     float* x32;     // FP32 copy of the current iterate (FP32 tier), or its split-BF16 parts
     int32_t* xexp;  // per-slot exponents of the split-BF16 parts
     int32_t* recheck;  // [cap] slots whose norm the product kernels left to the norms kernel
+    float* x32n;       // FP32 tier, one system: the copy of the next iterate, written by the product
     Sp2Ctl* ctl;
     sp2_iter_log* dlog;  // [kMaxLog] records written by the device control (graph mode)
 };
@@ -466,6 +475,7 @@ void carve_sp2(Carver& c, int nb, int b, int N, int64_t cap, int64_t max_pairs, 
     w.x32 = precision ? c.take<float>((size_t)cap * b * b) : nullptr;
     w.xexp = precision == 2 ? c.take<int32_t>(cap) : nullptr;
     w.recheck = c.take<int32_t>(cap);
+    w.x32n = (precision == 1 && !x1_outside) ? c.take<float>((size_t)cap * b * b) : nullptr;
 }
 
 // argument checks shared by the single and the batched purification
@@ -904,7 +914,13 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     // products with the combine fused, block norms, truncation.  done: the
     // device stop flag (graph mode), null in the host loop.  evs: phase
     // events (host loop only).
-    auto enqueue_step = [&](const MatView& xv, const MatView& nv, const int32_t* done, hipEvent_t* evs,
+    // FP32 tier (one system): the FP32 copy of X~_{i-1} is f32buf[par] and the
+    // product writes the copy of X~_i into f32buf[1 - par] (par: the step's
+    // parity), so no conversion pass runs inside the loop
+    float* f32buf[2] = {w.x32, w.x32n};
+    const bool f32_fused = p->precision == 1 && w.x32n != nullptr;
+    if (f32_fused) launch_to_f32(b, X0.nslot, X0.cap, X0.brow, X0.val, f32buf[0], 1, nullptr, s);  // X~_0
+    auto enqueue_step = [&](const MatView& xv, const MatView& nv, int par, const int32_t* done, hipEvent_t* evs,
                             hipStream_t st) -> int {
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
         if (p->variant != 2 && p->bound_kind != 0)
@@ -926,7 +942,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             if (p->precision == 2)
                 launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp,
                                  done, st);
-            else
+            else if (!f32_fused)
                 launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, st);
         }
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));
@@ -942,11 +958,12 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                   &w.ctl->branch, done, st);
         // evs[2]/evs[3] bracket the product kernel alone
         const uint16_t* x16 = p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr;
-        const float* x32 = p->precision == 1 ? w.x32 : nullptr;
+        const float* x32 = p->precision == 1 ? (f32_fused ? f32buf[par] : w.x32) : nullptr;
         const int32_t* xexp = p->precision == 2 ? w.xexp : nullptr;
         const int rg = run_gemm(xv, xv, 1, 1, nv, w.fromc, w.mw, xv.map, xv.val, &w.ctl->branch, done, st, x32, x32,
-                                evs ? evs[2] : nullptr, evs ? evs[3] : nullptr, x16, x16, xexp, xexp, step_norms);
-        if (rg) return fail(SPAMM_EINVAL, "fused block norms need the transposed-B product");
+                                evs ? evs[2] : nullptr, evs ? evs[3] : nullptr, x16, x16, xexp, xexp, step_norms,
+                                f32_fused ? f32buf[1 - par] : nullptr);
+        if (rg) return fail(SPAMM_EINVAL, "fused block norms or FP32 copies need the transposed-B product");
         launch_norms_listed(b, w.recheck, &w.mw.counters[8], nv.cap, nv.brow, nv.val, nv.sq, nv.sqlo, nv.norm, st,
                             done);
         if (evs) HIP_TRY(hipEventRecord(evs[4], st));
@@ -1006,7 +1023,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                           w.trace_out, &w.ctl->done, gg.cs);
             launch_sp2_control(w.ctl, w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, xv.nslot, w.dlog, kMaxLog,
                                gg.cs);
-            rc_cap = enqueue_step(xv, nv, &w.ctl->done, nullptr, gg.cs);
+            rc_cap = enqueue_step(xv, nv, q, &w.ctl->done, nullptr, gg.cs);
         }
         hipError_t ec = hipStreamEndCapture(gg.cs, &gg.g);
         if (rc_cap != SPAMM_OK) return rc_cap;
@@ -1128,7 +1145,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             ps.h->ctl_in = hc;  // read by the upload kernel, launched after this store
             std::atomic_thread_fence(std::memory_order_seq_cst);
             launch_ctl_upload(&hs_dev->ctl_in, w.ctl, s);
-            const int rc_step = enqueue_step(xv, view(Xn), nullptr, ev, s);
+            const int rc_step = enqueue_step(xv, view(Xn), (it - 1) & 1, nullptr, ev, s);
             if (rc_step != SPAMM_OK) return rc_step;
             if (every > 1 && it % every == 0 && it / every <= tape_steps) {
                 const int rcc = copy_mat(w.tape[it / every], *Xn, cap, s);  // checkpoint X~_it

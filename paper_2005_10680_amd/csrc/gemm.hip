@@ -422,13 +422,6 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 // read touches fall in 16 different bank quads.
 SPAMM_DEV int bf16_rot(int r) { return (r >> 2) & 3; }
 
-// Rotation of row k of an FP32 copy (the ring kernel's layout): element m of
-// row k at position (m + f32_rot(k)) mod b.  A read of four consecutive rows
-// (16 lanes each) then covers four different 16-float bank ranges; only
-// k mod 4 matters.
-template <int B>
-SPAMM_DEV int f32_rot(int k) { return B == 64 ? 16 * (k & 3) : 16 * ((k >> 1) & 1); }
-
 // Copy inner indices 32c .. 32c+31 of one split-BF16 block (hi part, then lo
 // part, each b rows of b bf16, row-major) into LDS: per part b rows of four
 // 16 B groups (8 inner indices each), rotated by bf16_rot.  Every 1 KB piece
@@ -862,6 +855,9 @@ SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int
     double* dstt = sht >= 0 ? d.val_out + (size_t)sht * B * B : nullptr;
     const double* xs = sx >= 0 ? d.valX + (size_t)sx * B * B : nullptr;
     const bool want_norm = d.sq_out && dst;
+    // the FP32-tier kernels also write the blocks' FP32 copies for the next step
+    float* d32 = (LOWT == 1 && d.out32 && sh >= 0) ? d.out32 + (size_t)sh * B * B : nullptr;
+    float* d32t = (LOWT == 1 && d.out32 && sht >= 0) ? d.out32 + (size_t)sht * B * B : nullptr;
     // each lane's share of the block's sum of squares; in the tier kernels
     // at leaf 64, whose registers are scarce, its running total waits in
     // ring slot NS - 1 behind the epilogue tile between passes
@@ -894,12 +890,15 @@ SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int
             }
             if (dst) dst[(size_t)(c0 + cl) * B + row] = v;
             if (want_norm) sq_add(sa, v);
+            if (LOWT == 1 && d32) d32[(c0 + cl) * B + ((row + f32_rot<B>(c0 + cl)) & (B - 1))] = (float)v;
         }
         if (dstt) {
             __syncthreads();
             for (int e = tid; e < PC * B; e += 256) {
                 const int cp = e / PC, rp = e % PC;
-                dstt[(size_t)cp * B + c0 + rp] = ldsd[rp * R::LDT + cp];
+                const double v = ldsd[rp * R::LDT + cp];
+                dstt[(size_t)cp * B + c0 + rp] = v;
+                if (LOWT == 1 && d32t) d32t[cp * B + ((c0 + rp + f32_rot<B>(cp)) & (B - 1))] = (float)v;
             }
         }
         if (kLdsSum && want_norm) lsum[tid] = pass ? dd_add(lsum[tid], sa.acc) : sa.acc;  // own entry

@@ -33,6 +33,13 @@ void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const in
                    const double* val, const double* sq, const double* sqlo, double* temp, double* out,
                    const int32_t* done, hipStream_t s);
 
+// Rotation of row k of an FP32 copy (the ring kernel's layout): element m of
+// row k (index k of the column-major block's columns) at position
+// (m + f32_rot(k)) mod b.  A read of four consecutive rows (16 lanes each)
+// then covers four different 16-float bank ranges; only k mod 4 matters.
+template <int B>
+SPAMM_DEV int f32_rot(int k) { return B == 64 ? 16 * (k & 3) : 16 * ((k >> 1) & 1); }
+
 // Row bitmaps of A (bit k of row i: A_ik present) and column bitmaps of B
 // (bit k of column j: B_kj present) turn the inner indices of output (i, j)
 // into a word AND.
@@ -86,7 +93,8 @@ struct NormOut {
 };
 void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t* brow, const int32_t* bcol,
                  const uint8_t* fromc, int nb, const int32_t* mapX, const double* valX, double* valH,
-                 const int32_t* branch, const int32_t* done, hipStream_t s, NormOut no = NormOut());
+                 const int32_t* branch, const int32_t* done, hipStream_t s, NormOut no = NormOut(),
+                 float* out32 = nullptr);
 
 // cse.hip
 size_t cse_cube_cap(int nb);
@@ -161,6 +169,10 @@ struct GemmArgs {
     double* nrm_out = nullptr;
     int32_t* recheck = nullptr;
     int32_t* nrecheck = nullptr;
+    // FP32 copies of the written blocks in the ring kernel's layout (rows
+    // rotated by f32_rot; null when not wanted; the FP32-tier kernels only),
+    // for the next step's low tier
+    float* out32 = nullptr;
 };
 // ev_start/ev_end (optional) are recorded right around the product kernel.
 void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start = nullptr,

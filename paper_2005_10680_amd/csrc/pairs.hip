@@ -219,14 +219,15 @@ void launch_hat_assign(int nb, int P, const int32_t* cnt, int sym, const int32_t
 }
 
 // Blocks of 2X - X^2 that no kept pair touches: X^ = 2 X (with their norms
-// when no.sq is set).
+// when no.sq is set, and their FP32 copies in the ring kernel's layout when
+// out32 is).
 template <int B>
 __global__ __launch_bounds__(256) void k_rest(const int32_t* __restrict__ nslot_p, int64_t cap,
                                              const int32_t* __restrict__ brow, const int32_t* __restrict__ bcol,
                                              const uint8_t* __restrict__ fromc, int nb, const int32_t* __restrict__ mapX,
                                              const double* __restrict__ valX, double* __restrict__ valH,
                                              const int32_t* __restrict__ branch, const int32_t* __restrict__ done,
-                                             NormOut no) {
+                                             NormOut no, float* __restrict__ out32) {
     if (done && *done) return;
     if (*branch != 1) return;
     int64_t nslot = *nslot_p;
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(256) void k_rest(const int32_t* __restrict__ nslot_
         if (sx < 0) continue;
         const double2* src = reinterpret_cast<const double2*>(valX + (size_t)sx * B * B);
         double2* dst = reinterpret_cast<double2*>(valH + (size_t)s * B * B);
+        float2* d32 = out32 ? reinterpret_cast<float2*>(out32 + (size_t)s * B * B) : nullptr;
         SqAcc a;
         for (int t = lane; t < B * B / 2; t += 64) {
             double2 v = src[t];
@@ -248,6 +250,11 @@ __global__ __launch_bounds__(256) void k_rest(const int32_t* __restrict__ nslot_
             if (no.sq) {
                 sq_add(a, v.x);
                 sq_add(a, v.y);
+            }
+            if (d32) {
+                // element pair (m, m + 1) of row k, m even: stays a pair after the rotation
+                const int k = (2 * t) / B, m = (2 * t) % B;
+                d32[(k * B + ((m + f32_rot<B>(k)) & (B - 1))) / 2] = float2{(float)v.x, (float)v.y};
             }
         }
         if (no.sq) {
@@ -268,12 +275,12 @@ __global__ __launch_bounds__(256) void k_rest(const int32_t* __restrict__ nslot_
 
 void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t* brow, const int32_t* bcol,
                  const uint8_t* fromc, int nb, const int32_t* mapX, const double* valX, double* valH,
-                 const int32_t* branch, const int32_t* done, hipStream_t s, NormOut no) {
+                 const int32_t* branch, const int32_t* done, hipStream_t s, NormOut no, float* out32) {
     int grid = grid_for(cap_hat, 4, 4096);
     switch (b) {
-        case 32: hipLaunchKernelGGL(k_rest<32>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no); break;
-        case 64: hipLaunchKernelGGL(k_rest<64>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no); break;
-        case 128: hipLaunchKernelGGL(k_rest<128>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no); break;
+        case 32: hipLaunchKernelGGL(k_rest<32>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no, out32); break;
+        case 64: hipLaunchKernelGGL(k_rest<64>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no, out32); break;
+        case 128: hipLaunchKernelGGL(k_rest<128>, dim3(grid), dim3(256), 0, s, nslot_hat, cap_hat, brow, bcol, fromc, nb, mapX, valX, valH, branch, done, no, nullptr); break;
     }
 }
 
