@@ -225,10 +225,18 @@ __global__ __launch_bounds__(256) void k_traces_part(const int32_t* __restrict__
         d2 = dd_add(d2, dd{sq[s], 0.0});
         d2 = dd_add(d2, dd{sqlo[s], 0.0});
         if (r == bcol[s]) {
+            // diagonal entries t < cnt (rows below n), added in ascending t;
+            // sixteen loads in flight before their additions
             const double* v = val + (size_t)s * b * b;
-            for (int t = 0; t < b; ++t) {
-                if ((int64_t)r * b + t >= n) break;
-                d1 = dd_add(d1, dd{v[(size_t)t * b + t], 0.0});
+            const int64_t rem = n - (int64_t)r * b;
+            const int cnt = rem < (int64_t)b ? (int)rem : b;
+            for (int t0 = 0; t0 < cnt; t0 += 16) {
+                double x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = t0 + u < cnt ? v[(size_t)(t0 + u) * b + t0 + u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (t0 + u < cnt) d1 = dd_add(d1, dd{x[u], 0.0});
             }
         }
     }
