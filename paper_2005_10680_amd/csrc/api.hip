@@ -44,7 +44,7 @@ int num_cus() {
     static int cached = -1;
     if (cached < 0) {
         int dev = 0;
-        hipGetDevice(&dev);
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) cached = p.multiProcessorCount;
         else cached = 256;
@@ -874,7 +874,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     struct EvGuard {
         hipEvent_t* e;
         ~EvGuard() {
-            for (int q = 0; q < 8; ++q) hipEventDestroy(e[q]);
+            for (int q = 0; q < 8; ++q) (void)hipEventDestroy(e[q]);
         }
     } guard{ev};
 
@@ -1006,9 +1006,9 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             ~GraphGuard() {
-                if (ge) hipGraphExecDestroy(ge);
-                if (g) hipGraphDestroy(g);
-                if (cs) hipStreamDestroy(cs);
+                if (ge) (void)hipGraphExecDestroy(ge);
+                if (g) (void)hipGraphDestroy(g);
+                if (cs) (void)hipStreamDestroy(cs);
             }
         } gg;
         HIP_TRY(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
@@ -1102,13 +1102,17 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                 L.npairs_low = tiered ? msc[3] : 0;
                 L.sigma = cs.sigma;
                 L.sidx = cs.sidx;
-                float ms = 0;
-                hipEventElapsedTime(&ms, ev[0], ev[1]); L.ms_sweep = ms;
-                hipEventElapsedTime(&ms, ev[1], ev[2]); L.ms_pairs = ms;
-                hipEventElapsedTime(&ms, ev[2], ev[3]); L.ms_gemm = ms;
-                hipEventElapsedTime(&ms, ev[3], ev[4]); L.ms_norms = ms;
-                hipEventElapsedTime(&ms, ev[4], ev[5]); L.ms_trunc = ms;
-                hipEventElapsedTime(&ms, ev[0], ev[5]); L.ms_total = ms;
+                // phase times (0 when an interval cannot be read)
+                auto elapsed = [](hipEvent_t a, hipEvent_t z) -> float {
+                    float ms = 0.f;
+                    return hipEventElapsedTime(&ms, a, z) == hipSuccess ? ms : 0.f;
+                };
+                L.ms_sweep = elapsed(ev[0], ev[1]);
+                L.ms_pairs = elapsed(ev[1], ev[2]);
+                L.ms_gemm = elapsed(ev[2], ev[3]);
+                L.ms_norms = elapsed(ev[3], ev[4]);
+                L.ms_trunc = elapsed(ev[4], ev[5]);
+                L.ms_total = elapsed(ev[0], ev[5]);
             }
             const double t1 = tr[0], t2 = tr[2];
             const double e = dd_diff(tr[0], tr[1], tr[2], tr[3]);
@@ -1578,10 +1582,10 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
         hipGraphExec_t ge = nullptr;
         hipEvent_t e = nullptr;
         ~GraphGuard() {
-            if (ge) hipGraphExecDestroy(ge);
-            if (g) hipGraphDestroy(g);
-            if (cs) hipStreamDestroy(cs);
-            if (e) hipEventDestroy(e);
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+            if (cs) (void)hipStreamDestroy(cs);
+            if (e) (void)hipEventDestroy(e);
         }
     } gg;
     HIP_TRY(hipEventCreate(&gg.e));
