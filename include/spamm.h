@@ -175,6 +175,24 @@ size_t spamm_truncate_workspace_bytes(int64_t cap);
 int spamm_truncate(spamm_bsm* X, double delta, uint32_t flags, double* removed_out, void* ws,
                    size_t ws_bytes, spamm_stream_t stream);
 
+/*
+ * Allocation-free truncation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same operation, kernels and results as spamm_truncate, with
+ * its scratch in a fixed device array of the library instead of a workspace:
+ * the call allocates nothing (no hipMalloc/hipFree, no allocating library
+ * routine).  The array holds the temporaries of X->cap <= 2^20 slots
+ * (spamm_truncate_noalloc_max_cap(); about 16 MiB, one copy per GPU the
+ * library runs on, held until the process ends); a larger X->cap is
+ * rejected with SPAMM_EINVAL.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams or host threads at once)
+ * race and must be serialised by the caller.
+ *   X, delta, flags, removed_out: as spamm_truncate.
+ */
+int64_t spamm_truncate_noalloc_max_cap(void);
+int spamm_truncate_noalloc(spamm_bsm* X, double delta, uint32_t flags, double* removed_out,
+                           spamm_stream_t stream);
+
 /* Parameters of purify_sp2 (Algorithms 1, 4 and 5 with SP2 polynomials). */
 typedef struct sp2_params {
     int64_t n_occ;       /* occupied count: the trace the iteration converges to */

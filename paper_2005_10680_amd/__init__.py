@@ -98,6 +98,9 @@ def lib() -> ctypes.CDLL:
     L.spamm_truncate_workspace_bytes.argtypes = [i64]
     L.spamm_truncate_workspace_bytes.restype = sz
     L.spamm_truncate.argtypes = [B, d, u32, P, P, sz, P]
+    L.spamm_truncate_noalloc_max_cap.argtypes = []
+    L.spamm_truncate_noalloc_max_cap.restype = i64
+    L.spamm_truncate_noalloc.argtypes = [B, d, u32, P, P]
     L.purify_sp2_workspace_bytes.argtypes = [i32, i32, i32, i64, i64, i32, i32]
     L.purify_sp2_workspace_bytes.restype = sz
     L.purify_sp2.argtypes = [B, ctypes.POINTER(sp2_params), B, ctypes.POINTER(sp2_iter_log),
@@ -420,6 +423,15 @@ def truncate(X: BlockSparse, delta: float, sync=False):
     ws = _ws(lib().spamm_truncate_workspace_bytes(X.cap), dev)
     _check(lib().spamm_truncate(ctypes.byref(X.struct()), float(delta), SYNC if sync else 0, _ptr(out), _ptr(ws),
                                 ws.numel(), _stream()))
+    return out
+
+
+def truncate_noalloc(X: BlockSparse, delta: float, sync=False):
+    """truncate() through the allocation-free entry point (the library's
+    fixed scratch array instead of a workspace; X.cap <= 2^20)."""
+    out = torch.zeros(2, dtype=torch.float64, device=X.device)
+    _check(lib().spamm_truncate_noalloc(ctypes.byref(X.struct()), float(delta), SYNC if sync else 0, _ptr(out),
+                                        _stream()))
     return out
 
 

@@ -807,6 +807,27 @@ int spamm_truncate(spamm_bsm* X, double delta, uint32_t flags, double* removed_o
     return SPAMM_OK;
 }
 
+int64_t spamm_truncate_noalloc_max_cap(void) { return trunc_noalloc_max_cap(); }
+
+int spamm_truncate_noalloc(spamm_bsm* X, double delta, uint32_t flags, double* removed_out, spamm_stream_t stream) {
+    int rc = check_bsm(X, "X", true);
+    if (rc) return rc;
+    if (!(delta >= 0.0) || !isfinite(delta)) return fail(SPAMM_EINVAL, "delta must be finite and >= 0");
+    if (X->cap > trunc_noalloc_max_cap())
+        return fail(SPAMM_EINVAL, "spamm_truncate_noalloc: capacity %lld exceeds its limit of %lld slots",
+                    (long long)X->cap, (long long)trunc_noalloc_max_cap());
+    TruncNoallocScratch sc;
+    HIP_TRY(trunc_noalloc_scratch(&sc));
+    hipStream_t s = (hipStream_t)stream;
+    fill_i32(sc.ovf, 1, 0, s);
+    launch_truncate(view(X), nullptr, delta, 1.0, sc.temp, X->cap, sc.stats, sc.ovf, nullptr, s);
+    if (removed_out)
+        hipLaunchKernelGGL(k_trunc_report, dim3(1), dim3(1), 0, s, sc.stats, nullptr, delta, 1.0, removed_out);
+    HIP_TRY(hipGetLastError());
+    if (flags & SPAMM_SYNC) HIP_TRY(hipStreamSynchronize(s));
+    return SPAMM_OK;
+}
+
 size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
                                   int32_t tape_steps, int32_t precision) {
     if (nb < 1 || N < 1 || cap_blocks < 1) return 0;

@@ -243,6 +243,13 @@ void launch_reblock(const MatView& X, const MatView& Y, int32_t* flag, int32_t* 
 
 // trunc.hip
 size_t trunc_temp_bytes(int64_t cap);
+struct TruncNoallocScratch {
+    void* temp;      // truncation temporaries for up to trunc_noalloc_max_cap() slots
+    int64_t* stats;  // [4]
+    int32_t* ovf;    // [4]
+};
+int64_t trunc_noalloc_max_cap();
+hipError_t trunc_noalloc_scratch(TruncNoallocScratch* out);
 void launch_truncate(const MatView& X, const double* delta_dev, double delta_host, double delta_scale,
                      void* temp, int64_t cap, int64_t* stats /* [4] */, int32_t* ovf, const int32_t* done,
                      hipStream_t s);

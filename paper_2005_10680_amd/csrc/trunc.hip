@@ -16,6 +16,8 @@
 // (k << 22 | r*nb + c) with exact per-digit key sums in LDS.
 #include <math.h>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -191,6 +193,43 @@ __global__ void k_trunc_reset(TruncTemp t, int64_t* stats, const int32_t* __rest
         *t.thr = 0;
         if (stats) { stats[0] = 0; stats[1] = 0; }
     }
+}
+
+// Scratch of the allocation-free truncation (spamm_truncate_noalloc): the
+// candidate keys of up to kTruncNoallocMaxCap slots, then the removal
+// statistics and the overflow word.  One copy per GPU, held until the process
+// ends; every call on a GPU reuses it (the kernels clear what must start at
+// zero), so calls that overlap on one GPU race.
+constexpr int64_t kTruncNoallocMaxCap = (int64_t)1 << 20;
+constexpr size_t kTruncNoallocStatsOff = ((size_t)kTruncNoallocMaxCap * 16 + 64 + 255) & ~(size_t)255;
+constexpr size_t kTruncNoallocBytes = kTruncNoallocStatsOff + 256;
+static __device__ __align__(256) char scratch[kTruncNoallocBytes];
+
+int64_t trunc_noalloc_max_cap() { return kTruncNoallocMaxCap; }
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (the host-side name is not a device address).
+hipError_t trunc_noalloc_scratch(TruncNoallocScratch* out) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDev] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        ptr[dev] = p;
+    }
+    char* base = (char*)ptr[dev];
+    out->temp = base;
+    out->stats = (int64_t*)(base + kTruncNoallocStatsOff);
+    out->ovf = (int32_t*)(base + kTruncNoallocStatsOff + 64);
+    return hipSuccess;
 }
 
 void launch_truncate(const MatView& X, const double* delta_dev, double delta_host, double delta_scale, void* temp,

@@ -22,7 +22,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libspamm.so not
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^(?:const\s+)?(?:int|size_t|double|char|void)\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text, re.M)
+    names = re.findall(r"^(?:const\s+)?(?:int64_t|int|size_t|double|char|void)\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", text, re.M)
     return sorted(set(names))
 
 
