@@ -140,8 +140,9 @@ int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev
  * Q = 2^(floor(log2 T) - 40), each unit gets the integer key
  * k = ceil(w*sq/Q) (w = 1 diagonal, 2 pair; saturated at 2^41).  Units are
  * taken in ascending (k, r*nb + c) order and the longest prefix whose key
- * sum stays below K_T = floor(T/Q) - ceil(floor(T/Q)/2^29) is removed,
- * which guarantees the exact removed Frobenius norm is < delta.
+ * sum stays below K_T = floor(T/Q) is removed, which guarantees the exact
+ * removed Frobenius norm is < delta (the key sum is then at most K_T - 1,
+ * a margin of Q > 2^-41 T over the rounding of sq and of T).
  * Removed slots become holes.  removed_out: device [2] = {removed units,
  * removed sum of w*sq}; may be NULL.
  * Workspace: spamm_truncate_workspace_bytes(cap).
@@ -239,8 +240,11 @@ typedef struct sp2_iter_log {
  * X~_0 truncated with delta_0, then X~_i = trunc(SpAMM-evaluated f_i(X~_{i-1}))
  * with f_i = x^2 or 2x - x^2 (the trace closer to n_occ), the SpAMM
  * threshold chosen by the sweep with budget delta_i/2 and the truncation
- * with delta_i/2 (Algorithm 5), delta_i = eps*g_i/(4*n_max) from the
- * mapped gap g_i, until the stop rule fires.
+ * with delta_i/2 (Algorithm 5), delta_i = eps*g_i/(2*sqrt(2)*(n_max + 1))
+ * from the mapped gap g_i (the occupied projector then drifts by at most
+ * eps/2 over the run, Davis-Kahan), until the stop rule fires: |e| <= e_tol
+ * or, with e = tr X~ - ||X~||_F^2, |e_{i-2}| <= 1/8 and
+ * |e_i| > 4 e_{i-2}^2 / (1 - 2|e_{i-2}|)^2 (no quadratic convergence).
  *   F     : symmetric input with norms NOT required (computed internally).
  *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise), with
  *           its block norms (as spamm_build_norms computes them).

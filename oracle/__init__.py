@@ -310,14 +310,23 @@ class TruncInfo:
 
 
 def trunc_quanta(delta: float):
-    """(T, Q, K_T) of the truncation rule for budget delta."""
+    """(T, Q, K_T) of the truncation rule for budget delta: T = RN(delta^2),
+    Q = 2^(e_T - 40) with T in [2^e_T, 2^(e_T + 1)) (not below 2^-1000),
+    K_T = floor(T/Q).
+
+    Why removing units whose integer keys k = ceil(w sq / Q) sum to less
+    than K_T keeps ||E||_F < delta: the key sum is then at most K_T - 1, so
+    sum(w sq) <= Q (K_T - 1) <= T - Q; Q > 2^-41 T, and each sq is the
+    exact sum of squares S rounded once (S <= sq (1 + 2^-52)), so the exact
+    removed sum of squares is below (T - Q)(1 + 2^-52) < T (1 - 2^-42) and
+    T <= delta^2 (1 + 2^-53): below delta^2.  With a key sum equal to K_T
+    it could reach T, which may exceed delta^2 when RN rounded up."""
     T = delta * delta
     if not (T > 0.0 and math.isfinite(T)):
         return T, 0.0, 0
     e_T = math.frexp(T)[1] - 1
     Q = math.ldexp(1.0, max(e_T - KEY_BITS, -1000))
-    tq = int(math.floor(T / Q))
-    kt = tq - ((tq + (1 << 29) - 1) >> 29)
+    kt = int(math.floor(T / Q))
     return T, Q, kt
 
 
@@ -438,20 +447,36 @@ def tier_constant(precision: int, b: int) -> float:
     gamma_3b(2^-23) (1 + 2u)(1+u)^2, and 2^-100 covers entries below the
     BF16 normal range (relative to the scaled blocks, whose norms are >= 1).
 
-    Both rounded up by a factor 1 + 2^-40."""
+    Both rounded up by a factor 1 + 2^-40 (tier_constant_parts gives the
+    terms before that factor)."""
+    parts = tier_constant_parts(precision, b)
+    if not parts:
+        return 0.0
+    return (parts["represent"] + parts["accumulate"] + parts["underflow"]) * (1.0 + 2.0 ** -40)
+
+
+def tier_constant_parts(precision: int, b: int) -> dict:
+    """The terms of tier_constant (see there), by the error they cover:
+    "represent": rounding the operands to the tier's format (FP32: 2u + u^2;
+    split BF16: kappa, the dropped lo*lo term and the split residuals);
+    "accumulate": the FP32 accumulation of the exact operand products, the
+    number of terms per output entry (b for FP32, 3b for the three split
+    products) times the assumed unit roundoff 2^-23, as gamma_m, scaled by
+    the operands' size relative to the exact ones; "underflow": entries below
+    the BF16 normal range (split BF16 only)."""
     m = float(b)
     if precision == 1:
         u = 2.0 ** -24
         ue = 2.0 * u
         gam = m * ue / (1.0 - m * ue)
-        return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 2.0 ** -40)
+        return {"represent": 2.0 * u + u * u, "accumulate": gam * (1.0 + u) * (1.0 + u), "underflow": 0.0}
     if precision == 2:
         u = 2.0 ** -8
         ue = 2.0 * 2.0 ** -24
         kappa = u * u * ((1.0 + u) ** 2 + 2.0 * (1.0 + u) ** 3 + u * u * (1.0 + u) ** 2)
         gam = 3.0 * m * ue / (1.0 - 3.0 * m * ue)
-        return (kappa + gam * (1.0 + 2.0 * u) * (1.0 + u) ** 2 + 2.0 ** -100) * (1.0 + 2.0 ** -40)
-    return 0.0
+        return {"represent": kappa, "accumulate": gam * (1.0 + 2.0 * u) * (1.0 + u) ** 2, "underflow": 2.0 ** -100}
+    return {}
 
 
 @dataclass
@@ -479,12 +504,27 @@ class SP2State:
     e_hist: list
 
 
+# RN(2 sqrt(2)): the Davis-Kahan factor of the tolerance schedule
+DK_FACTOR = 2.8284271247461903
+
+
 def step_delta(p: SP2Params, gap: float) -> float:
-    """delta_i = eps * g_i / (4 n_max), g_i the mapped gap of X_i (reading of
-    the refs the paper cites for the tolerance schedule), or the constant."""
+    """delta_i = eps g_i / (2 sqrt(2) (n_max + 1)), g_i the mapped gap of
+    X_i, or the constant.
+
+    Derivation (the paper defers the schedule to the references it cites):
+    step i perturbs f_i(X~_{i-1}) by less than delta_i in Frobenius norm
+    (SpAMM and truncation together).  With g_i the gap of the exactly mapped
+    spectrum around the occupied/virtual split, the Davis-Kahan sin-theta
+    theorem moves the projector onto the occupied subspace by at most
+    sqrt(2) delta_i / g_i (first order in delta_i / g_i).  A run has at most
+    n_max + 1 perturbations (X~_0 and n_max steps), so the projector drifts
+    by at most sum sqrt(2) delta_i / g_i <= eps / 2 in all; the other half
+    of eps is left to the distance of D~ from its own projector at the
+    stop, 2 |tr X~ - ||X~||_F^2| (bounded when the spectrum lies in [0, 1])."""
     if math.isfinite(p.delta_const):
         return p.delta_const
-    return p.eps * gap / (4.0 * p.n_max)
+    return p.eps * gap / (DK_FACTOR * float(p.n_max + 1))
 
 
 def choose_branch(t1: float, t2: float, n_occ: int) -> int:
@@ -498,21 +538,31 @@ def map_gap(x: float, branch: int) -> float:
 
 
 def should_stop(e_hist: list, e_tol: float) -> bool:
-    """Stop when |e| <= e_tol, or once two further steps failed to reduce |e|
-    after it fell below 1e-3 (rounding/truncation noise floor), or once two
-    further steps failed to square it after it fell below 1e-8: there one
-    step of each SP2 polynomial takes every eigenvalue's distance d to
-    {0, 1} to at most 4 d^2, so |e_i| > 4 e_{i-2}^2 means the iterate is at
-    the noise floor (the quadratic-convergence test of parameterless
-    stopping criteria)."""
+    """Stop when |e_i| <= e_tol, or when two steps failed to converge
+    quadratically: |e_{i-2}| <= 1/8 and |e_i| > 4 e_{i-2}^2 / (1 - 2|e_{i-2}|)^2.
+
+    Derivation (the idea of the parameterless stopping criteria the paper
+    cites): e = tr X - ||X||_F^2 = sum_k d_k (1 - d_k) with d_k the distance
+    of eigenvalue k to {0, 1}.  Two SP2 steps with different polynomials take
+    every d to at most 4 d^2, and for e <= 1/8 every d_k <= 2e, so
+    sum d_k <= e / (1 - 2e) and the next e is at most
+    4 sum d_k^2 <= 4 e^2 / (1 - 2e)^2 (< e).  Two steps with the same
+    polynomial are chosen by the trace rule only when the side they do not
+    square is already of second order, which gives the same bound to first
+    order.  In exact arithmetic the test therefore never fires; when it does,
+    the rounding, SpAMM and truncation errors dominate e and further steps
+    add error without convergence.  1/8 is where the bound is a contraction
+    (4e / (1 - 2e)^2 < 1 needs e < 0.134)."""
     if not e_hist:
         return False
     if abs(e_hist[-1]) <= e_tol:
         return True
-    if len(e_hist) >= 3 and abs(e_hist[-3]) < 1e-3 and abs(e_hist[-1]) >= abs(e_hist[-3]):
-        return True
-    if len(e_hist) >= 3 and abs(e_hist[-3]) < 1e-8 and abs(e_hist[-1]) > 4.0 * e_hist[-3] * e_hist[-3]:
-        return True
+    if len(e_hist) >= 3:
+        a = abs(e_hist[-3])
+        if a <= 0.125:
+            d = 1.0 - 2.0 * a
+            if abs(e_hist[-1]) > 4.0 * a * a / (d * d):
+                return True
     return False
 
 

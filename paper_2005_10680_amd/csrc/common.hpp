@@ -185,10 +185,13 @@ struct Sp2Ctl {
 // device control kernel so both take identical decisions (double precision,
 // one rounding per operation, no contraction).
 // ---------------------------------------------------------------------------
-// delta_i = eps * g / (4 n_max) from the mapped gap g, or the given constant
+// delta_i = eps * g / (2 sqrt(2) (n_max + 1)) from the mapped gap g, or the
+// given constant.  Each step perturbs the iterate by < delta_i (Frobenius),
+// which moves the occupied projector by at most sqrt(2) delta_i / g
+// (Davis-Kahan, first order); over X~_0 and n_max steps that is eps / 2.
 SPAMM_HD double sp2_step_delta(double eps, int n_max, double delta_const, double gap) {
     if (!(delta_const != delta_const)) return delta_const;  // not NaN: explicit delta
-    return eps * gap / (4.0 * (double)n_max);
+    return eps * gap / (2.8284271247461903 * (double)(n_max + 1));
 }
 // SP2: x^2 (0) when its trace lands closer to n_occ, else 2x - x^2 (1)
 SPAMM_HD int sp2_choose_branch(double t1, double t2, int64_t n_occ) {
@@ -196,16 +199,23 @@ SPAMM_HD int sp2_choose_branch(double t1, double t2, int64_t n_occ) {
     return fabs(t2 - no) <= fabs((2.0 * t1 - t2) - no) ? 0 : 1;
 }
 SPAMM_HD double sp2_map_gap(double x, int br) { return br == 0 ? x * x : 2.0 * x - x * x; }
-// stop when |e_i| <= e_tol, or at the noise floor: |e_i| >= |e_{i-2}| once
-// |e_{i-2}| < 1e-3, or |e_i| > 4 e_{i-2}^2 once |e_{i-2}| < 1e-8.
+// stop when |e_i| <= e_tol, or when two steps failed to converge
+// quadratically: |e_{i-2}| <= 1/8 and |e_i| > 4 e_{i-2}^2 / (1 - 2|e_{i-2}|)^2.
+// With e = sum over eigenvalues of d (1 - d), d the distance to {0, 1}, two
+// SP2 steps take every d to at most 4 d^2, and e <= 1/8 keeps every d below
+// 2e, so exact arithmetic stays under the bound; above it, rounding, SpAMM
+// and truncation errors dominate and further steps do not converge.
 // e: the last n_e values, most recent first (n_e <= 3).
 SPAMM_HD bool sp2_should_stop(const double* e, int n_e, double e_tol) {
     if (n_e < 1) return false;
     if (fabs(e[0]) <= e_tol) return true;
-    if (n_e >= 3 && fabs(e[2]) < 1e-3 && fabs(e[0]) >= fabs(e[2])) return true;
-    // deep in the quadratic regime a step of each polynomial takes every
-    // eigenvalue's distance d to {0, 1} to at most 4 d^2: more is noise
-    if (n_e >= 3 && fabs(e[2]) < 1e-8 && fabs(e[0]) > 4.0 * e[2] * e[2]) return true;
+    if (n_e >= 3) {
+        const double a = fabs(e[2]);
+        if (a <= 0.125) {
+            const double d = 1.0 - 2.0 * a;
+            if (fabs(e[0]) > 4.0 * a * a / (d * d)) return true;
+        }
+    }
     return false;
 }
 // RN(a - b) for double-doubles a = ahi + alo, b = bhi + blo

@@ -5,11 +5,13 @@
 // (weight 2, keyed by the upper block).  With T = RN(delta^2) and the
 // power-of-two quantum Q = 2^(floor(log2 T) - 40), a unit's integer key is
 // k = ceil(w * sq / Q) (saturated at 2^41), and the budget is
-// K_T = floor(T/Q) - ceil(floor(T/Q) / 2^29).  Units are ordered by
-// (k, r*nb + c) and the longest prefix whose key sum is < K_T is removed.
-// Integer keys make the prefix sums exact and order-independent, so the
-// removed set is unique; ceil() and the 2^-29 margin make it a rigorous
-// bound on the exact removed norm.
+// K_T = floor(T/Q).  Units are ordered by (k, r*nb + c) and the longest
+// prefix whose key sum is < K_T is removed.  Integer keys make the prefix
+// sums exact and order-independent, so the removed set is unique.  The
+// bound is rigorous: a key sum of at most K_T - 1 means sum(w sq) <= T - Q
+// with Q > 2^-41 T, which leaves room for the rounding of each sq (2^-53
+// relative) and of T = RN(delta^2) (2^-53), so the exact removed squared
+// norm stays below delta^2.
 //
 // Only units with k < K_T can ever be removed; they are collected first and
 // the cut is found by an 8-pass radix select over the 64-bit composite key
@@ -45,8 +47,7 @@ SPAMM_DEV TruncQuanta trunc_quanta(double delta) {
     int eq = eT - kKeyBits;
     if (eq < -1000) eq = -1000;
     q.Q = ldexp(1.0, eq);
-    uint64_t tq = (uint64_t)floor(T / q.Q);
-    q.kt = tq - ((tq + (1ull << 29) - 1) >> 29);
+    q.kt = (uint64_t)floor(T / q.Q);
     if (q.kt == 0) q.any = false;
     return q;
 }

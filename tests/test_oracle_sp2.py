@@ -193,15 +193,19 @@ def test_leaf_bound_tier_selection_converges(precision):
 
 
 def test_stop_rule_cases():
-    """The stop rule on explicit histories (oldest first): e_tol, the
-    non-decrease test below 1e-3 and the quadratic test below 1e-8."""
+    """The stop rule on explicit histories (oldest first): e_tol, and the
+    quadratic-convergence test |e_i| > 4 e_{i-2}^2 / (1 - 2|e_{i-2}|)^2,
+    applied once |e_{i-2}| <= 1/8."""
     S = oracle.should_stop
     assert not S([], 0.0)
     assert S([0.5, 1e-4, 0.0], 0.0)                       # |e| <= e_tol
-    assert not S([1e-2, 1e-3, 9e-4], 0.0)                 # above 1e-3 two steps back: keep going
+    assert not S([0.2, 0.1, 0.15], 0.0)                   # above 1/8 two steps back: keep going
+    assert not S([0.1, 0.05, 0.06], 0.0)                  # 4 (0.1)^2 / 0.8^2 = 0.0625
+    assert S([0.1, 0.05, 0.07], 0.0)
+    assert not S([0.125, 0.05, 0.111], 0.0)               # 4/64 / (3/4)^2 = 0.1111...
+    assert S([0.125, 0.05, 0.1112], 0.0)
+    assert not S([0.1251, 0.05, 0.12], 0.0)               # just above 1/8
     assert S([5e-4, 1e-4, 5e-4], 0.0)                     # no decrease over two steps
-    assert not S([5e-4, 1e-4, 4.9e-4], 0.0)
-    assert not S([1e-7, 1e-9, 1e-13], 0.0)                # 1e-7 is not below 1e-8
-    assert not S([5e-9, 1e-12, 9e-17], 0.0)               # squared: 9e-17 <= 4 (5e-9)^2 = 1e-16
-    assert S([5e-9, 1e-12, 2e-16], 0.0)                   # more than 4 (5e-9)^2: noise floor
+    assert not S([5e-9, 1e-12, 9e-17], 0.0)               # squared: 9e-17 <= 4 (5e-9)^2 / (1 - 1e-8)^2
+    assert S([5e-9, 1e-12, 2e-16], 0.0)                   # more: the noise floor
     assert S([-7.6e-9, 7.6e-10, -2.5e-10], 0.0)           # signs do not matter
