@@ -8,15 +8,22 @@ synthetic 3D system n = 16384, leaf 64, 32 candidate thresholds, eps = 1e-6,
 with the input resident in HBM.  value = executed kept-pair flops (2 b^3 per
 pair, i <= j outputs) over the whole timed purification.
 
-Besides the timed steps the line carries: the same purification as a
-replayed graph, with the FP32 and split-BF16 leaf-product tiers; the
-paper's multiplication experiment on the converged D~ (SpAMM at the swept
-threshold against the exact product plus truncation, delta = 1e-6, 1e-8,
-1e-10); the n = 65536 system in FP64 and both tiers against a reference
-run; the oracle timed on a sample of the workload (cpu_baseline).
+Besides the timed steps the line carries: ||D - D~||_F of every
+purification against the exact projector from a dense eigensolver (outside
+the timed regions); the same purification as a replayed graph, selecting
+with B_flat, and with the FP32 and split-BF16 leaf-product tiers; the
+paper's three purification variants (Algorithms 5, 4, 1); the paper's
+multiplication experiment on the converged D~ (SpAMM at the swept threshold,
+exact product plus truncation, and SpAMM plus truncation at half the budget
+each, delta = 1e-6, 1e-8, 1e-10); the small chain; the n = 65536 system in
+FP64 and both tiers against a reference run; the reverse mode at n = 32768
+with a finite-difference check; the 64-system batched workload in FP64 and
+FP32 against the same systems run one after another; the oracle timed on a
+sample of the workload and on the whole chain purification (cpu_baseline).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--verify]
-                    [--adjoint] [--batch N] [--no-big] [--no-protocol] [--no-mixed]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-verify]
+                    [--no-adjoint] [--batch N] [--no-big] [--no-protocol] [--no-mixed]
+                    [--no-variants]
 """
 from __future__ import annotations
 
@@ -57,15 +64,18 @@ def main():
     ap.add_argument("--leaf", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--verify", action="store_true", help="check ||D - D~||_F with a dense eigensolver")
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the dense-eigensolver check of ||D - D~||_F (on by default, outside the timed region)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision purification")
     ap.add_argument("--graph", type=int, default=8,
                     help="also time the graph-captured loop, polling every K iterations (0: skip)")
-    ap.add_argument("--adjoint", action="store_true",
-                    help="also time the reverse mode on the n = 32768 system with a banded W (checkpointed tape)")
-    ap.add_argument("--batch", type=int, default=0,
-                    help="also time the batched workload: the first N of the 64 systems (sizes log-uniform in "
-                         "[2048, 32768], seed 4), leaf sizes by the autotuner")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the reverse mode on the n = 32768 system with a banded W (checkpointed tape)")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="systems of the batched workload to time (the first N of the 64 systems, sizes "
+                         "log-uniform in [2048, 32768], seed 4, leaf sizes by the autotuner; 0: skip)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the three purification variants (Algorithms 5, 4 and 1) on the main workload")
     ap.add_argument("--no-protocol", action="store_true",
                     help="skip the paper's multiplication experiment on the converged D~ "
                          "(delta = 1e-6, 1e-8, 1e-10)")
@@ -101,10 +111,10 @@ def main():
     max_pairs = nb * nb * (nb + 1) // 2
     eps = 1e-6
 
-    def run_once(precision="fp64", graph_steps=0, keep_tape=False, cap_=None, bound="tree"):
+    def run_once(precision="fp64", graph_steps=0, keep_tape=False, cap_=None, bound="tree", variant="hybrid"):
         return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap_ or cap,
                         max_pairs=max_pairs, precision=precision, graph_steps=graph_steps, keep_tape=keep_tape,
-                        bound=bound)
+                        bound=bound, variant=variant)
 
     log(f"input ready: n={n} leaf={b} blocks={Fh.nblk}")
     for w in range(args.warmup):
@@ -128,6 +138,36 @@ def main():
         logs_all.append(res.logs)
     total_s = sum(times)
     value = flops / total_s / 1e12
+
+    # the exact projector D = theta(mu - F) from a dense eigensolver (outside
+    # every timed region), for ||D - D~||_F of each purification below
+    dref = None
+    if not args.no_verify:
+        t0 = time.perf_counter()
+        Fd = torch.from_numpy(Fh.to_dense()).to(dev)
+        _, U = torch.linalg.eigh(Fd)
+        del Fd
+        Uo = U[:, :n_occ].contiguous()
+        del U
+        dref = Uo @ Uo.T
+        del Uo
+        torch.cuda.synchronize()
+        log(f"dense reference projector in {time.perf_counter() - t0:.1f} s")
+
+    def verify_err(r):
+        """||D - D~||_F of a purification result (None without the reference)."""
+        if dref is None:
+            return None
+        Dh = r.D.to_host()
+        Dd = torch.zeros((n, n), dtype=torch.float64, device=dev)
+        for k in range(Dh.brow.shape[0]):
+            rr, cc = int(Dh.brow[k]), int(Dh.bcol[k])
+            blk = torch.from_numpy(np.ascontiguousarray(Dh.vals[k].T)).to(dev)
+            nr, nc = min(b, n - rr * b), min(b, n - cc * b)
+            Dd[rr * b:rr * b + nr, cc * b:cc * b + nc] = blk[:nr, :nc]
+        e = float(torch.linalg.norm(Dd - dref).item())
+        del Dd
+        return e
     steps = [l for l in res.logs if l["branch"] >= 0]
     ngemm = len(steps) * args.steps
     avg_gemm_ms = gemm_ms / ngemm
@@ -149,6 +189,7 @@ def main():
         "config": {"workload": f"sp2_hybrid_sys3d_n{n}_leaf{b}_tau32_eps1e-6", "n": n, "leaf": b,
                    "candidates": 32, "eps": eps, "variant": "hybrid", "n_occ": n_occ, "seed": args.seed},
         "sp2_time_s": round(float(np.median(times)), 4),
+        "verify_fro_err": verify_err(res),
         "iterations": len(steps),
         "kept_pairs_per_run": int(sum(l["npairs"] for l in steps)),
         "phase_ms_per_run": {k: round(sum(l[k] for l in steps), 3)
@@ -184,8 +225,6 @@ def main():
                              "same_decisions": bool(same)}
 
     # the same purification selecting tau (and sigma) with the leaf-level bound B_flat
-    res_mixed = {}
-    res_flat = None
     if not args.no_mixed:
         for prec, key in (("fp64", "bound_flat"), ("bf16x3", "bound_flat_bf16x3")):
             run_once(prec, bound="flat")
@@ -196,8 +235,6 @@ def main():
                 rf = run_once(prec, bound="flat")
                 torch.cuda.synchronize()
                 ftimes.append(time.perf_counter() - t0)
-            if prec == "fp64":
-                res_flat = rf
             fsteps = [l for l in rf.logs if l["branch"] >= 0]
             fpairs = sum(l["npairs"] for l in fsteps)
             flow = sum(l["npairs_low"] for l in fsteps)
@@ -210,14 +247,9 @@ def main():
                         "speedup_vs_fp64_tree": round(float(np.median(times)) / float(np.median(ftimes)), 4),
                         "mean_tau_ratio_vs_tree_fp64": round(float(np.exp(np.mean(
                             [np.log(a["tau"] / b["tau"]) for a, b in zip(fsteps, steps)
-                             if a["tau"] > 0 and b["tau"] > 0]))), 3)}
-            if prec != "fp64":
-                res_mixed[key] = rf
-
-    # reverse mode at n = 32768 with a banded W (checkpointed tape)
-    if args.adjoint:
-        torch.cuda.empty_cache()
-        out["adjoint"] = adjoint_leg(dev, P, synth, torch)
+                             if a["tau"] > 0 and b["tau"] > 0]))), 3),
+                        "verify_fro_err": verify_err(rf)}
+            del rf
 
     # mixed precision (FP32 and split-BF16 leaf-product tiers) on the same workload
     if not args.no_mixed:
@@ -230,7 +262,6 @@ def main():
                 rm = run_once(tier)
                 torch.cuda.synchronize()
                 mtimes.append(time.perf_counter() - t0)
-            res_mixed[key] = rm
             msteps = [l for l in rm.logs if l["branch"] >= 0]
             mpairs = sum(l["npairs"] for l in msteps)
             mlow = sum(l["npairs_low"] for l in msteps)
@@ -242,43 +273,22 @@ def main():
                         "kept_TFLOP_per_s": round(mpairs * 2.0 * b ** 3 / float(np.median(mtimes)) / 1e12, 4),
                         "speedup_vs_fp64": round(float(np.median(times)) / float(np.median(mtimes)), 4),
                         "phase_ms_per_run": {k: round(sum(l[k] for l in msteps), 3)
-                                             for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc")}}
+                                             for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc")},
+                        "verify_fro_err": verify_err(rm)}
+            del rm
 
-    if args.verify:
-        D = res.D.to_host()
-        Dd = np.zeros((n, n))
-        for k in range(D.brow.shape[0]):
-            r, c = int(D.brow[k]), int(D.bcol[k])
-            blk = D.vals[k].T
-            rr, cc = min(b, n - r * b), min(b, n - c * b)
-            Dd[r * b:r * b + rr, c * b:c * b + cc] = blk[:rr, :cc]
-        Fd = torch.from_numpy(Fh.to_dense()).to(dev)
-        w, U = torch.linalg.eigh(Fd)
-        Uo = U[:, :n_occ]
-        Dref = Uo @ Uo.T
-        err = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
-        out["verify_fro_err"] = err
-        for key, rm in res_mixed.items():
-            Dm = rm.D.to_host()
-            Dd[:] = 0.0
-            for k in range(Dm.brow.shape[0]):
-                r, c = int(Dm.brow[k]), int(Dm.bcol[k])
-                blk = Dm.vals[k].T
-                rr, cc = min(b, n - r * b), min(b, n - c * b)
-                Dd[r * b:r * b + rr, c * b:c * b + cc] = blk[:rr, :cc]
-            out[key]["verify_fro_err"] = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
-        if res_flat is not None:
-            res_mixed["bound_flat"] = res_flat
-            Dm = res_flat.D.to_host()
-            Dd[:] = 0.0
-            for k in range(Dm.brow.shape[0]):
-                r, c = int(Dm.brow[k]), int(Dm.bcol[k])
-                blk = Dm.vals[k].T
-                rr, cc = min(b, n - r * b), min(b, n - c * b)
-                Dd[r * b:r * b + rr, c * b:c * b + cc] = blk[:rr, :cc]
-            out["bound_flat"]["verify_fro_err"] = float(torch.linalg.norm(torch.from_numpy(Dd).to(dev) - Dref).item())
-        log(f"verified: fp64 {err:.3e}" + "".join(f", {k} {out[k]['verify_fro_err']:.3e}" for k in res_mixed))
-        del Fd, U, Uo, Dref
+    # the paper's three purification variants on the same workload:
+    # Algorithm 5 (hybrid), 4 (SpAMM only) and 1 (exact product + truncation)
+    if not args.no_variants:
+        out["variants"] = variants_leg(run_once, torch, args.steps, b, eps, verify_err)
+
+    if dref is not None:
+        errs = [out["verify_fro_err"]] + [out[k]["verify_fro_err"] for k in
+                                          ("bound_flat", "bound_flat_bf16x3", "mixed", "mixed_bf16x3") if k in out]
+        log("verified: " + ", ".join(f"{e:.3e}" for e in errs))
+        del dref
+        dref = None
+        torch.cuda.empty_cache()
 
     if args.copy_mb:
         src = torch.ones(args.copy_mb * 2 ** 20 // 8, dtype=torch.float64, device=dev)
@@ -293,17 +303,26 @@ def main():
         out["protocol"] = protocol_leg(P, torch, res.D, taus)
         out["chain1024"] = chain_leg(P, torch, synth)
 
-    if args.batch > 0:
-        out["batched"] = batch_leg(args, dev, P, synth, batch_mats)
-
     if not args.no_big:
         keep = res
         out["big"] = big_leg(P, torch, synth)
         res = keep
+        torch.cuda.empty_cache()
+
+    # reverse mode at n = 32768 with a banded W (checkpointed tape)
+    if not args.no_adjoint:
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_leg(dev, P, synth, torch)
+        torch.cuda.empty_cache()
+
+    if args.batch > 0:
+        out["batched"] = batch_leg(args, dev, P, synth, batch_mats)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("timing the oracle on a sample (cpu baseline)")
         out["cpu_baseline"] = cpu_baseline(res, Fh, taus, b, args.cpu_seconds)
+        out["cpu_baseline_chain1024"] = cpu_chain_baseline(out.get("chain1024"))
 
     print(json.dumps(out), flush=True)
 
@@ -429,6 +448,43 @@ def adjoint_leg(dev, P, synth, torch):
             "checkpoint_every": every, "delta_const": dconst, "loss": L0,
             "forward_with_checkpoints_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
             "directional_derivative": got, "central_differences": fd}
+
+
+def variants_leg(run_once, torch, reps, b, eps, verify_err):
+    """The purification of the main workload with each of the paper's
+    variants: Algorithm 5 (hybrid: SpAMM with delta_i/2, truncation with
+    delta_i/2), Algorithm 4 (SpAMM with delta_i, no truncation) and
+    Algorithm 1 (exact product, truncation with delta_i).  Per variant: time
+    to D~ (median of reps host-loop runs), iterations, per-iteration mean of
+    the threshold sweep (T_CSE), the product (T_SpAMM, or T_mul for
+    Algorithm 1: kept-pair list and leaf products) and the truncation
+    (T_trunc), the mean and largest block counts of X^_i and X~_i, and
+    ||D - D~||_F against eps."""
+    rows = {}
+    for v in ("hybrid", "spamm", "truncmul"):
+        run_once(variant=v)
+        t, r = timed(lambda: run_once(variant=v), torch, reps)
+        st = [lg for lg in r.logs if lg["branch"] >= 0]
+        it = max(len(st), 1)
+        pairs = sum(lg["npairs"] for lg in st)
+        rows[v] = {"algorithm": {"hybrid": 5, "spamm": 4, "truncmul": 1}[v], "sp2_time_s": round(t, 4),
+                   "iterations": len(st), "kept_pairs_per_run": int(pairs),
+                   "kept_TFLOP_per_s": round(pairs * 2.0 * b ** 3 / t / 1e12, 3),
+                   "ms_per_iteration": {
+                       "cse": round(sum(lg["ms_sweep"] for lg in st) / it, 4),
+                       "product": round(sum(lg["ms_pairs"] + lg["ms_gemm"] + lg["ms_norms"] for lg in st) / it, 4),
+                       "trunc": round(sum(lg["ms_trunc"] for lg in st) / it, 4),
+                       "total": round(sum(lg["ms_total"] for lg in st) / it, 4)},
+                   "blocks_Xhat_mean_max": [round(float(np.mean([lg["nslot_hat"] for lg in st])), 1),
+                                            int(max(lg["nslot_hat"] for lg in st))],
+                   "blocks_Xtilde_mean_max": [round(float(np.mean([lg["nslot_kept"] for lg in st])), 1),
+                                              int(max(lg["nslot_kept"] for lg in st))],
+                   "status": int(r.status), "eps": eps, "verify_fro_err": verify_err(r)}
+        log(f"variant {v}: {t:.3f} s, {len(st)} iterations, {pairs} kept pairs, "
+            f"err {rows[v]['verify_fro_err']}")
+        del r
+        torch.cuda.empty_cache()
+    return rows
 
 
 def fro_diff(A, B, torch):
@@ -557,6 +613,32 @@ def protocol_leg(P, torch, D, taus, deltas=(1e-6, 1e-8, 1e-10), reps=3):
             f"trunc {1e3 * t_tr:.2f} ms")
         rows[-1]["err_below_bound"] = bool(err <= bnd or err < 1e-300)
         rows[-1]["err_below_delta"] = bool(err < delta)
+        # the hybrid step (Algorithm 5): SpAMM with delta/2, then truncation with delta/2
+        t_cse_h, (_, idx_h, tau_h) = timed(lambda: P.sweep_tau(D, D, taus, delta / 2, b_transposed=True), torch,
+                                           reps)
+        tau_hv = float(tau_h.item())
+        t_sp_h, r = timed(lambda: P.multiply(D, D, tau_hv, symmetric=True, b_transposed=True, out=Ca), torch, reps)
+        kept_h = int(r[1][0].item())
+        nnz_hat = live_blocks(Ca)
+        tt = []
+        for _ in range(reps):
+            ns = int(Ca.nslot.item())
+            for a in ("nslot", "brow", "bcol", "map"):
+                getattr(Ct, a).copy_(getattr(Ca, a))
+            Ct.val[: ns * b * b].copy_(Ca.val[: ns * b * b])
+            P.build_norms(Ct)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.truncate(Ct, delta / 2, sync=True)
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - t0)
+        err_h = fro_diff(Ct, Cx, torch)
+        rows[-1]["hybrid"] = {"tau": tau_hv, "kept_pairs": kept_h, "nnz_hat": nnz_hat, "nnz_tilde": live_blocks(Ct),
+                              "ms_cse": round(1e3 * t_cse_h, 3), "ms_spamm": round(1e3 * t_sp_h, 3),
+                              "ms_trunc": round(1e3 * float(np.median(tt)), 3), "err_measured": err_h,
+                              "err_below_delta": bool(err_h < delta)}
+        log(f"protocol delta={delta:.0e} hybrid: tau={tau_hv:.3e} kept {kept_h}, blocks {nnz_hat} -> "
+            f"{live_blocks(Ct)}, err {err_h:.3e}")
     del Cx, Ca, Ct
     torch.cuda.empty_cache()
     return rows
@@ -722,24 +804,23 @@ def batch_leg(args, dev, P, synth, mats):
         # one after another (graph loop each, capacity nb^2): the comparison,
         # and the peak block count of every system (runs are deterministic,
         # so the batched run needs exactly these capacities)
-        peaks, pair_peaks = [], []
+        peaks, pair_peaks, ts = [], [], 0.0
+        seq_logs = []
         for F in Fs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             r1 = P.purify(F, F.n // 2, eps, taus, delta_const=dconst, precision=prec, graph_steps=8)
+            torch.cuda.synchronize()
+            ts += time.perf_counter() - t0
             nf = int(F.live()[0].shape[0])
             peaks.append(max([nf + F.nb] + [int(l["nslot_hat"]) for l in r1.logs]))
             pair_peaks.append(max([1] + [int(l["npairs"]) for l in r1.logs]))
+            seq_logs.append([(l["branch"], l["idx"], l["npairs"]) for l in r1.logs])
             del r1
         torch.cuda.empty_cache()
-        log(f"batch {prec}: peak capacities measured")
+        log(f"batch {prec}: one after another {ts:.3f} s (peak capacities measured)")
         caps = [min(F.nb * F.nb, pk) for F, pk in zip(Fs, peaks)]
         caps_used = caps
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for F, cp in zip(Fs, caps):
-            P.purify(F, F.n // 2, eps, taus, delta_const=dconst, precision=prec, cap=cp, graph_steps=8)
-        torch.cuda.synchronize()
-        ts = time.perf_counter() - t0
-        torch.cuda.empty_cache()
         # the systems go into as few batched calls as fit in free device memory
         # (workspace plus output, which doubles as the second iterate buffer)
         free, _ = torch.cuda.mem_get_info()
@@ -765,13 +846,13 @@ def batch_leg(args, dev, P, synth, mats):
                     out_logs[q], out_status[q] = r.logs[t], r.status[t]
                 del r
             return out_logs, out_status
-        run_chunks()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         logs_b, status_b = run_chunks()
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         ok = sum(1 for st in status_b if st >= 0)
+        same = all([(l["branch"], l["idx"], l["npairs"]) for l in lg] == sl for lg, sl in zip(logs_b, seq_logs))
         flops = sum(sum(l["npairs"] for l in lg if l["branch"] >= 0) * 2.0 * F.b ** 3 for lg, F in zip(logs_b, Fs))
         iters = [sum(1 for l in lg if l["branch"] >= 0) for lg in logs_b]
         torch.cuda.empty_cache()
@@ -780,7 +861,8 @@ def batch_leg(args, dev, P, synth, mats):
         res_all[prec] = {"time_s": round(tb, 4), "kept_TFLOP_per_s": round(flops / tb / 1e12, 4),
                          "batched_calls": len(chunks), "systems_per_call": [len(c) for c in chunks],
                          "sequential_time_s": round(ts, 4), "speedup_vs_sequential": round(ts / tb, 4),
-                         "systems_ok": ok, "iterations_min_max": [min(iters), max(iters)]}
+                         "systems_ok": ok, "iterations_min_max": [min(iters), max(iters)],
+                         "same_decisions_as_single_runs": bool(same)}
     dense = sum(F.nb * F.nb for F in Fs)
     gib = sum(cp * F.b * F.b * 8 for cp, F in zip(caps_used, Fs)) / 2 ** 30 if caps_used else None
     return {"systems": len(Fs), "iterate_capacity_GiB": round(gib, 2) if gib else None, "sum_n": int(sum(F.n for F in Fs)),
@@ -819,15 +901,57 @@ def cpu_baseline(res, Fh, taus, b, seconds):
         pos = min(pos + chunk, order.shape[0])
         chunk = min(chunk * 2, 4096)
     tflops = done_pairs * 2.0 * b ** 3 / done_s / 1e12
+    return {"value": tflops, "unit": "TFLOP/s", "cores": oracle_threads(), "cpu_model": cpu_model(),
+            "kind": "oracle",
+            "sample": f"last purification step of the same workload: exact-norm sweep over all "
+                      f"{K.npairs} kept pairs ({t_sweep:.1f} s) and the leaf products of {pos} of "
+                      f"{K.oi.shape[0]} output blocks ({done_pairs} pairs, {done_s:.1f} s)"}
+
+
+def oracle_threads():
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     try:
         threads = min(threads, len(os.sched_getaffinity(0)))
     except AttributeError:
         pass
-    return {"value": tflops, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"last purification step of the same workload: exact-norm sweep over all "
-                      f"{K.npairs} kept pairs ({t_sweep:.1f} s) and the leaf products of {pos} of "
-                      f"{K.oi.shape[0]} output blocks ({done_pairs} pairs, {done_s:.1f} s)"}
+    return threads
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_chain_baseline(gpu_chain):
+    """The oracle's whole purification of the small chain (n = 1024, leaf 32,
+    the paper's 350 candidates, eps = 1e-6): every phase of every step on
+    the host cores, against the GPU's time for the same run."""
+    import oracle
+    import synth
+    spec = load_spectrum("chain1d_n1024_s1_b32")
+    F = oracle.BSM.of(synth.chain1d(1024, 1, 32))
+    p = oracle.SP2Params(n_occ=512, eps=1e-6, taus=synth.tau_paper(), homo=spec["homo"], lumo=spec["lumo"])
+    t0 = time.perf_counter()
+    _, logs, _ = oracle.sp2(F, p)
+    t = time.perf_counter() - t0
+    st = [lg for lg in logs if lg.branch >= 0]
+    pairs = sum(lg.npairs for lg in st)
+    out = {"value": round(t, 4), "unit": "s to D~ (whole purification)", "cores": oracle_threads(),
+           "cpu_model": cpu_model(), "kind": "oracle", "iterations": len(st), "kept_pairs": int(pairs),
+           "sample": "the whole chain purification (n = 1024, leaf 32, 350 candidates), every phase"}
+    if gpu_chain:
+        out["gpu_host_loop_s"] = gpu_chain["host_loop_ms"] * 1e-3
+        out["gpu_graph_loop_s"] = gpu_chain["graph_loop_ms"] * 1e-3
+        out["same_iterations_as_gpu"] = bool(len(st) == gpu_chain["iterations"])
+        out["same_kept_pairs_as_gpu"] = bool(int(pairs) == gpu_chain["kept_pairs_per_run"])
+    log(f"oracle chain purification: {t:.2f} s, {len(st)} iterations")
+    return out
 
 
 if __name__ == "__main__":

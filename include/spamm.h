@@ -108,6 +108,8 @@ int spamm_build_norms(spamm_bsm* X, spamm_stream_t stream);
  *   bound_out : device [N] bound of ||SpAMM(A,B,tau_k) - AB||_F per candidate.
  *   idx_out   : device [1] selected index (N when none qualifies).
  *   tau_out   : device [1] selected threshold (0 when none qualifies).
+ * With SPAMM_SYNC the call reads idx back and returns SPAMM_WTAUFALLBACK
+ * (results valid) when no candidate qualified.
  * Workspace: spamm_sweep_workspace_bytes(nb, N).
  */
 size_t spamm_sweep_workspace_bytes(int32_t nb, int32_t N);
@@ -223,7 +225,9 @@ typedef struct sp2_params {
 typedef struct sp2_iter_log {
     int32_t i, branch, idx, stop; /* branch 0: x^2, 1: 2x - x^2; stop != 0 on the final record */
     double delta, tau, t1, t2, e;
-    int64_t npairs, nout, nslot_hat, nslot_kept, removed_units;
+    int64_t npairs, nout, nslot_hat, nslot_kept, removed_units; /* kept pairs, output blocks of the product,
+                                                                   blocks of X^_i, blocks of X~_i (X^_i's minus
+                                                                   the truncated ones), truncated units */
     double removed_fro2;
     /* stream-event times in ms: threshold sweep (and FP32 copies), kept pairs
        and output pattern, the leaf-product kernel alone (which also forms
@@ -248,6 +252,9 @@ typedef struct sp2_iter_log {
  *   F     : symmetric input with norms NOT required (computed internally).
  *   D     : output, capacity D->cap slots (SPAMM_ECAPACITY otherwise), with
  *           its block norms (as spamm_build_norms computes them).
+ *   Returns SPAMM_WNOCONV when n_max was reached first, else
+ *   SPAMM_WTAUFALLBACK when some step (Algorithms 5 and 4) found no candidate
+ *   threshold below its budget and used the exact product (results valid).
  *   log   : host [n_max + 2] records; nlog_out: records written.
  * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, tape_steps, precision) with
  * tape_steps = n_max (keep_tape = 1), n_max / keep_tape (keep_tape > 1) or 0.

@@ -345,10 +345,12 @@ def build_norms(X: BlockSparse) -> None:
 
 
 def sweep_tau(A: BlockSparse, B: BlockSparse, taus, budget, b_transposed=False, mode=0, tau0=None, c_low=0.0,
-              sync=False, bound="tree"):
+              sync=False, bound="tree", with_status=False):
     """Error bound of SpAMM(A, B, tau_k) for every candidate (Algorithm 3's
     recursive bound, or the leaf-level "flat" / "sum" bounds) and the
-    selected candidate.  Returns device tensors (bound[N], idx[1], tau[1])."""
+    selected candidate.  Returns device tensors (bound[N], idx[1], tau[1]),
+    and with_status the call's status (with sync: SPAMM_WTAUFALLBACK when
+    no candidate met the budget)."""
     kind_flag = {0: 0, 1: BOUND_FLAT, 2: BOUND_SUM}[BOUNDS[bound]]
     dev = A.device
     taus = torch.as_tensor(taus, dtype=torch.float64, device=dev).contiguous()
@@ -360,11 +362,11 @@ def sweep_tau(A: BlockSparse, B: BlockSparse, taus, budget, b_transposed=False, 
     bdev = budget if isinstance(budget, torch.Tensor) else None
     t0 = torch.as_tensor([tau0 if tau0 is not None else 0.0], dtype=torch.float64, device=dev)
     flags = (B_TRANSPOSED if b_transposed else 0) | (SYNC if sync else 0) | kind_flag
-    _check(lib().spamm_sweep_tau(ctypes.byref(A.struct()), ctypes.byref(B.struct()), _ptr(taus), N,
-                                 _ptr(bdev) if bdev is not None else None,
-                                 float(budget) if bdev is None else 0.0, int(mode), _ptr(t0), float(c_low), flags,
-                                 _ptr(bound), _ptr(idx), _ptr(tau), _ptr(ws), ws.numel(), _stream()))
-    return bound, idx, tau
+    rc = _check(lib().spamm_sweep_tau(ctypes.byref(A.struct()), ctypes.byref(B.struct()), _ptr(taus), N,
+                                      _ptr(bdev) if bdev is not None else None,
+                                      float(budget) if bdev is None else 0.0, int(mode), _ptr(t0), float(c_low),
+                                      flags, _ptr(bound), _ptr(idx), _ptr(tau), _ptr(ws), ws.numel(), _stream()))
+    return (bound, idx, tau, rc) if with_status else (bound, idx, tau)
 
 
 def multiply(A: BlockSparse, B: BlockSparse, tau, symmetric=False, b_transposed=False, cap=None, max_pairs=None,

@@ -580,6 +580,18 @@ void run_adjoint_step(const MatView& X, const MatView& G, double tau, int branch
     launch_gemm_f64(g, num_cus(), s);
 }
 
+// SPAMM_WTAUFALLBACK when some step of a purification found no candidate
+// threshold below its budget and ran the exact product (tau = 0); Algorithm 1
+// (variant 2) always runs it and gets no warning.
+int tau_fallback_status(int status, const sp2_iter_log* log, int nlog, int variant, int N) {
+    if (status != SPAMM_OK || variant == 2) return status;
+    for (int q = 0; q < nlog; ++q)
+        if (log[q].branch >= 0 && log[q].idx >= N)
+            return fail(SPAMM_WTAUFALLBACK, "iteration %d: no candidate threshold met the budget, tau = 0 (exact product)",
+                        log[q].i);
+    return status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -658,7 +670,12 @@ int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, i
         run_sweep(view(A), view(B), (flags & SPAMM_B_TRANSPOSED) ? 1 : 0, tau, N, budget, budget_host, mode, tau0_dev,
                   c_low, bound_out, idx_out, tau_out, w, nullptr, s);
     HIP_TRY(hipGetLastError());
-    if (flags & SPAMM_SYNC) HIP_TRY(hipStreamSynchronize(s));
+    if (flags & SPAMM_SYNC) {
+        HIP_TRY(hipStreamSynchronize(s));
+        int32_t idx = 0;
+        HIP_TRY(hipMemcpy(&idx, idx_out, sizeof(idx), hipMemcpyDeviceToHost));
+        if (idx >= N) return fail(SPAMM_WTAUFALLBACK, "no candidate threshold met the budget: tau = 0");
+    }
     return SPAMM_OK;
 }
 
@@ -1093,7 +1110,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
                           w.trace_out, nullptr, s);
             double tr[4];
-            int64_t msc[4], ts[2];
+            int64_t msc[4], ts[3];
             int32_t ovf[2];
             Sp2Ctl cs;
             launch_host_status(w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, w.ctl, xv.nslot, hs_dev, s);
@@ -1104,7 +1121,6 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             memcpy(ts, ps.h->ts, sizeof(ts));
             memcpy(ovf, ps.h->ovf, sizeof(ovf));
             memcpy(&cs, &ps.h->ctl, sizeof(cs));
-            const int32_t nsl = ps.h->nslot;
             if (ovf[0] || ovf[1]) {
                 status = fail(SPAMM_ECAPACITY, "capacity exceeded in iteration %d (flags %d/%d; pairs %lld of %lld)",
                               it - 1, ovf[0], ovf[1], (long long)msc[0], (long long)max_pairs);
@@ -1119,7 +1135,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                 L.nslot_hat = msc[2];
                 L.removed_units = ts[0];
                 L.removed_fro2 = (double)ts[1] * trunc_quantum(L.delta * tb_scale);
-                L.nslot_kept = nsl;
+                L.nslot_kept = msc[2] - ts[2];  // blocks of X~: those of X^ minus the removed ones
                 L.npairs_low = tiered ? msc[3] : 0;
                 L.sigma = cs.sigma;
                 L.sidx = cs.sidx;
@@ -1187,7 +1203,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
         HIP_TRY(hipStreamSynchronize(s));
     }
     *nlog_out = nlog;
-    return status;
+    return tau_fallback_status(status, log, nlog, p->variant, p->N);
 }
 
 int purify_sp2(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2_iter_log* log, int32_t* nlog_out, void* ws,
@@ -1715,7 +1731,8 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
         if (nl > 0) HIP_TRY(hipMemcpy(log + (size_t)q * log_stride, w.dlog, sizeof(sp2_iter_log) * nl,
                                       hipMemcpyDeviceToHost));
         nlog_out[q] = nl;
-        status_out[q] = cs.status;
+        status_out[q] = tau_fallback_status(cs.status, log + (size_t)q * log_stride, nl, p[q].variant, p[q].N);
+        cs.status = status_out[q];
         if (cs.status < 0) {
             worst = cs.status;
             continue;

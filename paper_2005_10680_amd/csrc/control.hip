@@ -33,7 +33,7 @@ __global__ void k_sp2_control(Sp2Ctl* __restrict__ ctl, const double* __restrict
         L.nslot_hat = msc[2];
         L.removed_units = ts[0];
         L.removed_fro2 = (double)ts[1] * sp2_trunc_quantum(L.delta * ctl->trunc_scale);
-        L.nslot_kept = *nslot_cur;
+        L.nslot_kept = msc[2] - ts[2];  // blocks of X~: those of X^ minus the removed ones
         L.npairs_low = ctl->tiered ? msc[3] : 0;
         L.sigma = ctl->sigma;
         L.sidx = ctl->sidx;
@@ -93,6 +93,7 @@ __global__ void k_host_status(const double* __restrict__ tr, const int64_t* __re
     }
     out->ts[0] = ts[0];
     out->ts[1] = ts[1];
+    out->ts[2] = ts[2];
     out->ovf[0] = *ovf_mul;
     out->ovf[1] = *ovf_sweep;
     out->nslot = *nslot;

@@ -220,7 +220,7 @@ void launch_bound_leaf(int nb, int nw, const uint32_t* bitsA, const uint32_t* bi
 struct Sp2HostStatus {
     double tr[4];      // traces of the current iterate (double-double t1, t2)
     int64_t msc[4];    // kept pairs, outputs, slots of X^, low-tier pairs
-    int64_t ts[2];     // truncation: removed units, removed key sum
+    int64_t ts[3];     // truncation: removed units, removed key sum, removed blocks
     int32_t ovf[2];    // capacity flags of the product and of the sweep
     int32_t nslot;     // slots of the current iterate
     int32_t pad;
@@ -256,6 +256,8 @@ void launch_truncate(const MatView& X, const double* delta_dev, double delta_hos
 
 // x0.hip
 void launch_gersch(const MatView& F, double* rowtmp /* [nb*b*2] */, double* lam /* [2] */, hipStream_t s);
+// rows whose radius the double-double sums left uncertified (lo[g] NaN, hi[g] the centre): exact radius
+void launch_gersch_exact(const MatView& F, double* lo, double* hi, hipStream_t s);
 void launch_x0(const MatView& F, const double* lam, const MatView& X, int32_t* diagflag, int32_t* diagpos,
                void* scan_temp, int64_t* tmp_count, hipStream_t s);
 

@@ -104,6 +104,49 @@ SPAMM_DEV double exact_sumsq_lane(const double* v, int len, uint32_t* L) {
     return limbs_round(L);
 }
 
+// Gerschgorin radii that the double-double row sums could not certify
+// (lo[g] is NaN; hi[g] holds the centre): one thread per such row sums
+// |f_gc| over c != g exactly in a long accumulator and rounds once.
+__global__ __launch_bounds__(64) void k_gersch_exact(MatView F, double* __restrict__ lo, double* __restrict__ hi) {
+    __shared__ uint32_t Ls[64][kLimbs];
+    const int64_t n = F.n;
+    const int b = F.b, nb = F.nb;
+    for (int64_t g0 = (int64_t)blockIdx.x * 64; g0 < n; g0 += (int64_t)gridDim.x * 64) {
+        const int64_t g = g0 + threadIdx.x;
+        if (g >= n || !isnan(lo[g])) continue;
+        uint32_t* L = Ls[threadIdx.x];
+        for (int t = 0; t < kLimbs; ++t) L[t] = 0;
+        bool has_nan = false, has_inf = false;
+        const int I = (int)(g / b), r = (int)(g % b);
+        for (int J = 0; J < nb; ++J) {
+            const int sl = F.map[(size_t)I * nb + J];
+            if (sl < 0) continue;
+            const double* v = F.val + (size_t)sl * b * b;
+            for (int c = 0; c < b; ++c) {
+                const int64_t gj = (int64_t)J * b + c;
+                if (gj >= n) break;
+                if (gj == g) continue;
+                const double x = fabs(v[(size_t)c * b + r]);
+                if (isnan(x)) { has_nan = true; continue; }
+                if (isinf(x)) { has_inf = true; continue; }
+                if (x == 0.0) continue;
+                uint64_t m;
+                int e;
+                split_double(x, m, e);
+                limbs_add128(L, m, 0ull, e + 2148);
+            }
+        }
+        const double R = has_nan ? NAN : (has_inf ? INFINITY : limbs_round(L));
+        const double c0 = hi[g];
+        lo[g] = c0 - R;
+        hi[g] = c0 + R;
+    }
+}
+
+void launch_gersch_exact(const MatView& F, double* lo, double* hi, hipStream_t s) {
+    hipLaunchKernelGGL(k_gersch_exact, dim3(grid_for(F.n, 64, 1024)), dim3(64), 0, s, F, lo, hi);
+}
+
 // Exactly rounded sum of squares of slot s (one wave): double-double
 // accumulation, certified; else (typically an exact tie, as with entries of
 // few significant bits) the same sum again with every addition checked for

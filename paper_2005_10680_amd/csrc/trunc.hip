@@ -178,11 +178,13 @@ __global__ void k_trunc_mark(MatView X, TruncTemp t, int64_t cap, int64_t* __res
         const int s2 = X.map[(size_t)cc * nb + r];
         if (s1 >= 0) X.brow[s1] = -1;
         if (s2 >= 0) X.brow[s2] = -1;
+        const int nrem = (s1 >= 0 ? 1 : 0) + (s2 >= 0 && s2 != s1 ? 1 : 0);
         X.map[(size_t)r * nb + cc] = -1;
         X.map[(size_t)cc * nb + r] = -1;
         if (stats) {
             atomicAdd((unsigned long long*)&stats[0], 1ull);
             atomicAdd((unsigned long long*)&stats[1], (unsigned long long)t.k[c]);
+            atomicAdd((unsigned long long*)&stats[2], (unsigned long long)nrem);
         }
     }
 }
@@ -192,7 +194,7 @@ __global__ void k_trunc_reset(TruncTemp t, int64_t* stats, const int32_t* __rest
     if (threadIdx.x == 0) {
         *t.ncand = 0;
         *t.thr = 0;
-        if (stats) { stats[0] = 0; stats[1] = 0; }
+        if (stats) { stats[0] = 0; stats[1] = 0; stats[2] = 0; }
     }
 }
 

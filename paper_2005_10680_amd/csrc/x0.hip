@@ -9,11 +9,16 @@
 
 namespace spamm {
 
-// per-row disc: centre f_rr, radius RN(sum_{c != r} |f_rc|) (double-double
-// sum).  One workgroup per block row I; thread t takes row r = t % b of the
-// block row and the block columns J = t / b, t / b + P, ... (P = 256 / b),
-// so each wave reads whole block columns (coalesced) and looks the block up
-// once; the P partial sums of a row are combined in a fixed order.
+// per-row disc: centre f_rr, radius RN(sum_{c != r} |f_rc|), the exact sum
+// rounded once.  One workgroup per block row I; thread t takes row r = t % b
+// of the block row and the block columns J = t / b, t / b + P, ...
+// (P = 256 / b), so each wave reads whole block columns (coalesced) and
+// looks the block up once; the P double-double partial sums of a row are
+// combined in a fixed order.  The high part is the rounded exact sum when
+// the double-double value lies farther from a rounding boundary than its
+// error bound (at most 2^18 positive terms: below 2^-87 of the sum); a row
+// that misses the certificate gets lo[g] = NaN and its radius is summed
+// exactly by launch_gersch_exact.
 __global__ __launch_bounds__(256) void k_gersch_rows(MatView F, double* __restrict__ lo, double* __restrict__ hi) {
     __shared__ double shi[256], slo[256], scen[256];
     __shared__ int shas[256];
@@ -25,7 +30,7 @@ __global__ __launch_bounds__(256) void k_gersch_rows(MatView F, double* __restri
         const int64_t g = (int64_t)I * b + r;
         dd rad = {0.0, 0.0};
         double cen = 0.0;
-        bool has_cen = false;
+        bool has_cen = false, special = false, tiny = false;
         for (int J = part; J < nb; J += P) {
             const int s = F.map[(size_t)I * nb + J];
             if (s < 0) continue;
@@ -38,24 +43,34 @@ __global__ __launch_bounds__(256) void k_gersch_rows(MatView F, double* __restri
                     cen = x;
                     has_cen = true;
                 } else {
-                    rad = dd_add(rad, dd{fabs(x), 0.0});
+                    const double ax = fabs(x);
+                    if (!(ax < 0x1p1000)) special = true;           // huge, inf or NaN
+                    else if (ax != 0.0 && ax < 0x1p-900) tiny = true;  // error terms may underflow
+                    rad = dd_add(rad, dd{ax, 0.0});
                 }
             }
         }
         shi[threadIdx.x] = rad.hi;
         slo[threadIdx.x] = rad.lo;
         scen[threadIdx.x] = cen;
-        shas[threadIdx.x] = has_cen ? 1 : 0;
+        shas[threadIdx.x] = (has_cen ? 1 : 0) | (special ? 2 : 0) | (tiny ? 4 : 0);
         __syncthreads();
         if (part == 0 && g < n) {
             dd acc = {shi[r], slo[r]};
-            double c0 = shas[r] ? scen[r] : 0.0;
+            double c0 = (shas[r] & 1) ? scen[r] : 0.0;
+            int fl = shas[r];
             for (int q = 1; q < P; ++q) {
                 acc = dd_add(acc, dd{shi[q * b + r], slo[q * b + r]});
-                if (shas[q * b + r]) c0 = scen[q * b + r];  // the part that met column g
+                if (shas[q * b + r] & 1) c0 = scen[q * b + r];  // the part that met column g
+                fl |= shas[q * b + r];
             }
-            lo[g] = c0 - acc.hi;
-            hi[g] = c0 + acc.hi;
+            if (sq_certified(acc, (fl & 2) != 0, (fl & 4) != 0)) {
+                lo[g] = c0 - acc.hi;
+                hi[g] = c0 + acc.hi;
+            } else {
+                lo[g] = NAN;  // summed exactly by launch_gersch_exact
+                hi[g] = c0;
+            }
         }
         __syncthreads();
     }
@@ -87,6 +102,7 @@ __global__ __launch_bounds__(1024) void k_gersch_final(const double* __restrict_
 
 void launch_gersch(const MatView& F, double* rowtmp, double* lam, hipStream_t s) {
     hipLaunchKernelGGL(k_gersch_rows, dim3(grid_for(F.nb, 1, 4096)), dim3(256), 0, s, F, rowtmp, rowtmp + F.n);
+    launch_gersch_exact(F, rowtmp, rowtmp + F.n, s);
     hipLaunchKernelGGL(k_gersch_final, dim3(1), dim3(1024), 0, s, rowtmp, rowtmp + F.n, F.n, lam);
 }
 

@@ -1,8 +1,10 @@
 """Batched purification (independent systems, one persistent product launch
 per leaf size and tier per step): every system's result and per-iteration
-records are bit-identical to its own single-system run (whose parity with
-the oracle the other GPU tests establish); systems stop at different
-iterations; a failing system leaves the others intact."""
+records are bit-identical to its own single-system run, and every system is
+checked against the oracle -- FP64 systems end to end (the oracle's
+decisions at every step, result within 1e-12), tier systems step by step
+from the GPU's own iterates; systems stop at different iterations; a
+failing system leaves the others intact."""
 import numpy as np
 import pytest
 
@@ -15,6 +17,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
+import oracle_checks as oc  # noqa: E402
 import paper_2005_10680_amd as P  # noqa: E402
 
 FIELDS = ["i", "branch", "idx", "stop", "delta", "tau", "t1", "t2", "e", "npairs", "nout", "nslot_hat",
@@ -68,11 +71,13 @@ def test_batch_matches_single_runs():
     assert res.rc == P.SPAMM_OK and all(st == P.SPAMM_OK for st in res.status)
     iters = []
     for q, (d, F) in enumerate(zip(data, Fs)):
-        single = P.purify(F, d[1], 1e-6, d[2], homo=d[3], lumo=d[4], variant=variants[q], precision=precs[q])
+        single = P.purify(F, d[1], 1e-6, d[2], homo=d[3], lumo=d[4], variant=variants[q], precision=precs[q],
+                          keep_tape=precs[q] != "fp64")
         same_logs(single.logs, res.logs[q])
         same_matrix(single.D, res.D[q])
         exact_norms(res.D[q])
         iters.append(len(res.logs[q]))
+        oracle_check(d, variants[q], precs[q], res.logs[q], res.D[q], single)
     assert len(set(iters)) > 1          # the systems stop at different iterations
     # converged against the dense eigensolver
     for q in (0, 2):
@@ -82,6 +87,17 @@ def test_batch_matches_single_runs():
         brow, bcol, vals, _, _, _ = res.D[q].live()
         Dg = oracle.BSM(Fs[q].n, Fs[q].b, brow, bcol, vals).to_dense()
         assert np.linalg.norm(Dg - Dref) < 1e-6
+
+
+def oracle_check(d, variant, prec, logs, D, single):
+    """System d of a batch against the oracle: FP64 end to end; a tier
+    system step by step on its single run's tape (bit-identical to the
+    batched run)."""
+    p = oc.params(d[1], d[2], d[3], d[4], variant=variant, precision=prec)
+    if prec == "fp64":
+        oc.end_to_end(d[0], p, logs, D)
+    else:
+        oc.teacher_forced(d[0], p, single)
 
 
 def test_batch_isolates_a_failing_system():
@@ -115,6 +131,8 @@ def test_batch_all_product_groups():
                            [d[4] for d in data], precision=precs, graph_steps=4)
     assert res.rc == P.SPAMM_OK
     for q, (d, F) in enumerate(zip(data, Fs)):
-        single = P.purify(F, d[1], 1e-6, d[2], homo=d[3], lumo=d[4], precision=precs[q])
+        single = P.purify(F, d[1], 1e-6, d[2], homo=d[3], lumo=d[4], precision=precs[q],
+                          keep_tape=precs[q] != "fp64")
         same_logs(single.logs, res.logs[q])
         same_matrix(single.D, res.D[q])
+        oracle_check(d, "hybrid", precs[q], res.logs[q], res.D[q], single)

@@ -122,3 +122,54 @@ def test_degenerate_occupation(occ):
     assert np.abs(Dg - Do.to_dense()).max() < 1e-12
     want = np.zeros((n, n)) if occ == "none" else np.eye(n)
     assert np.linalg.norm(Dg - want) < 1e-6
+
+
+def test_tau_fallback_warning():
+    """No candidate below the budget: the synchronising sweep and the
+    purification return the SPAMM_WTAUFALLBACK warning with tau = 0 (the
+    exact product), and the purification's steps equal the oracle's."""
+    X = sym_x(1024, 32, 1)
+    G = P.BlockSparse.from_host(X)
+    P.build_norms(G)
+    tl = synth.tau_log(8, -4.0)                       # 1 ... 1e-4
+    bound, idx, tau, rc = P.sweep_tau(G, G, tl, 1e-30, b_transposed=True, sync=True, with_status=True)
+    assert rc == P.SPAMM_WTAUFALLBACK and int(idx.item()) == len(tl) and float(tau.item()) == 0.0
+    bound, idx, tau, rc = P.sweep_tau(G, G, tl, 1e30, b_transposed=True, sync=True, with_status=True)
+    assert rc == P.SPAMM_OK and int(idx.item()) == 0
+    Fm = synth.chain1d(512, 1, 32)
+    F = oracle.BSM.of(Fm)
+    p = oracle.SP2Params(n_occ=256, eps=1e-6, taus=tl, delta_const=1e-14)
+    Do, logs_o, _ = oracle.sp2(F, p)
+    assert any(l.branch >= 0 and l.idx == len(tl) for l in logs_o)
+    res = P.purify(P.BlockSparse.from_host(Fm), 256, 1e-6, tl, delta_const=1e-14)
+    assert res.status == P.SPAMM_WTAUFALLBACK
+    assert [(l["branch"], l["idx"], l["npairs"]) for l in res.logs if l["branch"] >= 0] == \
+        [(l.branch, l.idx, l.npairs) for l in logs_o if l.branch >= 0]
+    assert np.abs(to_oracle(res.D).to_dense() - Do.to_dense()).max() < 1e-12
+    # Algorithm 1 always runs the exact product: no warning
+    res = P.purify(P.BlockSparse.from_host(Fm), 256, 1e-6, tl, delta_const=1e-14, variant="truncmul")
+    assert res.status == P.SPAMM_OK
+
+
+def test_x0_gerschgorin_radius_exactly_rounded():
+    """A Gerschgorin row whose |f| sum 1 + 2^-53 + 2^-110 lies just above a
+    rounding tie: double-double accumulation keeps 1 + 2^-53 and would round
+    to 1, the exact sum rounds to 1 + 2^-52.  That row sets lambda_max, so
+    X_0 is bit-identical to the oracle's only with the exactly rounded
+    radius."""
+    n, b = 64, 32
+    Fd = np.diag(np.where(np.arange(n) % 2 == 0, 0.1, -0.1))
+    Fd[5, 5] = 0.5
+    for j, v in ((10, 1.0), (40, 2.0 ** -53), (50, 2.0 ** -110)):
+        Fd[5, j] = Fd[j, 5] = v
+    Fm = synth.BlockMatrix.from_dense(Fd, b)
+    F = oracle.BSM.of(Fm)
+    lmin, lmax = oracle.gerschgorin(F)
+    assert lmax == 1.5 + 2.0 ** -52
+    p = oracle.SP2Params(n_occ=n // 2, eps=1e-6, taus=synth.tau_log(16), delta_const=1e-300)
+    X0o, _, _, _ = oracle.sp2_start(F, p)
+    res = P.purify(P.BlockSparse.from_host(Fm), n // 2, 1e-6, synth.tau_log(16), delta_const=1e-300,
+                   keep_tape=True, n_max=4)
+    X0g = to_oracle(res.tape(0))
+    assert np.array_equal(X0g.keys(), X0o.keys())
+    assert np.array_equal(X0g.vals.view(np.uint64), X0o.sorted().vals.view(np.uint64))

@@ -134,7 +134,7 @@ def test_sys3d_16384_fp64_full_run():
     X0o, _, st, _ = oracle.sp2_start(F, p)
     X0g, _ = to_oracle(res.tape(0))
     assert np.array_equal(X0g.keys(), X0o.keys())
-    assert np.abs(X0g.to_dense() - X0o.to_dense()).max() < 1e-14
+    assert np.array_equal(X0g.vals.view(np.uint64), X0o.sorted().vals.view(np.uint64))   # bit for bit
     steps = [lg for lg in res.logs if lg["branch"] >= 0]
     assert len(steps) >= 30
     picks = set(range(0, len(steps), 5)) | {1, 2, len(steps) - 2, len(steps) - 1}
@@ -211,7 +211,7 @@ def test_sys3d_65536_first_step(sys3d_65536, precision):
         X, nu_g = to_oracle(res.tape(t))
         if t == 0:
             assert np.array_equal(X.keys(), X0s.keys())
-            assert np.abs(X.vals - X0s.vals).max() < 1e-14
+            assert np.array_equal(X.vals.view(np.uint64), X0s.vals.view(np.uint64))   # bit for bit
         check_step(X, nu_g, lg, xh, xl, p, res.tape(t + 1), rng)
         if prec:
             assert lg["npairs_low"] > 0

@@ -1,8 +1,12 @@
 """The graph-captured purification loop (decisions on the device, the step
-replayed as one HIP graph) against the host-driven loop: same kernels, same
-decisions, so the results and every per-iteration record must be identical
-bit for bit.  The graph is replayed many times within one run and the run
-is repeated with eager host-loop work in between."""
+replayed as one HIP graph) against the oracle and against the host-driven
+loop: an FP64 graph run takes the oracle's decisions at every step and
+ends within 1e-12 of its result (each of Algorithms 5, 4 and 1); with the
+FP32 tier each step is checked against the oracle from the GPU's own
+iterate.  Same kernels and decisions as the host loop, so results and every
+per-iteration record are identical bit for bit.  The graph is replayed many
+times within one run and the run is repeated with eager host-loop work in
+between."""
 import numpy as np
 import pytest
 
@@ -15,6 +19,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
+import oracle_checks as oc  # noqa: E402
 import paper_2005_10680_amd as P  # noqa: E402
 
 FIELDS = ["i", "branch", "idx", "stop", "delta", "tau", "t1", "t2", "e", "npairs", "nout", "nslot_hat",
@@ -61,6 +66,14 @@ def test_graph_loop_matches_host_loop(case, variant, precision):
         gk = P.purify(F, n_occ, 1e-6, taus, graph_steps=k, **kw)
         same(host, gk)
     assert sum(1 for lg in host.logs if lg["branch"] >= 0) >= 8
+    # against the oracle
+    p = oc.params(n_occ, taus, homo, lumo, variant=variant, precision=precision)
+    if precision == "fp64":
+        oc.end_to_end(Fm, p, g1.logs, g1.D)
+    else:
+        taped = P.purify(F, n_occ, 1e-6, taus, keep_tape=True, **kw)
+        same(taped, g1)
+        assert oc.teacher_forced(Fm, p, taped) > 0
 
 
 def test_graph_loop_n_max_warning():

@@ -283,7 +283,7 @@ def test_purify_teacher_forced_steps():
     X0o, _, st, _ = oracle.sp2_start(F, p)
     X0g = to_oracle(res.tape(0))
     assert np.array_equal(X0g.keys(), X0o.keys())
-    assert np.abs(X0g.to_dense() - X0o.to_dense()).max() < 1e-14
+    assert np.array_equal(X0g.vals.view(np.uint64), X0o.sorted().vals.view(np.uint64))   # bit for bit
     steps = [lg for lg in logs if lg["branch"] >= 0]
     assert len(steps) >= 8
     xh, xl = st.xh, st.xl
@@ -299,6 +299,7 @@ def test_purify_teacher_forced_steps():
         T = res.tape(t + 1)
         Xg = to_oracle(T)
         assert np.array_equal(Xg.keys(), Xn.keys())
+        assert lg["nslot_kept"] == Xn.nblk and lg["nslot_hat"] == Xh.nblk      # block counts of X~_i, X^_i
         assert rel_fro(Xg.vals, Xn.vals) <= 1e-12
         # the iterate's norms (from the product epilogue) are the exactly
         # rounded norms of its own values
