@@ -111,8 +111,10 @@ def main():
     max_pairs = nb * nb * (nb + 1) // 2
     eps = 1e-6
 
-    def run_once(precision="fp64", graph_steps=0, keep_tape=False, cap_=None, bound="tree", variant="hybrid"):
-        return P.purify(F, n_occ, eps, taus, homo=spec["homo"], lumo=spec["lumo"], cap=cap_ or cap,
+    def run_once(precision="fp64", graph_steps=0, keep_tape=False, cap_=None, bound="tree", variant="hybrid",
+                 taus_=None):
+        return P.purify(F, n_occ, eps, taus if taus_ is None else taus_, homo=spec["homo"], lumo=spec["lumo"],
+                        cap=cap_ or cap,
                         max_pairs=max_pairs, precision=precision, graph_steps=graph_steps, keep_tape=keep_tape,
                         bound=bound, variant=variant)
 
@@ -276,6 +278,11 @@ def main():
                                              for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc")},
                         "verify_fro_err": verify_err(rm)}
             del rm
+
+    # candidate lists: length and first candidate (the paper's closing
+    # discussion names the threshold vector as a tuning knob)
+    if not args.no_variants:
+        out["candidate_lists"] = candidate_list_leg(run_once, torch, args.steps, b, synth)
 
     # the paper's three purification variants on the same workload:
     # Algorithm 5 (hybrid), 4 (SpAMM only) and 1 (exact product + truncation)
@@ -448,6 +455,33 @@ def adjoint_leg(dev, P, synth, torch):
             "checkpoint_every": every, "delta_const": dconst, "loss": L0,
             "forward_with_checkpoints_s": round(t_fwd, 4), "adjoint_s": round(t_adj, 4),
             "directional_derivative": got, "central_differences": fd}
+
+
+def candidate_list_leg(run_once, torch, reps, b, synth):
+    """The main workload with other candidate lists: N log-spaced thresholds
+    from 1 down to 1e-16 (N = 16, 32, 64, 128), and 40 from 1e4 (a first
+    candidate above every block-pair product), in FP64 and, for N = 32 and
+    64, the split-BF16 tier; time to D~ (median of reps), kept pairs, the
+    sweep's share.  The selection rule and the error guarantee are the same
+    for every list; a denser list lets tau (and sigma) sit closer to the
+    budget at a higher sweep cost."""
+    lists = [(f"log{N}", synth.tau_log(N)) for N in (16, 32, 64, 128)]
+    lists.append(("log40_from_1e4", np.logspace(4.0, -16.0, 40)))
+    rows = []
+    for name, taus_ in lists:
+        for prec in ("fp64", "bf16x3"):
+            if prec != "fp64" and name not in ("log32", "log64"):
+                continue
+            t, r = timed(lambda: run_once(prec, taus_=taus_), torch, reps)
+            st = [lg for lg in r.logs if lg["branch"] >= 0]
+            rows.append({"list": name, "N": int(len(taus_)), "precision": prec, "sp2_time_s": round(t, 4),
+                         "iterations": len(st), "kept_pairs_per_run": int(sum(lg["npairs"] for lg in st)),
+                         "low_tier_pairs_per_run": int(sum(lg["npairs_low"] for lg in st)),
+                         "sweep_ms_per_run": round(sum(lg["ms_sweep"] for lg in st), 3)})
+            log(f"candidates {name} ({prec}): {t:.3f} s, {rows[-1]['kept_pairs_per_run']} kept pairs, "
+                f"sweep {rows[-1]['sweep_ms_per_run']:.1f} ms")
+            del r
+    return rows
 
 
 def variants_leg(run_once, torch, reps, b, eps, verify_err):

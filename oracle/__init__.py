@@ -193,8 +193,10 @@ def cse_flat_sum(A: BSM, B: BSM, taus, nuA=None, nuB=None, mode=0, tau0=0.0, c_l
     (sum over k of the leaf values)^2)^(1/2) (eq. (6) applied to each output's
     leaf blocks) and B_sum = the sum of all leaf values.  Leaf values as in
     Algorithm 3: p when p < tau_k (mode 0); in mode 1 (precision tiers) p when
-    p < tau0, c_low p when tau0 <= p < tau_k, else 0.  Plain FP64 sums in
-    the order outputs (i, j) row-major, k ascending."""
+    p < tau0, c_low p when tau0 <= p < tau_k, else 0.  Per output the leaf
+    values are summed in ascending k (one rounding per addition), s_ij; the
+    sums over outputs are exact, rounded once: B_sum = RN(sum s_ij),
+    B_flat = sqrt_RN(RN(sum RN(s_ij^2))), independent of the output order."""
     taus = np.ascontiguousarray(taus, dtype=np.float64)
     nuA = norms(A)[1] if nuA is None else np.ascontiguousarray(nuA)
     nuB = norms(B)[1] if nuB is None else np.ascontiguousarray(nuB)

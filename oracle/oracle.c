@@ -270,10 +270,17 @@ int o_cse_tree_leafvals(int nb, const int32_t* mapA, const int32_t* mapB, const 
 /* The two comparison bounds (used for invariants only):
  *   flat[k] = sqrt( sum_ij ( sum_{kk: p < tau_k} p )^2 )   (eq. (6) at leaf level)
  *   sum[k]  = sum over skipped pairs of p.                                      */
+/* Leaf-level bounds for every candidate.  Per output (i, j) the leaf       */
+/* values are summed in ascending k, one rounding per addition: s_ij.       */
+/* B_sum  = RN(exact sum over outputs of s_ij),                             */
+/* B_flat = sqrt_RN(RN(exact sum over outputs of RN(s_ij^2))):              */
+/* exactly rounded outer sums, so the result does not depend on the order   */
+/* in which the outputs are visited.                                        */
 void o_cse_flat_sum(int nb, const int32_t* mapA, const double* nuA, const int32_t* mapB, const double* nuB,
                     const double* tau, int N, int mode, double tau0, double c_low, double* flat, double* sum) {
     double* colsum = (double*)malloc(sizeof(double) * N);
-    for (int k = 0; k < N; ++k) { flat[k] = 0.0; sum[k] = 0.0; }
+    big_t* accf = (big_t*)calloc((size_t)N, sizeof(big_t));
+    big_t* accs = (big_t*)calloc((size_t)N, sizeof(big_t));
     for (int i = 0; i < nb; ++i)
         for (int j = 0; j < nb; ++j) {
             for (int k = 0; k < N; ++k) colsum[k] = 0.0;
@@ -288,14 +295,22 @@ void o_cse_flat_sum(int nb, const int32_t* mapA, const double* nuA, const int32_
                     double v;
                     if (mode == 0) v = p < tau[k] ? p : 0.0;
                     else v = p < tau0 ? p : (p < tau[k] ? c_low * p : 0.0);
-                    if (v != 0.0) { colsum[k] += v; sum[k] += v; any = 1; }
+                    if (v != 0.0) { colsum[k] += v; any = 1; }
                 }
             }
             if (any)
-                for (int k = 0; k < N; ++k) flat[k] += colsum[k] * colsum[k];
+                for (int k = 0; k < N; ++k) {
+                    big_add_double(&accs[k], colsum[k]);
+                    big_add_double(&accf[k], colsum[k] * colsum[k]);
+                }
         }
-    for (int k = 0; k < N; ++k) flat[k] = sqrt(flat[k]);
+    for (int k = 0; k < N; ++k) {
+        sum[k] = big_round(&accs[k]);
+        flat[k] = sqrt(big_round(&accf[k]));
+    }
     free(colsum);
+    free(accf);
+    free(accs);
 }
 
 /* ------------------------------------------------------------------------ */

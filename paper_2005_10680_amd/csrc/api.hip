@@ -118,7 +118,7 @@ struct SweepWs {
     // leaf-level bounds (B_flat, B_sum)
     int nw;
     uint32_t *bitsA, *bitsB;
-    double* part;   // per-wave partial sums [waves][N]
+    void* part;     // the leaf-level bounds' partial sums and exact accumulators
     double* bleaf;  // [N]
     int64_t* one;
 };
@@ -146,7 +146,7 @@ void carve_sweep(Carver& c, int nb, int N, SweepWs& w) {
     w.nw = (nb + 31) / 32;
     w.bitsA = c.take<uint32_t>((size_t)nb * w.nw);
     w.bitsB = c.take<uint32_t>((size_t)nb * w.nw);
-    w.part = c.take<double>((size_t)bound_part_waves(nb) * N);
+    w.part = c.take<char>(bound_leaf_scratch_bytes(nb, N));
     w.bleaf = c.take<double>(N);
     w.one = c.take<int64_t>(1);
 }

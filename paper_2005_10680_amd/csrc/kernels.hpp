@@ -205,13 +205,14 @@ void launch_adj_fbar(const MatView& F, const int32_t* map0, const double* g0, co
 
 // bounds.hip: leaf-level bounds B_flat (flat = 1) / B_sum (flat = 0) for the N
 // candidates into out [N] (mode 1: tier mode, tau0 the fixed skip threshold,
-// c_low the low tier's per-pair factor); part holds bound_part_waves(nb) * N
-// doubles
+// c_low the low tier's per-pair factor), exactly rounded sums over the
+// outputs; scratch holds bound_leaf_scratch_bytes(nb, N) bytes
 constexpr int kBoundMaxNb = 2048;
 int64_t bound_part_waves(int nb);
+size_t bound_leaf_scratch_bytes(int nb, int N);
 void launch_bound_leaf(int nb, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
                        const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
-                       int N, int flat, int mode, const double* tau0, double c_low, double* part, double* out,
+                       int N, int flat, int mode, const double* tau0, double c_low, void* scratch, double* out,
                        const int32_t* done, hipStream_t s);
 
 // control.hip

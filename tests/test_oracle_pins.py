@@ -382,3 +382,80 @@ def test_stop_rule_fires_at_a_perturbation_floor():
     first = next(i for i, e in enumerate(es) if abs(e) <= 1e-5)
     assert fired - 1 <= first + 3, (first, fired, es[first - 2:fired])
     assert all(abs(e) > 1e-5 for e in es[:first])
+
+
+# ---------------------------------------------------------------------------
+# leaf-level bounds: exactly rounded sums over the outputs
+# ---------------------------------------------------------------------------
+
+def _diag_single(nb, b, values):
+    """Block-diagonal matrix whose block (i, i) holds values[i] at its first
+    entry: nu(block i) = |values[i]| exactly."""
+    vals = np.zeros((nb, b, b))
+    vals[:, 0, 0] = values
+    idx = np.arange(nb, dtype=np.int32)
+    return oracle.BSM(nb * b, b, idx, idx.copy(), vals)
+
+
+def test_leaf_bounds_round_the_output_sum_once():
+    """Outputs whose skipped products are 1, 2^-53, 2^-53: the exact sum
+    1 + 2^-52 rounds to itself, while adding the outputs one after another
+    in double would stop at 1 (each addition a tie to even).  Likewise for
+    B_flat with one term 1 and 32 terms 2^-56: the exact sum 1 + 2^-51 gives
+    sqrt_RN = 1 + 2^-52, the running sum stays at 1."""
+    b = 32
+    A = _diag_single(3, b, [1.0, 2.0 ** -26, 2.0 ** -26])
+    B = _diag_single(3, b, [1.0, 2.0 ** -27, 2.0 ** -27])
+    flat, ssum = oracle.cse_flat_sum(A, B, np.array([4.0]))
+    assert ssum[0] == 1.0 + 2.0 ** -52
+    seq = 0.0
+    for v in (1.0, 2.0 ** -53, 2.0 ** -53):
+        seq += v
+    assert seq == 1.0                       # the order-dependent running sum differs
+    A = _diag_single(33, b, [1.0] + [2.0 ** -14] * 32)
+    B = _diag_single(33, b, [1.0] + [2.0 ** -14] * 32)
+    flat, ssum = oracle.cse_flat_sum(A, B, np.array([4.0]))
+    exact = Fraction(1) + 32 * Fraction(2) ** -56
+    assert Fraction(float(exact)) == exact
+    assert flat[0] == math.sqrt(float(exact)) == 1.0 + 2.0 ** -52
+    # a sum that is exactly a tie rounds to even
+    A = _diag_single(2, b, [1.0, 2.0 ** -26])
+    B = _diag_single(2, b, [1.0, 2.0 ** -27])
+    flat, ssum = oracle.cse_flat_sum(A, B, np.array([4.0]))
+    assert ssum[0] == 1.0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_leaf_bounds_equal_exact_rational_sums(seed):
+    """On random block-sparse inputs the bounds equal sums evaluated with
+    exact rationals from the per-output k-ascending double sums."""
+    rng = np.random.default_rng(900 + seed)
+    nb, b = 5, 32
+    def rnd():
+        keep = rng.random((nb, nb)) < 0.6
+        rr, cc = np.nonzero(keep)
+        vals = np.zeros((rr.shape[0], b, b))
+        vals[:, 0, 0] = np.exp(rng.uniform(-20, 2, rr.shape[0]))
+        vals[:, 1, 3] = np.exp(rng.uniform(-30, 0, rr.shape[0]))
+        return oracle.BSM(nb * b, b, rr.astype(np.int32), cc.astype(np.int32), vals)
+    A, B = rnd(), rnd()
+    nuA, nuB = oracle.norms(A)[1], oracle.norms(B)[1]
+    mA, mB = A.block_map(), B.block_map()
+    taus = synth.tau_log(12, -12.0)
+    flat, ssum = oracle.cse_flat_sum(A, B, taus, nuA, nuB)
+    for m, t in enumerate(taus):
+        S, F2 = Fraction(0), Fraction(0)
+        for i in range(nb):
+            for j in range(nb):
+                s = 0.0
+                for k in range(nb):
+                    sa, sb = mA[i * nb + k], mB[k * nb + j]
+                    if sa < 0 or sb < 0:
+                        continue
+                    p = nuA[sa] * nuB[sb]
+                    if p < t:
+                        s += p
+                S += Fraction(s)
+                F2 += Fraction(s * s)
+        assert ssum[m] == float(S)
+        assert flat[m] == math.sqrt(float(F2))
