@@ -151,18 +151,44 @@ void carve_sweep(Carver& c, int nb, int N, SweepWs& w) {
     w.one = c.take<int64_t>(1);
 }
 
+// Occupancy of a matrix X with a symmetric block pattern, for the products
+// X X^T of the purification (A = X, B given transposed as X): the row
+// bitmaps (nw words per block row) and the level-l0 tiles of X serve as both
+// operands' (the tiles of X^T are the transposed tiles of X, equal for a
+// symmetric pattern), so one pass builds what the sweep and the kept pairs
+// would otherwise build four times.
+struct SymOcc {
+    const uint32_t* bits;
+    const uint8_t* tiles;
+};
+
+SymOcc build_sym_occ(const MatView& X, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0, const int32_t* done,
+                     hipStream_t s) {
+    fill_u32(bits, (int64_t)X.nb * nw, 0u, s);
+    fill_u8(tiles, (int64_t)T * T, 0, s);
+    launch_occupancy(X, kOccA, bits, nw, tiles, T, l0, done, s);
+    return SymOcc{bits, tiles};
+}
+
 // The leaf-level bounds B_flat (kind 1) or B_sum (kind 2) for every
 // candidate (mode 1: the tier mode, as in run_sweep), then the selection rule.
+// occ: precomputed occupancy of A = B (symmetric pattern), or null.
 void run_sweep_leaf(const MatView& A, const MatView& B, int btrans, const double* tau, int N,
                     const double* budget_dev, double budget_host, int kind, int mode, const double* tau0_dev,
                     double c_low, double* bound_out, int32_t* idx_out, double* tau_out, SweepWs& w,
-                    const int32_t* done, hipStream_t s) {
+                    const int32_t* done, hipStream_t s, const SymOcc* occ = nullptr) {
     const int nb = A.nb;
-    fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
-    fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
-    launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
-    launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
-    launch_bound_leaf(nb, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, tau, N, kind == 1 ? 1 : 0,
+    const uint32_t* bA = w.bitsA;
+    const uint32_t* bB = w.bitsB;
+    if (occ) {
+        bA = bB = occ->bits;
+    } else {
+        fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
+        fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
+        launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
+        launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
+    }
+    launch_bound_leaf(nb, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, tau, N, kind == 1 ? 1 : 0,
                       mode, tau0_dev, c_low, w.part, w.bleaf, done, s);
     fill_i64(w.one, 1, 1, s);
     launch_select(w.bleaf, w.one, tau, N, budget_dev, budget_host, bound_out, idx_out, tau_out, done, s);
@@ -170,13 +196,17 @@ void run_sweep_leaf(const MatView& A, const MatView& B, int btrans, const double
 
 void run_sweep(const MatView& A, const MatView& B, int btrans, const double* tau, int N, const double* budget_dev,
                double budget_host, int mode, const double* tau0, double c_low, double* bound_out, int32_t* idx_out,
-               double* tau_out, SweepWs& w, const int32_t* done, hipStream_t s) {
+               double* tau_out, SweepWs& w, const int32_t* done, hipStream_t s, const SymOcc* occ = nullptr) {
     const int T = w.T;
-    fill_u8(w.tA, (int64_t)T * T, 0, s);
-    fill_u8(w.tB, (int64_t)T * T, 0, s);
-    launch_occupancy(A, kOccA, nullptr, 0, w.tA, T, w.l0, done, s);
-    launch_occupancy(B, btrans ? kOccBt : kOccB, nullptr, 0, w.tB, T, w.l0, done, s);
-    launch_cube_flags(T, w.tA, w.tB, w.flag, done, s);
+    if (occ) {
+        launch_cube_flags(T, occ->tiles, occ->tiles, w.flag, done, s);
+    } else {
+        fill_u8(w.tA, (int64_t)T * T, 0, s);
+        fill_u8(w.tB, (int64_t)T * T, 0, s);
+        launch_occupancy(A, kOccA, nullptr, 0, w.tA, T, w.l0, done, s);
+        launch_occupancy(B, btrans ? kOccBt : kOccB, nullptr, 0, w.tB, T, w.l0, done, s);
+        launch_cube_flags(T, w.tA, w.tB, w.flag, done, s);
+    }
     scan_i32(w.flag, w.idx, w.ncap, nullptr, &w.cnt[0], w.scan_tmp, s);
     launch_cube_list(T, w.flag, w.idx, w.keys[0], &w.cnt[0], w.ncap, w.ovf, done, s);
     launch_cube_eval(mode, w.l0, A.nb, w.keys[0], &w.cnt[0], w.ncap, A.map, A.norm, B.map, B.norm, btrans, tau, N,
@@ -245,19 +275,25 @@ void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
 // (map, brow, bcol, nslot); with X given, the pattern of 2X - C (branch 1).
 void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const double* tau_dev, const double* sigma_dev,
                const MatView& C, uint8_t* fromc, MulWs& w, const int32_t* mapX, const int32_t* branch_dev,
-               const int32_t* done, hipStream_t s) {
+               const int32_t* done, hipStream_t s, const SymOcc* occ = nullptr) {
     const int nb = A.nb;
-    fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
-    fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
-    launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
-    launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
-    launch_kept_count(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, sigma_dev,
+    const uint32_t* bA = w.bitsA;
+    const uint32_t* bB = w.bitsB;
+    if (occ) {
+        bA = bB = occ->bits;
+    } else {
+        fill_u32(w.bitsA, (int64_t)nb * w.nw, 0u, s);
+        fill_u32(w.bitsB, (int64_t)nb * w.nw, 0u, s);
+        launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
+        launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
+    }
+    launch_kept_count(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, sigma_dev,
                       w.cnt, w.cflag, sigma_dev ? w.cnt_low : nullptr, done, s);
     scan_i32(w.cnt, w.off, w.PP, nullptr, &w.sc[0], w.scan_tmp, s);
     scan_i32(w.cflag, w.oidx, w.PP, nullptr, &w.sc[1], w.scan_tmp, s);
     if (sigma_dev) scan_i32(w.cnt_low, w.hslot, w.PP, nullptr, &w.sc[3], w.scan_tmp, s);  // total low pairs
     else fill_i64(&w.sc[3], 1, 0, s);
-    launch_kept_fill(nb, w.P, w.nw, w.bitsA, w.bitsB, A.map, A.norm, B.map, B.norm, btrans, tau_dev, sigma_dev, w.cnt,
+    launch_kept_fill(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, tau_dev, sigma_dev, w.cnt,
                      w.off, w.oidx, &w.sc[0], &w.sc[1], w.cap_pairs, w.cap_out, w.oi, w.oj, w.optr, w.pairs,
                      sigma_dev ? w.olow : nullptr, w.ovf, done, s);
     launch_hat_flags(nb, w.P, w.cnt, sym, mapX, branch_dev, w.hflag, done, s);
@@ -961,22 +997,24 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     auto enqueue_step = [&](const MatView& xv, const MatView& nv, int par, const int32_t* done, hipEvent_t* evs,
                             hipStream_t st) -> int {
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
+        // the iterate's occupancy, shared by the sweeps and the kept pairs
+        const SymOcc occ = build_sym_occ(xv, w.mw.bitsA, w.mw.nw, w.sw.tA, w.sw.T, w.sw.l0, done, st);
         if (p->variant != 2 && p->bound_kind != 0)
             run_sweep_leaf(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, p->bound_kind, 0, nullptr, 0.0,
                            w.bound, &w.ctl->idx,
-                           &w.ctl->tau, w.sw, done, st);
+                           &w.ctl->tau, w.sw, done, st, &occ);
         else if (p->variant != 2)
             run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
-                      &w.ctl->tau, w.sw, done, st);
+                      &w.ctl->tau, w.sw, done, st, &occ);
         if (tiered) {
             // largest low-precision limit whose bound (skipped p plus c_low p for the low
             // tier) stays below the whole product budget
             if (p->bound_kind != 0)
                 run_sweep_leaf(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, p->bound_kind, 1, &w.ctl->tau, c_low,
-                               w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st);
+                               w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st, &occ);
             else
                 run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2,
-                          &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st);
+                          &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st, &occ);
             if (p->precision == 2)
                 launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp,
                                  done, st);
@@ -993,7 +1031,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
         step_norms.recheck = w.recheck;
         step_norms.nrecheck = &w.mw.counters[8];
         run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
-                  &w.ctl->branch, done, st);
+                  &w.ctl->branch, done, st, &occ);
         // evs[2]/evs[3] bracket the product kernel alone
         const uint16_t* x16 = p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr;
         const float* x32 = p->precision == 1 ? (f32_fused ? f32buf[par] : w.x32) : nullptr;
@@ -1648,22 +1686,23 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             const int32_t* done = &w.ctl->done;
             MatView xv = view(&w.X[par]);
             MatView nv = view(&w.X[1 - par]);
+            const SymOcc occ = build_sym_occ(xv, w.mw.bitsA, w.mw.nw, w.sw.tA, w.sw.T, w.sw.l0, done, gg.cs);
             if (pq->variant != 2 && pq->bound_kind != 0)
                 run_sweep_leaf(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, pq->bound_kind, 0, nullptr, 0.0,
                                w.bound,
-                               &w.ctl->idx, &w.ctl->tau, w.sw, done, gg.cs);
+                               &w.ctl->idx, &w.ctl->tau, w.sw, done, gg.cs, &occ);
             else if (pq->variant != 2)
                 run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, 0, nullptr, 0.0, w.bound, &w.ctl->idx,
-                          &w.ctl->tau, w.sw, done, gg.cs);
+                          &w.ctl->tau, w.sw, done, gg.cs, &occ);
             if (tiered) {
                 if (pq->bound_kind != 0)
                     run_sweep_leaf(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget, 0.0, pq->bound_kind, 1, &w.ctl->tau,
                                    tier_constant(pq->precision, F[q].b), w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw,
-                                   done, gg.cs);
+                                   done, gg.cs, &occ);
                 else
                     run_sweep(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau,
                               tier_constant(pq->precision, F[q].b), w.bound2, &w.ctl->sidx, &w.ctl->sigma, w.sw, done,
-                              gg.cs);
+                              gg.cs, &occ);
                 if (pq->precision == 2)
                     launch_to_bf16x2(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32),
                                      w.xexp, done, gg.cs);
@@ -1671,7 +1710,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                     launch_to_f32(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, gg.cs);
             }
             run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
-                      &w.ctl->branch, done, gg.cs);
+                      &w.ctl->branch, done, gg.cs, &occ);
             fill_i32(&w.mw.counters[8], 1, 0, gg.cs);  // recheck count of the epilogue norms
         }
         // one persistent product launch per group over all its systems

@@ -25,9 +25,11 @@
 // list (Morton order) is cut into 8 contiguous ranges of equal kept-pair
 // count, and the workgroups of XCD x take outputs of range x from an atomic
 // counter, so neighbouring outputs -- which share A rows and B columns --
-// run under the same L2; a workgroup whose range is drained goes on with the
-// other ranges' counters, so the XCDs finish together.  Every output is computed by exactly one workgroup
-// in a fixed order: results are bitwise reproducible.
+// run under the same L2.  In the ring kernels (k_gemm_ring, k_gemm_ring_batch)
+// a workgroup whose range is drained goes on with the other ranges' counters,
+// so the XCDs finish together; the register-staged k_gemm (B not given
+// transposed) stops at the end of its own range.  Every output is computed by
+// exactly one workgroup in a fixed order: results are bitwise reproducible.
 #include <type_traits>
 
 #include "common.hpp"
@@ -950,13 +952,19 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
     // read with scalar loads that never wait behind the copies in flight):
     // from this XCD's range while it lasts, then from the other ranges in
     // turn, so that no XCD idles while another still has outputs; -1 once
-    // every range is drained (at most 8 failed claims per workgroup)
+    // every range is drained (at most 8 failed claims per workgroup, and none on
+    // a range whose counter already shows it drained)
     int r = 0;
     auto fetch = [&]() -> int {
         if (tid == 0) {
             int on = -1;
             for (; r < 8; ++r) {
                 const int x = (xcd + r) & 7;
+                // a drained range is seen with a plain load, so the atomics
+                // (serialised per counter) go to ranges that still have work
+                if (__hip_atomic_load(&g.counters[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                    s_cut[x + 1] - s_cut[x])
+                    continue;
                 const int c = s_cut[x] + atomicAdd(&g.counters[x], 1);
                 if (c < s_cut[x + 1]) {
                     on = c;
@@ -1031,6 +1039,9 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
             int on = -1;
             for (; r < 8; ++r) {
                 const int x = (xcd + r) & 7;
+                if (__hip_atomic_load(&counters[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                    s_cut[x + 1] - s_cut[x])
+                    continue;  // drained (a plain load; see k_gemm_ring)
                 const int c = s_cut[x] + atomicAdd(&counters[x], 1);
                 if (c < s_cut[x + 1]) {
                     on = c;
