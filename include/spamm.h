@@ -110,7 +110,11 @@ int spamm_build_norms(spamm_bsm* X, spamm_stream_t stream);
  *   tau_out   : device [1] selected threshold (0 when none qualifies).
  * With SPAMM_SYNC the call reads idx back and returns SPAMM_WTAUFALLBACK
  * (results valid) when no candidate qualified.
- * Workspace: spamm_sweep_workspace_bytes(nb, N).
+ * Workspace: spamm_sweep_workspace_bytes(nb, N).  Its size does not depend
+ * on the occupancy: the octree's cube level is held densely, two arrays of
+ * T^3 * N doubles with T = 2^(L - l0) cubes per side, L = ceil(log2 nb),
+ * l0 = max(3, L - 7) (T <= 128): 17 MB at nb = 256 and N = 32, 11.7 GB at
+ * nb = 2048 and N = 350, 34 GB at nb = 2048 and N = 1024.
  */
 size_t spamm_sweep_workspace_bytes(int32_t nb, int32_t N);
 int spamm_sweep_tau(const spamm_bsm* A, const spamm_bsm* B, const double* tau, int32_t N,
@@ -155,7 +159,9 @@ int spamm_multiply(const spamm_bsm* A, const spamm_bsm* B, const double* tau_dev
  * each pair's product added into the FP64 accumulator, with
  * ||fl(A_ik B_kj) - A_ik B_kj||_F <= c_t p (spamm_tier_constant):
  *   FP32 tier (default): FP32 copies on the FP32 MFMA,
- *     c_32 = 2u + u^2 + gamma_b(2u)(1+u)^2, u = 2^-24;
+ *     c_32 = 2u + u^2 + gamma_b(2u)(1+u)^2 + 2^-31, u = 2^-24 (the last
+ *     term covers entries and partial results below FP32's normal range);
+ *     a pair whose A or B block has a norm below 2^-40 stays FP64;
  *   split-BF16 tier (SPAMM_TIER_BF16, needs SPAMM_B_TRANSPOSED): each block
  *     scaled by a power of two and split x = hi + lo (BF16), the products
  *     hi*hi + hi*lo + lo*hi on the BF16 MFMA with FP32 accumulation, rescaled

@@ -430,6 +430,35 @@ def combine(X: BSM, C: BSM, branch: int) -> BSM:
     return BSM(X.n, b, (keys // nb).astype(np.int32), (keys % nb).astype(np.int32), vals)
 
 
+# the FP32 tier evaluates a pair only when both of its blocks have a norm of
+# at least this (see tier_constant): below it the pair stays FP64
+FP32_TIER_NORM_MIN = 2.0 ** -40
+
+
+def low_tier_pairs(X: "BSM", tau: float, sigma: float, nu: np.ndarray, precision: int) -> int:
+    """Kept pairs of the symmetric product X X evaluated in the low tier:
+    tau <= p < sigma, and for the FP32 tier both block norms at least
+    FP32_TIER_NORM_MIN."""
+    if not sigma > tau:
+        return 0
+    K = kept(X, X, tau, True, nu, nu)
+    if K.npairs == 0:
+        return 0
+    nb = X.nb
+    mp = X.block_map()
+    counts = (K.kptr[1:] - K.kptr[:-1]).astype(np.int64)
+    ii = np.repeat(K.oi.astype(np.int64), counts)
+    jj = np.repeat(K.oj.astype(np.int64), counts)
+    kk = K.klist.astype(np.int64)
+    na = nu[mp[ii * nb + kk]]
+    nbv = nu[mp[kk * nb + jj]]
+    p = na * nbv
+    low = p < sigma
+    if precision == 1:
+        low &= (na >= FP32_TIER_NORM_MIN) & (nbv >= FP32_TIER_NORM_MIN)
+    return int(np.count_nonzero(low))
+
+
 def tier_constant(precision: int, b: int) -> float:
     """Per-pair rounding factor c of a low-precision leaf-product tier (not in
     the paper): ||fl(AB) - AB||_F <= c ||A||_F ||B||_F for one b x b pair.
@@ -437,7 +466,12 @@ def tier_constant(precision: int, b: int) -> float:
     precision 1, FP32: operands rounded to FP32 (unit roundoff u = 2^-24
     each), b products accumulated in FP32 with an assumed unit roundoff of
     2u: |fl(AB) - AB| <= (2u + u^2 + gamma_b(2u) (1+u)^2) |A||B| entrywise,
-    gamma_m(x) = m x / (1 - m x), then Cauchy-Schwarz per entry.
+    gamma_m(x) = m x / (1 - m x), then Cauchy-Schwarz per entry.  Entries
+    and partial results below FP32's normal range (2^-126) may lose up to
+    2^-126 each (flushed to zero): with both blocks' norms at least
+    FP32_TIER_NORM_MIN = 2^-40 (the tier takes no other pair) that adds at
+    most b^2 2^-126 / 2^-80 + 2 b 2^-126 / 2^-40 < 2^-31 relative to
+    ||A|| ||B|| for b <= 128, the term "underflow".
 
     precision 2, split BF16: each block scaled by a power of two (max entry
     in [1, 2)), split x = hi + lo + e with hi = RN_bf16(x), lo = RN_bf16(x -
@@ -471,7 +505,7 @@ def tier_constant_parts(precision: int, b: int) -> dict:
         u = 2.0 ** -24
         ue = 2.0 * u
         gam = m * ue / (1.0 - m * ue)
-        return {"represent": 2.0 * u + u * u, "accumulate": gam * (1.0 + u) * (1.0 + u), "underflow": 0.0}
+        return {"represent": 2.0 * u + u * u, "accumulate": gam * (1.0 + u) * (1.0 + u), "underflow": 2.0 ** -31}
     if precision == 2:
         u = 2.0 ** -8
         ue = 2.0 * 2.0 ** -24
@@ -625,8 +659,7 @@ def sp2_step(X: BSM, st: SP2State, p: SP2Params):
         sidx, sigma = select(bound2, taus, budget)
     C, K = spamm(X, X, tau, sym=True, nuA=nu, nuB=nu)
     if p.precision:
-        nlow = int(kept(X, X, tau, True, nu, nu).npairs - kept(X, X, max(sigma, tau), True, nu, nu).npairs) \
-            if sigma > tau else 0
+        nlow = low_tier_pairs(X, tau, sigma, nu, p.precision)
     Xh = combine(X, C, br)
     if p.variant == "spamm":
         Xt, ti = Xh.sorted(), None

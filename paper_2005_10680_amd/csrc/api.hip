@@ -275,7 +275,7 @@ void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
 // (map, brow, bcol, nslot); with X given, the pattern of 2X - C (branch 1).
 void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const double* tau_dev, const double* sigma_dev,
                const MatView& C, uint8_t* fromc, MulWs& w, const int32_t* mapX, const int32_t* branch_dev,
-               const int32_t* done, hipStream_t s, const SymOcc* occ = nullptr) {
+               const int32_t* done, hipStream_t s, const SymOcc* occ = nullptr, double norm_min = 0.0) {
     const int nb = A.nb;
     const uint32_t* bA = w.bitsA;
     const uint32_t* bB = w.bitsB;
@@ -288,12 +288,12 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
         launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
     }
     launch_kept_count(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, sigma_dev,
-                      w.cnt, w.cflag, sigma_dev ? w.cnt_low : nullptr, done, s);
+                      norm_min, w.cnt, w.cflag, sigma_dev ? w.cnt_low : nullptr, done, s);
     scan_i32(w.cnt, w.off, w.PP, nullptr, &w.sc[0], w.scan_tmp, s);
     scan_i32(w.cflag, w.oidx, w.PP, nullptr, &w.sc[1], w.scan_tmp, s);
     if (sigma_dev) scan_i32(w.cnt_low, w.hslot, w.PP, nullptr, &w.sc[3], w.scan_tmp, s);  // total low pairs
     else fill_i64(&w.sc[3], 1, 0, s);
-    launch_kept_fill(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, tau_dev, sigma_dev, w.cnt,
+    launch_kept_fill(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, tau_dev, sigma_dev, norm_min, w.cnt,
                      w.off, w.oidx, &w.sc[0], &w.sc[1], w.cap_pairs, w.cap_out, w.oi, w.oj, w.optr, w.pairs,
                      sigma_dev ? w.olow : nullptr, w.ovf, done, s);
     launch_hat_flags(nb, w.P, w.cnt, sym, mapX, branch_dev, w.hflag, done, s);
@@ -388,9 +388,12 @@ bool should_stop(const std::vector<double>& eh, double e_tol) {
 double tier_constant(int precision, int b) {
     const double m = (double)b;
     if (precision == 1) {
+        // operands rounded to FP32, b products accumulated in FP32 (unit
+        // roundoff 2^-23 assumed); 2^-31 covers entries and partial results
+        // below the FP32 normal range, with both block norms >= kFp32TierNormMin
         const double u = 0x1p-24, ue = 2.0 * u;
         const double gam = m * ue / (1.0 - m * ue);
-        return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u)) * (1.0 + 0x1p-40);
+        return (2.0 * u + u * u + gam * (1.0 + u) * (1.0 + u) + 0x1p-31) * (1.0 + 0x1p-40);
     }
     if (precision == 2) {
         // split BF16: x = hi + lo + e after a power-of-two block scaling,
@@ -819,7 +822,8 @@ int spamm_multiply_tiered(const spamm_bsm* A, const spamm_bsm* B, const double* 
         launch_to_f32(A->b, A->nslot, A->cap, A->brow, A->val, a32, btrans, nullptr, s);
         launch_to_f32(B->b, B->nslot, B->cap, B->brow, B->val, b32, btrans, nullptr, s);
     }
-    run_pairs(view(A), view(B), btrans, sym, tau_dev, sigma_dev, view(C), nullptr, w, nullptr, nullptr, nullptr, s);
+    run_pairs(view(A), view(B), btrans, sym, tau_dev, sigma_dev, view(C), nullptr, w, nullptr, nullptr, nullptr, s,
+              nullptr, (flags & SPAMM_TIER_BF16) ? 0.0 : kFp32TierNormMin);
     run_gemm(view(A), view(B), btrans, sym, view(C), nullptr, w, nullptr, nullptr, nullptr, nullptr, s,
              bf16 ? nullptr : a32, bf16 ? nullptr : b32, nullptr, nullptr, bf16 ? a16 : nullptr, bf16 ? b16 : nullptr,
              bf16 ? ea : nullptr, bf16 ? eb : nullptr);
@@ -1031,7 +1035,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
         step_norms.recheck = w.recheck;
         step_norms.nrecheck = &w.mw.counters[8];
         run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
-                  &w.ctl->branch, done, st, &occ);
+                  &w.ctl->branch, done, st, &occ, p->precision == 1 ? kFp32TierNormMin : 0.0);
         // evs[2]/evs[3] bracket the product kernel alone
         const uint16_t* x16 = p->precision == 2 ? reinterpret_cast<const uint16_t*>(w.x32) : nullptr;
         const float* x32 = p->precision == 1 ? (f32_fused ? f32buf[par] : w.x32) : nullptr;
@@ -1710,7 +1714,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
                     launch_to_f32(F[q].b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, gg.cs);
             }
             run_pairs(xv, xv, 1, 1, &w.ctl->tau, tiered ? &w.ctl->sigma : nullptr, nv, w.fromc, w.mw, xv.map,
-                      &w.ctl->branch, done, gg.cs, &occ);
+                      &w.ctl->branch, done, gg.cs, &occ, pq->precision == 1 ? kFp32TierNormMin : 0.0);
             fill_i32(&w.mw.counters[8], 1, 0, gg.cs);  // recheck count of the epilogue norms
         }
         // one persistent product launch per group over all its systems

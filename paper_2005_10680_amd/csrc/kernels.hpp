@@ -63,20 +63,25 @@ SPAMM_DEV void for_each_kept(int i, int j, int nb, int nw, const uint32_t* bitsA
     }
 }
 
+// the FP32 tier takes a pair only when both block norms are at least this
+// (entries and partial results below FP32's normal range then lose less than
+// the rounding constant's underflow term covers)
+constexpr double kFp32TierNormMin = 0x1p-40;
+
 // pairs.hip
 enum OccMode { kOccA = 0, kOccB = 1, kOccBt = 2 };
 void launch_occupancy(const MatView& M, int mode, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0,
                       const int32_t* done, hipStream_t s);
 void launch_kept_count(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
                        const double* normA, const int32_t* mapB, const double* normB, int btrans, int sym,
-                       const double* tau, const double* sigma, int32_t* cnt, int32_t* cnt_flag, int32_t* cnt_low,
-                       const int32_t* done, hipStream_t s);
+                       const double* tau, const double* sigma, double norm_min, int32_t* cnt, int32_t* cnt_flag,
+                       int32_t* cnt_low, const int32_t* done, hipStream_t s);
 void launch_kept_fill(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
                       const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
-                      const double* sigma, const int32_t* cnt, const int32_t* off, const int32_t* oidx,
-                      const int64_t* npairs, const int64_t* nout, int64_t cap_pairs, int64_t cap_out, int32_t* oi,
-                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int32_t* ovf, const int32_t* done,
-                      hipStream_t s);
+                      const double* sigma, double norm_min, const int32_t* cnt, const int32_t* off,
+                      const int32_t* oidx, const int64_t* npairs, const int64_t* nout, int64_t cap_pairs,
+                      int64_t cap_out, int32_t* oi, int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow,
+                      int32_t* ovf, const int32_t* done, hipStream_t s);
 void launch_hat_flags(int nb, int P, const int32_t* cnt, int sym, const int32_t* mapX, const int32_t* branch,
                       int32_t* flag, const int32_t* done, hipStream_t s);
 void launch_hat_assign(int nb, int P, const int32_t* cnt, int sym, const int32_t* flag, const int32_t* slot,

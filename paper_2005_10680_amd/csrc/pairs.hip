@@ -44,7 +44,7 @@ __global__ void k_kept_count(int nb, int P, int nw, const uint32_t* __restrict__
                              const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
                              const double* __restrict__ normA, const int32_t* __restrict__ mapB,
                              const double* __restrict__ normB, int btrans, int sym, const double* __restrict__ tau_p,
-                             const double* __restrict__ sigma_p, int32_t* __restrict__ cnt,
+                             const double* __restrict__ sigma_p, double norm_min, int32_t* __restrict__ cnt,
                              int32_t* __restrict__ cnt_flag, int32_t* __restrict__ cnt_low,
                              const int32_t* __restrict__ done) {
     if (done && *done) return;
@@ -57,9 +57,9 @@ __global__ void k_kept_count(int nb, int P, int nw, const uint32_t* __restrict__
         int c = 0, cl = 0;
         if ((int)i < nb && (int)j < nb && !(sym && i > j)) {
             for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                          [&](int, int, int, double p) {
+                          [&](int, int sa, int sb, double p) {
                               ++c;
-                              if (p < sigma) ++cl;
+                              if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) ++cl;
                           });
         }
         cnt[z] = c;
@@ -70,21 +70,21 @@ __global__ void k_kept_count(int nb, int P, int nw, const uint32_t* __restrict__
 
 void launch_kept_count(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
                        const double* normA, const int32_t* mapB, const double* normB, int btrans, int sym,
-                       const double* tau, const double* sigma, int32_t* cnt, int32_t* cnt_flag, int32_t* cnt_low,
-                       const int32_t* done, hipStream_t s) {
+                       const double* tau, const double* sigma, double norm_min, int32_t* cnt, int32_t* cnt_flag,
+                       int32_t* cnt_low, const int32_t* done, hipStream_t s) {
     int64_t PP = (int64_t)P * P;
     hipLaunchKernelGGL(k_kept_count, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB, mapA,
-                       normA, mapB, normB, btrans, sym, tau, sigma, cnt, cnt_flag, cnt_low, done);
+                       normA, mapB, normB, btrans, sym, tau, sigma, norm_min, cnt, cnt_flag, cnt_low, done);
 }
 
-// Pairs of one output: low-precision pairs (tau <= p < sigma) first, then the
-// FP64 ones, each group in ascending k.  Without tiers (sigma null) every
-// pair is FP64.
+// Pairs of one output: low-precision pairs (tau <= p < sigma, both block
+// norms >= norm_min) first, then the FP64 ones, each group in ascending k.
+// Without tiers (sigma null) every pair is FP64.
 __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ bitsA,
                             const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
                             const double* __restrict__ normA, const int32_t* __restrict__ mapB,
                             const double* __restrict__ normB, int btrans, const double* __restrict__ tau_p,
-                            const double* __restrict__ sigma_p, const int32_t* __restrict__ cnt,
+                            const double* __restrict__ sigma_p, double norm_min, const int32_t* __restrict__ cnt,
                             const int32_t* __restrict__ off, const int32_t* __restrict__ oidx,
                             const int64_t* __restrict__ npairs_p, const int64_t* __restrict__ nout_p, int64_t cap_pairs,
                             int64_t cap_out, int32_t* __restrict__ oi, int32_t* __restrict__ oj,
@@ -115,7 +115,7 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
         if (sigma_p) {
             for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
                           [&](int, int sa, int sb, double p) {
-                              if (p < sigma) {
+                              if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) {
                                   if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
                                   ++w;
                               }
@@ -123,7 +123,7 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
             if (olow) olow[o] = (int32_t)(w - off[z]);
             for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
                           [&](int, int sa, int sb, double p) {
-                              if (!(p < sigma)) {
+                              if (!(p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min)) {
                                   if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
                                   ++w;
                               }
@@ -140,13 +140,13 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
 
 void launch_kept_fill(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
                       const double* normA, const int32_t* mapB, const double* normB, int btrans, const double* tau,
-                      const double* sigma, const int32_t* cnt, const int32_t* off, const int32_t* oidx,
-                      const int64_t* npairs, const int64_t* nout, int64_t cap_pairs, int64_t cap_out, int32_t* oi,
-                      int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int32_t* ovf, const int32_t* done,
-                      hipStream_t s) {
+                      const double* sigma, double norm_min, const int32_t* cnt, const int32_t* off,
+                      const int32_t* oidx, const int64_t* npairs, const int64_t* nout, int64_t cap_pairs,
+                      int64_t cap_out, int32_t* oi, int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow,
+                      int32_t* ovf, const int32_t* done, hipStream_t s) {
     int64_t PP = (int64_t)P * P;
     hipLaunchKernelGGL(k_kept_fill, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB, mapA,
-                       normA, mapB, normB, btrans, tau, sigma, cnt, off, oidx, npairs, nout, cap_pairs, cap_out, oi,
+                       normA, mapB, normB, btrans, tau, sigma, norm_min, cnt, off, oidx, npairs, nout, cap_pairs, cap_out, oi,
                        oj, optr, pairs, olow, ovf, done);
 }
 

@@ -195,7 +195,7 @@ def test_tiers_with_leaf_bound_teacher_forced(precision):
         assert lg["sidx"] == sidx and lg["sigma"] == sigma
         K = oracle.kept(X, X, tau, True, nu, nu)
         assert lg["npairs"] == K.npairs
-        low = K.npairs - oracle.kept(X, X, max(sigma, tau), True, nu, nu).npairs if sigma > tau else 0
+        low = oracle.low_tier_pairs(X, tau, sigma, nu, prec)
         assert lg["npairs_low"] == low
         nlow += low
     assert nlow > 0

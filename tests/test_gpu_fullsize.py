@@ -73,7 +73,7 @@ def check_step(X, nu_gpu, lg, xh, xl, p, Xnext, rng, nsample=24):
         bound2 = oracle.cse_tree(X, X, taus, nu, nu, mode=1, tau0=tau, c_low=c_low)
         sidx, sigma = oracle.select(bound2, taus, budget)
         assert lg["sidx"] == sidx and lg["sigma"] == sigma
-        nlow = K.npairs - oracle.kept(X, X, max(sigma, tau), True, nu, nu).npairs if sigma > tau else 0
+        nlow = oracle.low_tier_pairs(X, tau, sigma, nu, p.precision)
         assert lg["npairs_low"] == nlow
     # sampled output blocks: the longest k list, the first and last outputs,
     # random ones that the truncation kept and random ones it removed

@@ -55,7 +55,7 @@ def test_multiply_tiered_within_folded_bound(n, b, seed, tier):
     Co, Ko = oracle.spamm(X, X, tau, sym=True)
     kg = kept.cpu().numpy()
     assert int(kg[0]) == Ko.npairs
-    nlow = Ko.npairs - oracle.kept(X, X, sigma, True).npairs
+    nlow = oracle.low_tier_pairs(X, tau, sigma, nu, TIERS[tier])
     assert int(kg[2]) == nlow and nlow > 0
     G = to_oracle(C)
     assert np.array_equal(G.keys(), Co.keys())

@@ -459,3 +459,58 @@ def test_leaf_bounds_equal_exact_rational_sums(seed):
                 F2 += Fraction(s * s)
         assert ssum[m] == float(S)
         assert flat[m] == math.sqrt(float(F2))
+
+
+# ---------------------------------------------------------------------------
+# the FP32 tier's operand-norm guard
+# ---------------------------------------------------------------------------
+
+def _ftz32(x):
+    """Round to FP32 and flush values below the normal range to zero (the
+    worst a flush-to-zero datapath does)."""
+    y = np.asarray(x, dtype=np.float32).astype(np.float64)
+    y[np.abs(y) < 2.0 ** -126] = 0.0
+    return y
+
+
+@pytest.mark.parametrize("b", [32, 64])
+def test_fp32_tier_guard_and_underflow_term(b):
+    """A block whose entries all lie below FP32's normal range loses them
+    entirely under flush-to-zero, an error of the whole product that no
+    relative rounding constant covers: the FP32 tier must not take it, and
+    oracle.low_tier_pairs keeps such pairs in FP64.  Blocks that pass the
+    guard (norm >= 2^-40) but hold entries below 2^-126 stay within c_32,
+    whose underflow term covers the flushed part."""
+    rng = np.random.default_rng(b + 5)
+    c = oracle.tier_constant(1, b)
+    # below the guard: every entry subnormal in FP32
+    A = rng.standard_normal((b, b)) * 2.0 ** -140
+    B = rng.standard_normal((b, b))
+    err = np.linalg.norm(_ftz32(A) @ _ftz32(B) - A @ B) / (np.linalg.norm(A) * np.linalg.norm(B))
+    assert np.linalg.norm(A) < oracle.FP32_TIER_NORM_MIN and err > 1e-2 > 100 * c
+    # at the guard: norm 2^-40, a third of the entries far below 2^-126
+    for _ in range(20):
+        A = rng.standard_normal((b, b))
+        A[rng.random((b, b)) < 0.33] *= 2.0 ** -110
+        A *= oracle.FP32_TIER_NORM_MIN / np.linalg.norm(A)
+        B = rng.standard_normal((b, b))
+        B *= oracle.FP32_TIER_NORM_MIN / np.linalg.norm(B) * 4.0
+        P32 = (_ftz32(A).astype(np.float32) @ _ftz32(B).astype(np.float32)).astype(np.float64)
+        err = np.linalg.norm(P32 - A @ B) / (np.linalg.norm(A) * np.linalg.norm(B))
+        assert err <= c
+    # the tier split: a pair with a block below the guard stays FP64
+    nb = 3
+    vals = np.zeros((nb, b, b))
+    vals[0, 0, 0] = 1.0
+    vals[1, 0, 0] = 2.0 ** -50              # below the guard
+    vals[2, 0, 0] = 2.0 ** -20
+    idx = np.arange(nb, dtype=np.int32)
+    X = oracle.BSM(nb * b, b, np.concatenate([idx, [0, 1]]).astype(np.int32),
+                   np.concatenate([idx, [1, 0]]).astype(np.int32),
+                   np.concatenate([vals, vals[2:3], vals[2:3]]))
+    X = X.sorted()
+    nu = oracle.norms(X)[1]
+    all_low = oracle.low_tier_pairs(X, 0.0, 1e300, nu, 2)      # split BF16: no guard
+    fp32_low = oracle.low_tier_pairs(X, 0.0, 1e300, nu, 1)
+    K = oracle.kept(X, X, 0.0, True, nu, nu)
+    assert all_low == K.npairs and fp32_low < all_low
