@@ -953,17 +953,20 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
     // from this XCD's range while it lasts, then from the other ranges in
     // turn, so that no XCD idles while another still has outputs; -1 once
     // every range is drained (at most 8 failed claims per workgroup, and none on
-    // a range whose counter already shows it drained)
+    // another range whose counter already shows it drained)
     int r = 0;
     auto fetch = [&]() -> int {
         if (tid == 0) {
             int on = -1;
             for (; r < 8; ++r) {
                 const int x = (xcd + r) & 7;
-                // a drained range is seen with a plain load, so the atomics
-                // (serialised per counter) go to ranges that still have work
-                if (__hip_atomic_load(&g.counters[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-                    s_cut[x + 1] - s_cut[x])
+                // another XCD's range: skip it when a plain load shows it
+                // drained, so that with few outputs the many idle workgroups
+                // do not queue atomics (serialised per counter) on empty
+                // ranges; the own range is claimed at once (the load would
+                // add its latency to every claim)
+                if (r > 0 && __hip_atomic_load(&g.counters[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                 s_cut[x + 1] - s_cut[x])
                     continue;
                 const int c = s_cut[x] + atomicAdd(&g.counters[x], 1);
                 if (c < s_cut[x + 1]) {
@@ -1039,9 +1042,9 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
             int on = -1;
             for (; r < 8; ++r) {
                 const int x = (xcd + r) & 7;
-                if (__hip_atomic_load(&counters[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-                    s_cut[x + 1] - s_cut[x])
-                    continue;  // drained (a plain load; see k_gemm_ring)
+                if (r > 0 && __hip_atomic_load(&counters[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                                 s_cut[x + 1] - s_cut[x])
+                    continue;  // another range, drained (a plain load; see k_gemm_ring)
                 const int c = s_cut[x] + atomicAdd(&counters[x], 1);
                 if (c < s_cut[x + 1]) {
                     on = c;
