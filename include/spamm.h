@@ -402,6 +402,20 @@ int spamm_set_gemm_schedule(int32_t b, int32_t workgroups_per_cu);
 int spamm_get_gemm_schedule(int32_t b);
 
 /*
+ * Small-system passes (not in the paper): for nb <= 64 the occupancy and
+ * sweep-list pass, the kept-pair and output-pattern passes of a product and
+ * the truncation (iterates of at most 4096 slots) each run in one workgroup
+ * instead of a chain of device-wide launches.  Same lists in the same order,
+ * so every result is bit-identical either way; only the number of dependent
+ * launches per purification step changes.  on: 1 (default) or 0;
+ * process-wide, read when work is enqueued (a captured graph keeps the
+ * passes it was captured with).  SPAMM_EINVAL for other values.
+ * spamm_get_small_path returns the current setting.
+ */
+int spamm_set_small_path(int32_t on);
+int spamm_get_small_path(void);
+
+/*
  * Leaf-size and schedule autotuner (not in the paper).  For each leaf size
  * (32, 64, 128; 32 and 64 with the FP32 tier) F is re-blocked and the first
  * trial_steps steps of its purification with parameters p are timed (the

@@ -127,6 +127,8 @@ def lib() -> ctypes.CDLL:
     L.spamm_reblock.argtypes = [B, B, P, sz, P]
     L.spamm_set_gemm_schedule.argtypes = [i32, i32]
     L.spamm_get_gemm_schedule.argtypes = [i32]
+    L.spamm_set_small_path.argtypes = [i32]
+    L.spamm_get_small_path.argtypes = []
     L.purify_sp2_autotune_workspace_bytes.argtypes = [i64, i32, i32]
     L.purify_sp2_autotune_workspace_bytes.restype = sz
     L.purify_sp2_autotune.argtypes = [B, ctypes.POINTER(sp2_params), i32, P, P, P, P, sz, P]
@@ -561,6 +563,14 @@ def set_gemm_schedule(b: int, workgroups_per_cu: int) -> None:
 
 def get_gemm_schedule(b: int) -> int:
     return _check(lib().spamm_get_gemm_schedule(int(b)))
+
+
+def set_small_path(on: bool) -> None:
+    _check(lib().spamm_set_small_path(1 if on else 0))
+
+
+def get_small_path() -> bool:
+    return bool(_check(lib().spamm_get_small_path()))
 
 
 def autotune(F: BlockSparse, n_occ: int, eps: float, taus, homo=float("nan"), lumo=float("nan"), variant="hybrid",

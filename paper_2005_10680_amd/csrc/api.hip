@@ -16,6 +16,13 @@
 
 using namespace spamm;
 
+namespace spamm {
+// small-system single-workgroup passes (on by default)
+static std::atomic<bool> g_small_path{true};
+bool small_path_enabled() { return g_small_path.load(std::memory_order_relaxed); }
+void set_small_path(bool on) { g_small_path.store(on, std::memory_order_relaxed); }
+}  // namespace spamm
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -160,14 +167,23 @@ void carve_sweep(Carver& c, int nb, int N, SweepWs& w) {
 struct SymOcc {
     const uint32_t* bits;
     const uint8_t* tiles;
+    bool cubes;  // the sweep's cube list of X X^T is in sw->keys[0] / sw->cnt[0]
 };
 
+// With sw given and a small X, one workgroup builds the occupancy and the
+// sweep's cube list (the sweeps of the step then start at the cube pass;
+// for nb <= kSmallNb no level pass runs below the top levels, so the list
+// stays intact across the step's sweeps).
 SymOcc build_sym_occ(const MatView& X, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0, const int32_t* done,
-                     hipStream_t s) {
+                     hipStream_t s, SweepWs* sw = nullptr) {
+    if (X.nb <= kSmallNb && T <= kSmallTiles && small_path_enabled()) {
+        launch_occ_small(X, bits, nw, tiles, T, l0, sw ? sw->keys[0] : nullptr, sw ? &sw->cnt[0] : nullptr, done, s);
+        return SymOcc{bits, tiles, sw != nullptr};
+    }
     fill_u32(bits, (int64_t)X.nb * nw, 0u, s);
     fill_u8(tiles, (int64_t)T * T, 0, s);
     launch_occupancy(X, kOccA, bits, nw, tiles, T, l0, done, s);
-    return SymOcc{bits, tiles};
+    return SymOcc{bits, tiles, false};
 }
 
 // The leaf-level bounds B_flat (kind 1) or B_sum (kind 2) for every
@@ -198,7 +214,9 @@ void run_sweep(const MatView& A, const MatView& B, int btrans, const double* tau
                double budget_host, int mode, const double* tau0, double c_low, double* bound_out, int32_t* idx_out,
                double* tau_out, SweepWs& w, const int32_t* done, hipStream_t s, const SymOcc* occ = nullptr) {
     const int T = w.T;
-    if (occ) {
+    if (occ && occ->cubes) {
+        // cube list already built with the occupancy
+    } else if (occ) {
         launch_cube_flags(T, occ->tiles, occ->tiles, w.flag, done, s);
     } else {
         fill_u8(w.tA, (int64_t)T * T, 0, s);
@@ -207,8 +225,10 @@ void run_sweep(const MatView& A, const MatView& B, int btrans, const double* tau
         launch_occupancy(B, btrans ? kOccBt : kOccB, nullptr, 0, w.tB, T, w.l0, done, s);
         launch_cube_flags(T, w.tA, w.tB, w.flag, done, s);
     }
-    scan_i32(w.flag, w.idx, w.ncap, nullptr, &w.cnt[0], w.scan_tmp, s);
-    launch_cube_list(T, w.flag, w.idx, w.keys[0], &w.cnt[0], w.ncap, w.ovf, done, s);
+    if (!(occ && occ->cubes)) {
+        scan_i32(w.flag, w.idx, w.ncap, nullptr, &w.cnt[0], w.scan_tmp, s);
+        launch_cube_list(T, w.flag, w.idx, w.keys[0], &w.cnt[0], w.ncap, w.ovf, done, s);
+    }
     launch_cube_eval(mode, w.l0, A.nb, w.keys[0], &w.cnt[0], w.ncap, A.map, A.norm, B.map, B.norm, btrans, tau, N,
                      tau0, c_low, w.vals[0], done, s);
     // levels whose children may number more than kTopNodes (8^4) run as
@@ -242,6 +262,7 @@ struct MulWs {
     int32_t* counters;
     int32_t* ovf;
     void* scan_tmp;
+    bool counters_clear = false;  // the last pair pass cleared the product's work counters
 };
 
 void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
@@ -287,6 +308,15 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
         launch_occupancy(A, kOccA, w.bitsA, w.nw, nullptr, 0, 0, done, s);
         launch_occupancy(B, btrans ? kOccBt : kOccB, w.bitsB, w.nw, nullptr, 0, 0, done, s);
     }
+    if (nb <= kSmallNb && small_path_enabled()) {
+        launch_pairs_small(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, sigma_dev,
+                           norm_min, w.cap_pairs, w.cap_out, w.oi, w.oj, w.optr, w.pairs, sigma_dev ? w.olow : nullptr,
+                           w.sc, C.cap, C.map, C.brow, C.bcol, C.nslot, fromc, mapX, branch_dev, w.counters, w.ovf,
+                           done, s);
+        w.counters_clear = true;
+        return;
+    }
+    w.counters_clear = false;
     launch_kept_count(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, sigma_dev,
                       norm_min, w.cnt, w.cflag, sigma_dev ? w.cnt_low : nullptr, done, s);
     scan_i32(w.cnt, w.off, w.PP, nullptr, &w.sc[0], w.scan_tmp, s);
@@ -358,7 +388,8 @@ int run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatV
         if (!btrans || !valA32) return -1;
         g.out32 = out32;
     }
-    launch_gemm_f64(g, num_cus(), s, ev_start, ev_end);
+    launch_gemm_f64(g, num_cus(), s, ev_start, ev_end, w.counters_clear);
+    w.counters_clear = false;
     if (mapX)
         launch_rest(A.b, C.nslot, C.cap, C.brow, C.bcol, fromc, nb, mapX, valX, C.val, branch_dev, done, s, no, out32);
     return 0;
@@ -485,6 +516,19 @@ struct Sp2Ws {
 // FP64, leaf 32 and 64 in the two tiers
 constexpr int kBatchGroups = 7;
 constexpr int kMaxLog = 10002;  // n_max <= 10000, plus the stop record
+
+// the control step of the device-driven loop, run by the traces launch
+TraceTail control_tail(const Sp2Ws& w) {
+    TraceTail t;
+    t.ctl = w.ctl;
+    t.msc = w.mw.sc;
+    t.ts = w.tstats;
+    t.ovf_mul = w.mw.ovf;
+    t.ovf_sweep = w.sw.ovf;
+    t.logs = w.dlog;
+    t.max_records = kMaxLog;
+    return t;
+}
 
 // x1_outside: the second iterate buffer X[1] is not carved (the batched
 // loop uses the caller's output matrix for it)
@@ -961,6 +1005,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     fill_i32(w.mw.ovf, 1, 0, s);
     fill_i32(w.sw.ovf, 1, 0, s);
     fill_i64(w.tstats, 4, 0, s);  // stays 0 when no step truncates (Algorithm 4)
+    launch_traces_init(w.trace_tmp, s);
 
     // X_0 and its first truncation
     MatView Fv = view(F);
@@ -1002,7 +1047,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
                             hipStream_t st) -> int {
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
         // the iterate's occupancy, shared by the sweeps and the kept pairs
-        const SymOcc occ = build_sym_occ(xv, w.mw.bitsA, w.mw.nw, w.sw.tA, w.sw.T, w.sw.l0, done, st);
+        const SymOcc occ = build_sym_occ(xv, w.mw.bitsA, w.mw.nw, w.sw.tA, w.sw.T, w.sw.l0, done, st, &w.sw);
         if (p->variant != 2 && p->bound_kind != 0)
             run_sweep_leaf(xv, xv, 1, p->tau, p->N, &w.ctl->budget_skip, 0.0, p->bound_kind, 0, nullptr, 0.0,
                            w.bound, &w.ctl->idx,
@@ -1100,9 +1145,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             MatView xv = view(&w.X[q]);
             MatView nv = view(&w.X[1 - q]);
             launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
-                          w.trace_out, &w.ctl->done, gg.cs);
-            launch_sp2_control(w.ctl, w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, xv.nslot, w.dlog, kMaxLog,
-                               gg.cs);
+                          w.trace_out, &w.ctl->done, gg.cs, control_tail(w));
             rc_cap = enqueue_step(xv, nv, q, &w.ctl->done, nullptr, gg.cs);
         }
         hipError_t ec = hipStreamEndCapture(gg.cs, &gg.g);
@@ -1149,13 +1192,19 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             spamm_bsm* Xc = full_tape ? &w.tape[it - 1] : &w.X[cur];
             spamm_bsm* Xn = full_tape ? (it <= tape_steps ? &w.tape[it] : nullptr) : &w.X[1 - cur];
             MatView xv = view(Xc);
+            TraceTail tail;
+            tail.hs = hs_dev;
+            tail.ctl_read = w.ctl;
+            tail.msc = w.mw.sc;
+            tail.ts = w.tstats;
+            tail.ovf_mul = w.mw.ovf;
+            tail.ovf_sweep = w.sw.ovf;
             launch_traces(xv.nslot, xv.cap, b, F->n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
-                          w.trace_out, nullptr, s);
+                          w.trace_out, nullptr, s, tail);
             double tr[4];
             int64_t msc[4], ts[3];
             int32_t ovf[2];
             Sp2Ctl cs;
-            launch_host_status(w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, w.ctl, xv.nslot, hs_dev, s);
             HIP_TRY(hipGetLastError());
             HIP_TRY(hipStreamSynchronize(s));
             memcpy(tr, ps.h->tr, sizeof(tr));
@@ -1552,6 +1601,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
         fill_i32(w.mw.ovf, 1, 0, s);
         fill_i32(w.sw.ovf, 1, 0, s);
         fill_i64(w.tstats, 4, 0, s);
+        launch_traces_init(w.trace_tmp, s);
         MatView Fv = view(&F[q]);
         MatView X0 = view(&w.X[0]);
         launch_gersch(Fv, w.rowtmp, w.lam, s);
@@ -1678,9 +1728,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             Sp2Ws& w = W[q];
             MatView xv = view(&w.X[par]);
             launch_traces(xv.nslot, xv.cap, F[q].b, F[q].n, xv.brow, xv.bcol, xv.val, xv.sq, xv.sqlo, w.trace_tmp,
-                          w.trace_out, &w.ctl->done, gg.cs);
-            launch_sp2_control(w.ctl, w.trace_out, w.mw.sc, w.tstats, w.mw.ovf, w.sw.ovf, xv.nslot, w.dlog, kMaxLog,
-                               gg.cs);
+                          w.trace_out, &w.ctl->done, gg.cs, control_tail(w));
         }
         // sweeps, kept pairs and output patterns, system by system
         for (int q = 0; q < nsys; ++q) {
@@ -1690,7 +1738,7 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
             const int32_t* done = &w.ctl->done;
             MatView xv = view(&w.X[par]);
             MatView nv = view(&w.X[1 - par]);
-            const SymOcc occ = build_sym_occ(xv, w.mw.bitsA, w.mw.nw, w.sw.tA, w.sw.T, w.sw.l0, done, gg.cs);
+            const SymOcc occ = build_sym_occ(xv, w.mw.bitsA, w.mw.nw, w.sw.tA, w.sw.T, w.sw.l0, done, gg.cs, &w.sw);
             if (pq->variant != 2 && pq->bound_kind != 0)
                 run_sweep_leaf(xv, xv, 1, pq->tau, pq->N, &w.ctl->budget_skip, 0.0, pq->bound_kind, 0, nullptr, 0.0,
                                w.bound,
@@ -1853,6 +1901,14 @@ int spamm_get_gemm_schedule(int32_t b) {
     if (b != 32 && b != 64 && b != 128) return fail(SPAMM_EINVAL, "leaf size must be 32, 64 or 128");
     return get_ring_per_cu(b);
 }
+
+int spamm_set_small_path(int32_t on) {
+    if (on != 0 && on != 1) return fail(SPAMM_EINVAL, "small-system path switch must be 0 or 1");
+    set_small_path(on != 0);
+    return SPAMM_OK;
+}
+
+int spamm_get_small_path(void) { return small_path_enabled() ? 1 : 0; }
 
 }  // extern "C"
 

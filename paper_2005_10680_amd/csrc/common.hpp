@@ -148,6 +148,29 @@ SPAMM_DEV bool sq_certified(dd acc, bool special, bool tiny) {
     return (dn + 2.0 * acc.lo) > 2.0 * eb;
 }
 
+// inclusive scan of one int64 per thread across a block of THREADS threads
+template <int THREADS = 256>
+SPAMM_DEV int64_t block_inclusive_scan(int64_t v, int64_t* sh_wave, int64_t& block_total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int64_t o = __shfl_up(v, d);
+        if (lane >= d) v += o;
+    }
+    if (lane == 63) sh_wave[w] = v;
+    __syncthreads();
+    int64_t off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < THREADS / 64; ++q) {
+        int64_t t = sh_wave[q];
+        if (q < w) off += t;
+        tot += t;
+    }
+    __syncthreads();
+    block_total = tot;
+    return v + off;
+}
+
 // ---------------------------------------------------------------------------
 // Device control block of one purification (all decisions stay on device).
 // ---------------------------------------------------------------------------

@@ -1,20 +1,24 @@
-// Device-side control of the purification loop (Algorithms 1, 4, 5): the
-// decisions the host loop takes between two steps, taken by one thread on
-// the device so that a captured graph of the whole step can be replayed
-// without reading anything back.  Same rules, same arithmetic (the shared
-// sp2_* functions of common.hpp).
+// The traces of the current iterate and the decisions the purification loop
+// (Algorithms 1, 4, 5) takes from them.
+//
+// In the device-driven loop the decisions are taken by one thread on the
+// device, so that a captured graph of the whole step can be replayed without
+// reading anything back; in the host loop the same launch gathers what the
+// host reads into host-mapped memory.  Both run in the traces launch itself,
+// in its last workgroup.  Same rules, same arithmetic as the host (the
+// shared sp2_* functions of common.hpp).
 #include "../../include/spamm.h"
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace spamm {
 
-__global__ void k_sp2_control(Sp2Ctl* __restrict__ ctl, const double* __restrict__ tr,
-                              const int64_t* __restrict__ msc, const int64_t* __restrict__ ts,
-                              const int32_t* __restrict__ ovf_mul, const int32_t* __restrict__ ovf_sweep,
-                              const int32_t* __restrict__ nslot_cur, sp2_iter_log* __restrict__ logs,
-                              int32_t max_records) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One control step: record the results of the step that produced the current
+// iterate, then (unless the loop stops) the next step's branch, delta_i and
+// budgets.  tr: t1 hi, lo, t2 hi, lo of the current iterate.
+SPAMM_DEV void sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts,
+                           const int32_t* ovf_mul, const int32_t* ovf_sweep, sp2_iter_log* logs,
+                           int32_t max_records) {
     if (ctl->done) return;
     const int nlog = ctl->nlog;
     const int it = nlog + 1;
@@ -82,29 +86,125 @@ __global__ void k_sp2_control(Sp2Ctl* __restrict__ ctl, const double* __restrict
     ctl->sidx = ctl->N;
 }
 
-__global__ void k_host_status(const double* __restrict__ tr, const int64_t* __restrict__ msc,
-                              const int64_t* __restrict__ ts, const int32_t* __restrict__ ovf_mul,
-                              const int32_t* __restrict__ ovf_sweep, const Sp2Ctl* __restrict__ ctl,
-                              const int32_t* __restrict__ nslot, Sp2HostStatus* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int q = 0; q < 4; ++q) {
-        out->tr[q] = tr[q];
-        out->msc[q] = msc[q];
+// ---------------------------------------------------------------------------
+// Traces: t1 = sum of the diagonal entries (rows below n), t2 = sum over the
+// live slots of (sq + sqlo) = ||X||_F^2, both in double-double.  Fixed
+// grid and fixed reduction order (slots strided over the grid, a wave tree,
+// the four waves in order, then the partials of the workgroups: lane l adds
+// partial l + 64 to partial l, then a wave tree), so the result depends only
+// on the slot contents and order.
+// ---------------------------------------------------------------------------
+constexpr int kTrBlocks = 120;
+static_assert(kTrBlocks <= 128, "two partials per lane in the last workgroup");
+
+__global__ __launch_bounds__(256) void k_traces(const int32_t* __restrict__ nslot_p, int64_t cap, int b, int64_t n,
+                                               const int32_t* __restrict__ brow, const int32_t* __restrict__ bcol,
+                                               const double* __restrict__ val, const double* __restrict__ sq,
+                                               const double* __restrict__ sqlo, double* part /* [kTrBlocks][4] */,
+                                               double* __restrict__ out, const int32_t* __restrict__ done,
+                                               TraceTail tail) {
+    __shared__ double sh[4][4];
+    __shared__ int s_last;
+    if (done && *done) return;
+    int64_t nslot = *nslot_p;
+    if (nslot > cap) nslot = cap;
+    dd d1 = {0, 0}, d2 = {0, 0};
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslot; s += (int64_t)gridDim.x * blockDim.x) {
+        int r = brow[s];
+        if (r < 0) continue;
+        d2 = dd_add(d2, dd{sq[s], 0.0});
+        d2 = dd_add(d2, dd{sqlo[s], 0.0});
+        if (r == bcol[s]) {
+            // diagonal entries t < cnt (rows below n), added in ascending t;
+            // sixteen loads in flight before their additions
+            const double* v = val + (size_t)s * b * b;
+            const int64_t rem = n - (int64_t)r * b;
+            const int cnt = rem < (int64_t)b ? (int)rem : b;
+            for (int t0 = 0; t0 < cnt; t0 += 16) {
+                double x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) x[u] = t0 + u < cnt ? v[(size_t)(t0 + u) * b + t0 + u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (t0 + u < cnt) d1 = dd_add(d1, dd{x[u], 0.0});
+            }
+        }
     }
-    out->ts[0] = ts[0];
-    out->ts[1] = ts[1];
-    out->ts[2] = ts[2];
-    out->ovf[0] = *ovf_mul;
-    out->ovf[1] = *ovf_sweep;
-    out->nslot = *nslot;
-    out->ctl = *ctl;
-    __threadfence_system();
+    d1 = dd_wave_sum(d1);
+    d2 = dd_wave_sum(d2);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[w][0] = d1.hi; sh[w][1] = d1.lo; sh[w][2] = d2.hi; sh[w][3] = d2.lo;
+    }
+    __syncthreads();
+    int32_t* ticket = reinterpret_cast<int32_t*>(part + kTrBlocks * 4);
+    if (threadIdx.x == 0) {
+        dd a = {0, 0}, c = {0, 0};
+        for (int q = 0; q < 4; ++q) {
+            a = dd_add(a, dd{sh[q][0], sh[q][1]});
+            c = dd_add(c, dd{sh[q][2], sh[q][3]});
+        }
+        part[blockIdx.x * 4 + 0] = a.hi; part[blockIdx.x * 4 + 1] = a.lo;
+        part[blockIdx.x * 4 + 2] = c.hi; part[blockIdx.x * 4 + 3] = c.lo;
+        __threadfence();  // the partial is visible before the ticket is taken
+        s_last = atomicAdd(ticket, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // last workgroup: every partial is written
+    __threadfence();
+    if (threadIdx.x >= 64) return;
+    const int G = (int)gridDim.x;
+    dd a = {0, 0}, c = {0, 0};
+    if (lane < G) {
+        a = dd{part[lane * 4 + 0], part[lane * 4 + 1]};
+        c = dd{part[lane * 4 + 2], part[lane * 4 + 3]};
+    }
+    if (lane + 64 < G) {
+        a = dd_add(a, dd{part[(lane + 64) * 4 + 0], part[(lane + 64) * 4 + 1]});
+        c = dd_add(c, dd{part[(lane + 64) * 4 + 2], part[(lane + 64) * 4 + 3]});
+    }
+    a = dd_wave_sum(a);
+    c = dd_wave_sum(c);
+    if (lane != 0) return;
+    *ticket = 0;
+    const double tr[4] = {a.hi, a.lo, c.hi, c.lo};
+    out[0] = tr[0]; out[1] = tr[1]; out[2] = tr[2]; out[3] = tr[3];
+    if (tail.ctl) sp2_control(tail.ctl, tr, tail.msc, tail.ts, tail.ovf_mul, tail.ovf_sweep, tail.logs,
+                              tail.max_records);
+    if (tail.hs) {
+        // what the host loop reads after each step, into host-mapped memory
+        Sp2HostStatus* o = tail.hs;
+        for (int q = 0; q < 4; ++q) {
+            o->tr[q] = tr[q];
+            o->msc[q] = tail.msc[q];
+        }
+        o->ts[0] = tail.ts[0];
+        o->ts[1] = tail.ts[1];
+        o->ts[2] = tail.ts[2];
+        o->ovf[0] = *tail.ovf_mul;
+        o->ovf[1] = *tail.ovf_sweep;
+        o->nslot = *nslot_p;
+        o->ctl = *tail.ctl_read;
+        __threadfence_system();
+    }
 }
 
-void launch_host_status(const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
-                        const int32_t* ovf_sweep, const Sp2Ctl* ctl, const int32_t* nslot, Sp2HostStatus* out,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_host_status, dim3(1), dim3(64), 0, s, tr, msc, ts, ovf_mul, ovf_sweep, ctl, nslot, out);
+size_t traces_temp_bytes() { return sizeof(double) * 4 * kTrBlocks + 64; }
+
+__global__ void k_traces_init(double* part) {
+    if (threadIdx.x == 0) *reinterpret_cast<int32_t*>(part + kTrBlocks * 4) = 0;
+}
+
+void launch_traces_init(double* temp, hipStream_t s) {
+    hipLaunchKernelGGL(k_traces_init, dim3(1), dim3(64), 0, s, temp);
+}
+
+void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
+                   const double* val, const double* sq, const double* sqlo, double* temp, double* out,
+                   const int32_t* done, hipStream_t s, const TraceTail& tail) {
+    hipLaunchKernelGGL(k_traces, dim3(kTrBlocks), dim3(256), 0, s, nslot, cap, b, n, brow, bcol, val, sq, sqlo, temp,
+                       out, done, tail);
 }
 
 __global__ void k_ctl_upload(const Sp2Ctl* __restrict__ src, Sp2Ctl* __restrict__ ctl) {
@@ -113,13 +213,6 @@ __global__ void k_ctl_upload(const Sp2Ctl* __restrict__ src, Sp2Ctl* __restrict_
 
 void launch_ctl_upload(const Sp2Ctl* src, Sp2Ctl* ctl, hipStream_t s) {
     hipLaunchKernelGGL(k_ctl_upload, dim3(1), dim3(64), 0, s, src, ctl);
-}
-
-void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
-                        const int32_t* ovf_sweep, const int32_t* nslot_cur, sp2_iter_log* logs, int max_records,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_sp2_control, dim3(1), dim3(64), 0, s, ctl, tr, msc, ts, ovf_mul, ovf_sweep, nslot_cur, logs,
-                       max_records);
 }
 
 }  // namespace spamm

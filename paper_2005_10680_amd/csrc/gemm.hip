@@ -1114,8 +1114,9 @@ __global__ void k_reset_counters(int32_t* c) {
     if (threadIdx.x < 16) c[threadIdx.x] = 0;
 }
 
-void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_end) {
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, g.counters);
+void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_end,
+                     bool counters_clear) {
+    if (!counters_clear) hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, g.counters);
     if (ev_start) (void)hipEventRecord(ev_start, s);
     const int per_cu = g.b == 128 ? 2 : 4;
     int grid = num_cu * per_cu;

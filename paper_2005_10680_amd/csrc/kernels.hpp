@@ -28,10 +28,6 @@ void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow,
 void launch_norms_listed(int b, const int32_t* list, const int32_t* nlist, int64_t cap, const int32_t* brow,
                          const double* val, double* sq, double* sqlo, double* nrm, hipStream_t s,
                          const int32_t* done = nullptr);
-size_t traces_temp_bytes();
-void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
-                   const double* val, const double* sq, const double* sqlo, double* temp, double* out,
-                   const int32_t* done, hipStream_t s);
 
 // Rotation of row k of an FP32 copy (the ring kernel's layout): element m of
 // row k (index k of the column-major block's columns) at position
@@ -100,6 +96,28 @@ void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t
                  const uint8_t* fromc, int nb, const int32_t* mapX, const double* valX, double* valH,
                  const int32_t* branch, const int32_t* done, hipStream_t s, NormOut no = NormOut(),
                  float* out32 = nullptr);
+
+// Small systems: the occupancy, sweep-list, kept-pair and output-pattern
+// passes of one step, each in a single workgroup (same results, fewer
+// dependent launches).  Used for nb <= kSmallNb while small_path_enabled().
+constexpr int kSmallNb = 64;
+constexpr int kSmallPP = kSmallNb * kSmallNb;  // output positions of the pair pass
+constexpr int kSmallTiles = 16;                // level-l0 tiles per side of the sweep
+bool small_path_enabled();
+void set_small_path(bool on);
+// bits (nb x nw words) and tiles (T x T) of X as k_occupancy with kOccA; with
+// cube_keys also the sweep's cube list of X X^T and its length in *ncubes
+void launch_occ_small(const MatView& X, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0, uint32_t* cube_keys,
+                      int64_t* ncubes, const int32_t* done, hipStream_t s);
+// kept pairs, output list, output pattern of C and its slots, sc[0..3] as the
+// device-wide passes, and counters[0..15] = 0
+void launch_pairs_small(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
+                        const double* normA, const int32_t* mapB, const double* normB, int btrans, int sym,
+                        const double* tau, const double* sigma, double norm_min, int64_t cap_pairs, int64_t cap_out,
+                        int32_t* oi, int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int64_t* sc,
+                        int64_t capC, int32_t* mapC, int32_t* browC, int32_t* bcolC, int32_t* nslotC,
+                        uint8_t* fromc, const int32_t* mapX, const int32_t* branch, int32_t* counters, int32_t* ovf,
+                        const int32_t* done, hipStream_t s);
 
 // cse.hip
 size_t cse_cube_cap(int nb);
@@ -180,8 +198,10 @@ struct GemmArgs {
     float* out32 = nullptr;
 };
 // ev_start/ev_end (optional) are recorded right around the product kernel.
+// counters_clear: the work counters g.counters[0..15] are already zero (the
+// small-system pair pass clears them), so the reset launch is skipped
 void launch_gemm_f64(const GemmArgs& g, int num_cu, hipStream_t s, hipEvent_t ev_start = nullptr,
-                     hipEvent_t ev_end = nullptr);
+                     hipEvent_t ev_end = nullptr, bool counters_clear = false);
 // workgroups per CU of the ring kernels' persistent grid, by leaf size
 int get_ring_per_cu(int b);
 void set_ring_per_cu(int b, int per_cu);
@@ -235,12 +255,30 @@ struct Sp2HostStatus {
 };
 // *ctl = *src, src in host-mapped memory
 void launch_ctl_upload(const Sp2Ctl* src, Sp2Ctl* ctl, hipStream_t s);
-void launch_host_status(const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
-                        const int32_t* ovf_sweep, const Sp2Ctl* ctl, const int32_t* nslot, Sp2HostStatus* out,
-                        hipStream_t s);
-void launch_sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts, const int32_t* ovf_mul,
-                        const int32_t* ovf_sweep, const int32_t* nslot_cur, ::sp2_iter_log* logs, int max_records,
-                        hipStream_t s);
+// What runs after the traces of the current iterate, in the traces launch
+// itself (by its last workgroup): the device control step (ctl set: graph
+// loop) or the host-status gather (hs set: host loop), reading the previous
+// step's results msc / ts / overflow flags.
+struct TraceTail {
+    Sp2Ctl* ctl = nullptr;             // control step on this block
+    Sp2HostStatus* hs = nullptr;       // host-status gather into this record
+    const Sp2Ctl* ctl_read = nullptr;  // hs: the control block it copies
+    const int64_t* msc = nullptr;
+    const int64_t* ts = nullptr;
+    const int32_t* ovf_mul = nullptr;
+    const int32_t* ovf_sweep = nullptr;
+    ::sp2_iter_log* logs = nullptr;
+    int max_records = 0;
+};
+// Traces t1 = tr(X) (rows below n) and t2 = ||X||_F^2 in double-double into
+// out[4] (t1 hi, lo, t2 hi, lo), then the tail.  temp: traces_temp_bytes(),
+// its completion counter cleared once by launch_traces_init before the first
+// launch (every launch leaves it cleared).
+size_t traces_temp_bytes();
+void launch_traces_init(double* temp, hipStream_t s);
+void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
+                   const double* val, const double* sq, const double* sqlo, double* temp, double* out,
+                   const int32_t* done, hipStream_t s, const TraceTail& tail = TraceTail());
 
 // reblock.hip: Y (leaf Y.b, same n) from X; flag/pos [P^2] with P the power
 // of two >= Y.nb, total: device int64, ovf: set when Y.cap is too small
@@ -249,6 +287,9 @@ void launch_reblock(const MatView& X, const MatView& Y, int32_t* flag, int32_t* 
 
 // trunc.hip
 size_t trunc_temp_bytes(int64_t cap);
+// iterates of at most this many slots are truncated by one workgroup (the
+// candidate keys in LDS) while small_path_enabled()
+constexpr int64_t kTruncSmallCap = 4096;
 struct TruncNoallocScratch {
     void* temp;      // truncation temporaries for up to trunc_noalloc_max_cap() slots
     int64_t* stats;  // [4]

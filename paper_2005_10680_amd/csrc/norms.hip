@@ -245,82 +245,4 @@ void launch_norms_listed(int b, const int32_t* list, const int32_t* nlist, int64
     }
 }
 
-// ---------------------------------------------------------------------------
-// Traces: t1 = sum of diagonal entries (rows < n), t2 = sum over slots of
-// (sq + sqlo) = ||X||_F^2, both in double-double, fixed reduction order.
-// ---------------------------------------------------------------------------
-constexpr int kTrBlocks = 120;
-
-__global__ __launch_bounds__(256) void k_traces_part(const int32_t* __restrict__ nslot_p, int64_t cap, int b,
-                                                    int64_t n, const int32_t* __restrict__ brow,
-                                                    const int32_t* __restrict__ bcol, const double* __restrict__ val,
-                                                    const double* __restrict__ sq, const double* __restrict__ sqlo,
-                                                    double* __restrict__ part /* [kTrBlocks][4] */,
-                                                    const int32_t* __restrict__ done) {
-    __shared__ double sh[4][4];
-    if (done && *done) return;
-    int64_t nslot = *nslot_p;
-    if (nslot > cap) nslot = cap;
-    dd d1 = {0, 0}, d2 = {0, 0};
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslot; s += (int64_t)gridDim.x * blockDim.x) {
-        int r = brow[s];
-        if (r < 0) continue;
-        d2 = dd_add(d2, dd{sq[s], 0.0});
-        d2 = dd_add(d2, dd{sqlo[s], 0.0});
-        if (r == bcol[s]) {
-            // diagonal entries t < cnt (rows below n), added in ascending t;
-            // sixteen loads in flight before their additions
-            const double* v = val + (size_t)s * b * b;
-            const int64_t rem = n - (int64_t)r * b;
-            const int cnt = rem < (int64_t)b ? (int)rem : b;
-            for (int t0 = 0; t0 < cnt; t0 += 16) {
-                double x[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) x[u] = t0 + u < cnt ? v[(size_t)(t0 + u) * b + t0 + u] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    if (t0 + u < cnt) d1 = dd_add(d1, dd{x[u], 0.0});
-            }
-        }
-    }
-    d1 = dd_wave_sum(d1);
-    d2 = dd_wave_sum(d2);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-        sh[w][0] = d1.hi; sh[w][1] = d1.lo; sh[w][2] = d2.hi; sh[w][3] = d2.lo;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        dd a = {0, 0}, c = {0, 0};
-        for (int q = 0; q < 4; ++q) {
-            a = dd_add(a, dd{sh[q][0], sh[q][1]});
-            c = dd_add(c, dd{sh[q][2], sh[q][3]});
-        }
-        part[blockIdx.x * 4 + 0] = a.hi; part[blockIdx.x * 4 + 1] = a.lo;
-        part[blockIdx.x * 4 + 2] = c.hi; part[blockIdx.x * 4 + 3] = c.lo;
-    }
-}
-
-__global__ void k_traces_final(const double* __restrict__ part, double* __restrict__ out /* t1hi,t1lo,t2hi,t2lo */,
-                               const int32_t* __restrict__ done) {
-    if (done && *done) return;
-    if (threadIdx.x != 0) return;
-    dd a = {0, 0}, c = {0, 0};
-    for (int q = 0; q < kTrBlocks; ++q) {
-        a = dd_add(a, dd{part[q * 4 + 0], part[q * 4 + 1]});
-        c = dd_add(c, dd{part[q * 4 + 2], part[q * 4 + 3]});
-    }
-    out[0] = a.hi; out[1] = a.lo; out[2] = c.hi; out[3] = c.lo;
-}
-
-size_t traces_temp_bytes() { return sizeof(double) * 4 * kTrBlocks; }
-
-void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
-                   const double* val, const double* sq, const double* sqlo, double* temp, double* out,
-                   const int32_t* done, hipStream_t s) {
-    hipLaunchKernelGGL(k_traces_part, dim3(kTrBlocks), dim3(256), 0, s, nslot, cap, b, n, brow, bcol, val, sq, sqlo,
-                       temp, done);
-    hipLaunchKernelGGL(k_traces_final, dim3(1), dim3(64), 0, s, temp, out, done);
-}
-
 }  // namespace spamm

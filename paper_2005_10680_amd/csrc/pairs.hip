@@ -284,4 +284,240 @@ void launch_rest(int b, const int32_t* nslot_hat, int64_t cap_hat, const int32_t
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small systems (nb <= kSmallNb): the passes above, each chain of launches
+// in one workgroup.  Same lists in the same order (exclusive scans in 2D
+// Morton order of the outputs, ascending k inside an output), so the
+// products, their norms and every later decision are bit-identical to the
+// device-wide passes; only the number of dependent launches per step
+// changes.
+// ---------------------------------------------------------------------------
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallPer = kSmallPP / kSmallThreads;
+static_assert(kSmallPP % kSmallThreads == 0, "whole items per thread");
+
+// Occupancy of a symmetric-pattern X (row bitmaps and level-l0 tiles, as
+// k_occupancy with kOccA) built in LDS; then, with cube_keys given, the
+// non-empty cubes of the sweep of X X^T (k_cube_flags, the scan and
+// k_cube_list with A = B = X) in ascending 3D Morton order.
+__global__ __launch_bounds__(kSmallThreads) void k_occ_small(MatView X, uint32_t* __restrict__ bits, int nw,
+                                                             uint8_t* __restrict__ tiles, int T, int l0,
+                                                             uint32_t* __restrict__ cube_keys,
+                                                             int64_t* __restrict__ ncubes,
+                                                             const int32_t* __restrict__ done) {
+    __shared__ uint32_t s_bits[kSmallNb * ((kSmallNb + 31) / 32)];
+    __shared__ uint8_t s_tiles[kSmallTiles * kSmallTiles];
+    __shared__ int64_t s_wave[kSmallThreads / 64];
+    if (done && *done) return;
+    const int tid = threadIdx.x;
+    const int nwords = X.nb * nw;
+    for (int t = tid; t < nwords; t += kSmallThreads) s_bits[t] = 0u;
+    for (int t = tid; t < T * T; t += kSmallThreads) s_tiles[t] = 0;
+    __syncthreads();
+    int64_t nslot = *X.nslot;
+    if (nslot > X.cap) nslot = X.cap;
+    for (int64_t s = tid; s < nslot; s += kSmallThreads) {
+        const int r = X.brow[s];
+        if (r < 0) continue;
+        const int c = X.bcol[s];
+        if (r >= X.nb || c < 0 || c >= X.nb) continue;
+        atomicOr(&s_bits[r * nw + (c >> 5)], 1u << (c & 31));
+        s_tiles[(r >> l0) * T + (c >> l0)] = 1;
+    }
+    __syncthreads();
+    for (int t = tid; t < nwords; t += kSmallThreads) bits[t] = s_bits[t];
+    for (int t = tid; t < T * T; t += kSmallThreads) tiles[t] = s_tiles[t];
+    if (!cube_keys) return;
+    // cubes: thread tid owns the kCubesPer consecutive Morton codes from tid * kCubesPer
+    constexpr int kCubesPer = kSmallTiles * kSmallTiles * kSmallTiles / kSmallThreads;
+    const int TTT = T * T * T;
+    const int z0 = tid * kCubesPer;
+    int f[kCubesPer];
+    int nf = 0;
+#pragma unroll
+    for (int u = 0; u < kCubesPer; ++u) {
+        f[u] = 0;
+        if (z0 + u < TTT) {
+            uint32_t I, K, J;
+            demorton3((uint32_t)(z0 + u), I, K, J);
+            f[u] = (s_tiles[I * T + K] && s_tiles[K * T + J]) ? 1 : 0;
+        }
+        nf += f[u];
+    }
+    int64_t tot = 0;
+    int64_t pos = block_inclusive_scan<kSmallThreads>(nf, s_wave, tot) - nf;
+#pragma unroll
+    for (int u = 0; u < kCubesPer; ++u)
+        if (f[u]) cube_keys[pos++] = (uint32_t)(z0 + u);
+    if (tid == 0) *ncubes = tot;
+}
+
+void launch_occ_small(const MatView& X, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0, uint32_t* cube_keys,
+                      int64_t* ncubes, const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_occ_small, dim3(1), dim3(kSmallThreads), 0, s, X, bits, nw, tiles, T, l0, cube_keys, ncubes,
+                       done);
+}
+
+// k_kept_count, the scans of the counts, the output flags and the low-tier
+// counts, k_kept_fill, k_hat_flags, the scan of the output pattern and
+// k_hat_assign for P * P <= kSmallPP outputs; also clears the product's 16
+// work counters (the product launch then skips its own reset).
+__global__ __launch_bounds__(kSmallThreads) void k_pairs_small(
+    int nb, int P, int nw, const uint32_t* __restrict__ bitsA, const uint32_t* __restrict__ bitsB,
+    const int32_t* __restrict__ mapA, const double* __restrict__ normA, const int32_t* __restrict__ mapB,
+    const double* __restrict__ normB, int btrans, int sym, const double* __restrict__ tau_p,
+    const double* __restrict__ sigma_p, double norm_min, int64_t cap_pairs, int64_t cap_out, int32_t* __restrict__ oi,
+    int32_t* __restrict__ oj, int32_t* __restrict__ optr, int2* __restrict__ pairs, int32_t* __restrict__ olow,
+    int64_t* __restrict__ sc, int64_t capC, int32_t* __restrict__ mapC, int32_t* __restrict__ browC,
+    int32_t* __restrict__ bcolC, int32_t* __restrict__ nslotC, uint8_t* __restrict__ fromc,
+    const int32_t* __restrict__ mapX, const int32_t* __restrict__ branch_p, int32_t* __restrict__ counters,
+    int32_t* __restrict__ ovf, const int32_t* __restrict__ done) {
+    __shared__ int32_t s_cnt[kSmallPP];
+    __shared__ int64_t s_wave[kSmallThreads / 64];
+    if (done && *done) return;
+    const int tid = threadIdx.x;
+    if (tid < 16) counters[tid] = 0;
+    const double tau = *tau_p;
+    const double sigma = sigma_p ? *sigma_p : 0.0;
+    const int PP = P * P;
+    const int z0 = tid * kSmallPer;
+    int cl[kSmallPer];
+    int sum_c = 0, sum_f = 0, sum_l = 0;
+#pragma unroll
+    for (int u = 0; u < kSmallPer; ++u) {
+        const int z = z0 + u;
+        int c = 0;
+        cl[u] = 0;
+        if (z < PP) {
+            uint32_t i, j;
+            demorton2((uint32_t)z, i, j);
+            if ((int)i < nb && (int)j < nb && !(sym && i > j)) {
+                for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                              [&](int, int sa, int sb, double p) {
+                                  ++c;
+                                  if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) ++cl[u];
+                              });
+            }
+            s_cnt[z] = c;
+        }
+        sum_c += c;
+        sum_f += c > 0 ? 1 : 0;
+        sum_l += cl[u];
+    }
+    int64_t npairs = 0, nout = 0, nlow = 0;
+    const int64_t off0 = block_inclusive_scan<kSmallThreads>(sum_c, s_wave, npairs) - sum_c;
+    const int64_t oidx0 = block_inclusive_scan<kSmallThreads>(sum_f, s_wave, nout) - sum_f;
+    if (sigma_p) block_inclusive_scan<kSmallThreads>(sum_l, s_wave, nlow);
+    if (tid == 0) {
+        sc[0] = npairs;
+        sc[1] = nout;
+        sc[3] = sigma_p ? nlow : 0;
+        if (nout <= cap_out) optr[nout] = (int32_t)(npairs <= cap_pairs ? npairs : cap_pairs);
+        if (npairs > cap_pairs) atomicOr(ovf, kOvfPairs);
+        if (nout > cap_out) atomicOr(ovf, kOvfOut);
+    }
+    // kept pairs of each output: low tier first, then FP64, ascending k in each
+    if (npairs <= cap_pairs) {
+        int64_t w = off0, o = oidx0;
+#pragma unroll
+        for (int u = 0; u < kSmallPer; ++u) {
+            const int z = z0 + u;
+            if (z >= PP || s_cnt[z] == 0) continue;
+            uint32_t i, j;
+            demorton2((uint32_t)z, i, j);
+            if (o < cap_out) {
+                oi[o] = (int32_t)i;
+                oj[o] = (int32_t)j;
+                optr[o] = (int32_t)w;
+                const int64_t w0 = w;
+                if (sigma_p) {
+                    for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                                  [&](int, int sa, int sb, double p) {
+                                      if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) {
+                                          if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                                          ++w;
+                                      }
+                                  });
+                    if (olow) olow[o] = (int32_t)(w - w0);
+                    for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                                  [&](int, int sa, int sb, double p) {
+                                      if (!(p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min)) {
+                                          if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                                          ++w;
+                                      }
+                                  });
+                } else {
+                    for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                                  [&](int, int sa, int sb, double) {
+                                      if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                                      ++w;
+                                  });
+                }
+                w = w0 + s_cnt[z];
+            } else {
+                w += s_cnt[z];
+            }
+            ++o;
+        }
+    }
+    // output pattern (k_hat_flags) and its slots (k_hat_assign)
+    const int br = branch_p ? *branch_p : 0;
+    int hf[kSmallPer];
+    int sum_h = 0;
+#pragma unroll
+    for (int u = 0; u < kSmallPer; ++u) {
+        const int z = z0 + u;
+        hf[u] = 0;
+        if (z < PP) {
+            uint32_t r, c;
+            demorton2((uint32_t)z, r, c);
+            if ((int)r < nb && (int)c < nb) {
+                const uint32_t cz = sym ? morton2(min(r, c), max(r, c)) : (uint32_t)z;
+                hf[u] = s_cnt[cz] > 0;
+                if (!hf[u] && mapX && br == 1) hf[u] = mapX[(size_t)r * nb + c] >= 0;
+            }
+        }
+        sum_h += hf[u];
+    }
+    int64_t total = 0;
+    int64_t sl = block_inclusive_scan<kSmallThreads>(sum_h, s_wave, total) - sum_h;
+    if (tid == 0) {
+        sc[2] = total;
+        *nslotC = (int32_t)(total <= capC ? total : capC);
+        if (total > capC) atomicOr(ovf, kOvfSlots);
+    }
+#pragma unroll
+    for (int u = 0; u < kSmallPer; ++u) {
+        const int z = z0 + u;
+        if (z >= PP) continue;
+        uint32_t r, c;
+        demorton2((uint32_t)z, r, c);
+        if ((int)r >= nb || (int)c >= nb) continue;
+        int32_t m = -1;
+        if (hf[u]) {
+            if (sl < capC) {
+                m = (int32_t)sl;
+                browC[sl] = (int32_t)r;
+                bcolC[sl] = (int32_t)c;
+                const uint32_t cz = sym ? morton2(min(r, c), max(r, c)) : (uint32_t)z;
+                if (fromc) fromc[sl] = s_cnt[cz] > 0 ? 1 : 0;
+            }
+            ++sl;
+        }
+        mapC[(size_t)r * nb + c] = m;
+    }
+}
+
+void launch_pairs_small(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
+                        const double* normA, const int32_t* mapB, const double* normB, int btrans, int sym,
+                        const double* tau, const double* sigma, double norm_min, int64_t cap_pairs, int64_t cap_out,
+                        int32_t* oi, int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int64_t* sc,
+                        int64_t capC, int32_t* mapC, int32_t* browC, int32_t* bcolC, int32_t* nslotC,
+                        uint8_t* fromc, const int32_t* mapX, const int32_t* branch, int32_t* counters, int32_t* ovf,
+                        const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_pairs_small, dim3(1), dim3(kSmallThreads), 0, s, nb, P, nw, bitsA, bitsB, mapA, normA, mapB,
+                       normB, btrans, sym, tau, sigma, norm_min, cap_pairs, cap_out, oi, oj, optr, pairs, olow, sc,
+                       capC, mapC, browC, bcolC, nslotC, fromc, mapX, branch, counters, ovf, done);
+}
+
 }  // namespace spamm

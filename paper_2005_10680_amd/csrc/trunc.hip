@@ -198,6 +198,112 @@ __global__ void k_trunc_reset(TruncTemp t, int64_t* stats, const int32_t* __rest
     }
 }
 
+// Small iterates (at most kTruncSmallCap slots): k_trunc_reset, k_trunc_keys,
+// k_trunc_select and k_trunc_mark in one workgroup with the candidate keys in
+// LDS (a candidate's k is its key >> 22).  Same quanta, keys and radix
+// select, so the removed set and the statistics are the same.
+__global__ __launch_bounds__(1024) void k_trunc_small(MatView X, const double* __restrict__ delta_dev,
+                                                     double delta_host, double scale, int64_t* __restrict__ stats,
+                                                     const int32_t* __restrict__ done) {
+    __shared__ uint64_t s_key[kTruncSmallCap];
+    __shared__ unsigned long long hs[256];
+    __shared__ unsigned long long s_st[3];
+    __shared__ uint64_t s_prefix, s_rem, s_thr;
+    __shared__ int s_fin, s_n;
+    if (done && *done) return;
+    const int tid = threadIdx.x;
+    const double delta = (delta_dev ? *delta_dev : delta_host) * scale;
+    const TruncQuanta q = trunc_quanta(delta);
+    if (tid == 0) {
+        s_n = 0;
+        s_st[0] = s_st[1] = s_st[2] = 0ull;
+        s_prefix = 0;
+        s_rem = q.kt;
+        s_thr = 0;
+        s_fin = q.any ? 0 : 1;
+    }
+    __syncthreads();
+    int64_t nslot = *X.nslot;
+    if (nslot > X.cap) nslot = X.cap;
+    if (q.any) {
+        for (int64_t s = tid; s < nslot; s += blockDim.x) {
+            const int r = X.brow[s];
+            if (r < 0) continue;
+            const int c = X.bcol[s];
+            if (r > c) continue;
+            const double w = (r == c) ? 1.0 : 2.0;
+            const double v = w * X.sq[s];
+            const double sc = v / q.Q;
+            const uint64_t k = sc < (double)kKSat ? (uint64_t)ceil(sc) : kKSat;
+            if (k < q.kt) s_key[atomicAdd(&s_n, 1)] = (k << 22) | ((uint64_t)r * (uint64_t)X.nb + (uint64_t)c);
+        }
+    }
+    __syncthreads();
+    const int n = s_n;
+    for (int d = 0; d < 8; ++d) {
+        if (s_fin) break;
+        const int shift = 56 - 8 * d;
+        const uint64_t mask_hi = d == 0 ? 0ull : ~((1ull << (shift + 8)) - 1ull);
+        for (int b = tid; b < 256; b += blockDim.x) hs[b] = 0ull;
+        __syncthreads();
+        const uint64_t pre = s_prefix;
+        for (int c = tid; c < n; c += blockDim.x) {
+            const uint64_t key = s_key[c];
+            if ((key & mask_hi) == (pre & mask_hi)) atomicAdd(&hs[(key >> shift) & 255u], key >> 22);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t cum = 0;
+            int found = -1;
+            for (int b = 0; b < 256; ++b) {
+                if (cum + hs[b] >= s_rem) {
+                    found = b;
+                    break;
+                }
+                cum += hs[b];
+            }
+            if (found < 0) {
+                s_thr = d == 0 ? ~0ull : ((pre | ((1ull << (shift + 8)) - 1ull)) + 1ull);
+                s_fin = 1;
+            } else {
+                s_prefix = pre | ((uint64_t)found << shift);
+                s_rem = s_rem - cum;
+                if (d == 7) {
+                    s_thr = s_prefix;
+                    s_fin = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const uint64_t thr = q.any ? s_thr : 0ull;
+    const int nb = X.nb;
+    for (int c = tid; c < n; c += blockDim.x) {
+        const uint64_t key = s_key[c];
+        if (key >= thr) continue;
+        const uint64_t ukey = key & ((1ull << 22) - 1ull);
+        const int r = (int)(ukey / (uint64_t)nb), cc = (int)(ukey % (uint64_t)nb);
+        const int s1 = X.map[(size_t)r * nb + cc];
+        const int s2 = X.map[(size_t)cc * nb + r];
+        if (s1 >= 0) X.brow[s1] = -1;
+        if (s2 >= 0) X.brow[s2] = -1;
+        const int nrem = (s1 >= 0 ? 1 : 0) + (s2 >= 0 && s2 != s1 ? 1 : 0);
+        X.map[(size_t)r * nb + cc] = -1;
+        X.map[(size_t)cc * nb + r] = -1;
+        if (stats) {
+            atomicAdd(&s_st[0], 1ull);
+            atomicAdd(&s_st[1], (unsigned long long)(key >> 22));
+            atomicAdd(&s_st[2], (unsigned long long)nrem);
+        }
+    }
+    __syncthreads();
+    if (stats && tid == 0) {
+        stats[0] = (int64_t)s_st[0];
+        stats[1] = (int64_t)s_st[1];
+        stats[2] = (int64_t)s_st[2];
+    }
+}
+
 // Scratch of the allocation-free truncation (spamm_truncate_noalloc): the
 // candidate keys of up to kTruncNoallocMaxCap slots, then the removal
 // statistics and the overflow word.  One copy per GPU, held until the process
@@ -237,6 +343,11 @@ hipError_t trunc_noalloc_scratch(TruncNoallocScratch* out) {
 
 void launch_truncate(const MatView& X, const double* delta_dev, double delta_host, double delta_scale, void* temp,
                      int64_t cap, int64_t* stats, int32_t* ovf, const int32_t* done, hipStream_t s) {
+    if (X.cap <= kTruncSmallCap && small_path_enabled()) {
+        hipLaunchKernelGGL(k_trunc_small, dim3(1), dim3(1024), 0, s, X, delta_dev, delta_host, delta_scale, stats,
+                           done);
+        return;
+    }
     TruncTemp t = carve_trunc(temp, cap);
     hipLaunchKernelGGL(k_trunc_reset, dim3(1), dim3(64), 0, s, t, stats, done);
     hipLaunchKernelGGL(k_trunc_keys, dim3(grid_for(X.cap, 256, 4096)), dim3(256), 0, s, X, delta_dev, delta_host,

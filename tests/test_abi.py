@@ -90,6 +90,13 @@ def test_schedule_queries_and_checks(lib):
     assert lib.spamm_get_gemm_schedule(48) < 0              # no such leaf size
     assert lib.spamm_set_gemm_schedule(64, 0) == 0          # 0: back to the default
     assert lib.spamm_get_gemm_schedule(64) == defaults[64]
+    lib.spamm_set_small_path.restype = ctypes.c_int
+    lib.spamm_set_small_path.argtypes = [ctypes.c_int32]
+    lib.spamm_get_small_path.restype = ctypes.c_int
+    assert lib.spamm_get_small_path() == 1                  # on by default
+    assert lib.spamm_set_small_path(2) < 0
+    assert lib.spamm_set_small_path(0) == 0 and lib.spamm_get_small_path() == 0
+    assert lib.spamm_set_small_path(1) == 0 and lib.spamm_get_small_path() == 1
 
 
 class Bsm(ctypes.Structure):
