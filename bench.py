@@ -687,7 +687,7 @@ def chain_leg(P, torch, synth, reps=20):
     spec = load_spectrum("chain1d_n1024_s1_b32")
     Fh = synth.chain1d(1024, 1, 32)
     F = P.BlockSparse.from_host(Fh)
-    taus = synth.tau_paper()
+    taus = torch.as_tensor(synth.tau_paper(), dtype=torch.float64, device=F.device)  # resident, like F
     kw = dict(homo=spec["homo"], lumo=spec["lumo"])
     host = lambda: P.purify(F, 512, 1e-6, taus, **kw)
     graph = lambda: P.purify(F, 512, 1e-6, taus, graph_steps=8, **kw)

@@ -59,6 +59,48 @@ int num_cus() {
     return cached;
 }
 
+// The stream a purification captures its graph on: one per host thread and
+// device, created on first use and kept until the process ends (creating
+// and destroying one per call costs about as much as a small system's
+// whole loop).  Calls on one thread run one after another, so they never
+// share it at the same time.
+hipError_t capture_stream(hipStream_t* out) {
+    constexpr int kMaxDev = 64;
+    thread_local hipStream_t streams[kMaxDev] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    *out = streams[dev];
+    return hipSuccess;
+}
+
+// Graph, executable graph and event of one device-driven loop; a capture
+// left open by an early return is ended first, so the kept stream stays
+// usable.
+struct GraphGuard {
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipEvent_t e = nullptr;
+    ~GraphGuard() {
+        if (cs) {
+            hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(cs, &st) == hipSuccess && st != hipStreamCaptureStatusNone) {
+                hipGraph_t open = nullptr;
+                if (hipStreamEndCapture(cs, &open) == hipSuccess && open) (void)hipGraphDestroy(open);
+            }
+        }
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
 // Pair lists use 32-bit offsets: a capacity derived from the workspace is
 // capped below 2^31, so that a longer list reports SPAMM_ECAPACITY.
 int64_t clamp_pairs(int64_t max_pairs) {
@@ -475,15 +517,8 @@ void carve_mat(Carver& c, int64_t n, int b, int64_t cap, spamm_bsm& m) {
 
 // dst = src (pattern, values, norms); both with capacity cap
 int copy_mat(const spamm_bsm& dst, const spamm_bsm& src, int64_t cap, hipStream_t s) {
-    const int nb = src.nb, b = src.b;
-    HIP_TRY(hipMemcpyAsync(dst.nslot, src.nslot, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dst.brow, src.brow, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dst.bcol, src.bcol, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dst.map, src.map, sizeof(int32_t) * nb * nb, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dst.val, src.val, sizeof(double) * cap * b * b, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dst.norm, src.norm, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dst.sq, src.sq, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(dst.sqlo, src.sqlo, sizeof(double) * cap, hipMemcpyDeviceToDevice, s));
+    launch_copy_live(view(&src), view(&dst), cap, s);
+    HIP_TRY(hipGetLastError());
     return SPAMM_OK;
 }
 
@@ -981,16 +1016,6 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     Sp2Ws w;
     carve_sp2(c, nb, b, p->N, cap, max_pairs, tape_steps, w, p->precision);
     if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
-    int64_t nf = 0;
-    {
-        int32_t t = 0;
-        HIP_TRY(hipMemcpyAsync(&t, F->nslot, sizeof(t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        nf = t;
-    }
-    if (nf + nb > cap && cap < (int64_t)nb * nb)
-        return fail(SPAMM_ECAPACITY, "D->cap must be at least min(nslot(F) + nb, nb^2)");
-
     hipEvent_t ev[8];
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     struct EvGuard {
@@ -1007,15 +1032,20 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     fill_i64(w.tstats, 4, 0, s);  // stays 0 when no step truncates (Algorithm 4)
     launch_traces_init(w.trace_tmp, s);
 
-    // X_0 and its first truncation
+    // X_0 and its first truncation: the spectral bounds and the slot count
+    // of F in one read-back, then the capacity check before X_0 is written
     MatView Fv = view(F);
     MatView X0 = view(&w.X[0]);
     launch_gersch(Fv, w.rowtmp, w.lam, s);
+    double lam[2];
+    int32_t nf = 0;
+    HIP_TRY(hipMemcpyAsync(lam, w.lam, sizeof(lam), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&nf, F->nslot, sizeof(nf), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if ((int64_t)nf + nb > cap && cap < (int64_t)nb * nb)
+        return fail(SPAMM_ECAPACITY, "D->cap must be at least min(nslot(F) + nb, nb^2)");
     launch_x0(Fv, w.lam, X0, w.dflag, w.dpos, w.mw.scan_tmp, w.dcount, s);
     launch_norms(b, X0.nslot, X0.cap, X0.brow, X0.val, X0.sq, X0.sqlo, X0.norm, s);
-    double lam[2];
-    HIP_TRY(hipMemcpyAsync(lam, w.lam, sizeof(lam), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
     const double W = lam[1] - lam[0];
     double xh = have_gap ? (lam[1] - p->homo) / W : NAN;
     double xl = have_gap ? (lam[1] - p->lumo) / W : NAN;
@@ -1126,17 +1156,8 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
         hc.trunc_scale = tb_scale;
         HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
         (void)num_cus();  // device properties are read once, outside the capture
-        struct GraphGuard {
-            hipStream_t cs = nullptr;
-            hipGraph_t g = nullptr;
-            hipGraphExec_t ge = nullptr;
-            ~GraphGuard() {
-                if (ge) (void)hipGraphExecDestroy(ge);
-                if (g) (void)hipGraphDestroy(g);
-                if (cs) (void)hipStreamDestroy(cs);
-            }
-        } gg;
-        HIP_TRY(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+        GraphGuard gg;
+        HIP_TRY(capture_stream(&gg.cs));
         HIP_TRY(hipEventRecord(ev[6], s));
         HIP_TRY(hipStreamWaitEvent(gg.cs, ev[6], 0));
         HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));
@@ -1705,20 +1726,9 @@ int purify_sp2_batched(int32_t nsys, const spamm_bsm* F, const sp2_params* p, sp
     HIP_TRY(hipMemcpyAsync(descs_dev, hd.data(), sizeof(GemmArgs) * hd.size(), hipMemcpyHostToDevice, s));
     (void)num_cus();
 
-    struct GraphGuard {
-        hipStream_t cs = nullptr;
-        hipGraph_t g = nullptr;
-        hipGraphExec_t ge = nullptr;
-        hipEvent_t e = nullptr;
-        ~GraphGuard() {
-            if (ge) (void)hipGraphExecDestroy(ge);
-            if (g) (void)hipGraphDestroy(g);
-            if (cs) (void)hipStreamDestroy(cs);
-            if (e) (void)hipEventDestroy(e);
-        }
-    } gg;
+    GraphGuard gg;
     HIP_TRY(hipEventCreate(&gg.e));
-    HIP_TRY(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking));
+    HIP_TRY(capture_stream(&gg.cs));
     HIP_TRY(hipEventRecord(gg.e, s));
     HIP_TRY(hipStreamWaitEvent(gg.cs, gg.e, 0));
     HIP_TRY(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal));

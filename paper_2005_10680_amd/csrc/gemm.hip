@@ -938,6 +938,9 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
     if (g.ovf && *g.ovf) return;
     const int tid = threadIdx.x;
     const int64_t nout = *g.nout;
+    // a grid larger than the output list: the first max(nout, 8) workgroups
+    // (every XCD keeps one) claim every output, the rest leave at once
+    if ((int64_t)blockIdx.x >= nout && blockIdx.x >= 8) return;
     const int xcd = blockIdx.x % 8;
     if (tid < 9) {
         const int64_t np = g.optr[nout];
@@ -1014,6 +1017,7 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
     __shared__ int s_o, s_cut[9];
     const int tid = threadIdx.x;
     const int64_t nout = out_off[nsys];
+    if ((int64_t)blockIdx.x >= nout && blockIdx.x >= 8) return;  // as in k_gemm_ring
     const int xcd = blockIdx.x % 8;
     auto sys_of = [&](int64_t o) -> int {
         int a = 0, z = nsys - 1;  // last s with out_off[s] <= o

@@ -24,6 +24,9 @@ struct MatView {
 // norms.hip
 void launch_norms(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, double* sq,
                   double* sqlo, double* nrm, hipStream_t s, const int32_t* done = nullptr);
+// dst <- src (slot count, block map, the live slots s < min(nslot, cap));
+// dst holds at least cap slots
+void launch_copy_live(const MatView& src, const MatView& dst, int64_t cap, hipStream_t s);
 // norms of the *nlist slots in list (the blocks a producer could not certify)
 void launch_norms_listed(int b, const int32_t* list, const int32_t* nlist, int64_t cap, const int32_t* brow,
                          const double* val, double* sq, double* sqlo, double* nrm, hipStream_t s,

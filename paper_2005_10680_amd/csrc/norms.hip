@@ -11,6 +11,8 @@
 // accumulator by one lane.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -243,6 +245,33 @@ void launch_norms_listed(int b, const int32_t* list, const int32_t* nlist, int64
         case 64: hipLaunchKernelGGL(k_norms<64>, dim3(grid), dim3(256), 0, s, ns, cap, brow, val, sq, sqlo, nrm, done, list, nlist); break;
         case 128: hipLaunchKernelGGL(k_norms<128>, dim3(grid), dim3(256), 0, s, ns, cap, brow, val, sq, sqlo, nrm, done, list, nlist); break;
     }
+}
+
+// dst <- src: the slot count, the whole block map and the live slots
+// (s < min(*src.nslot, cap)) with their values and norms, in one launch.
+__global__ void k_copy_live(MatView src, MatView dst, int64_t cap) {
+    int64_t ns = *src.nslot;
+    if (ns > cap) ns = cap;
+    if (ns < 0) ns = 0;
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gs = (int64_t)gridDim.x * blockDim.x;
+    if (gt == 0) *dst.nslot = *src.nslot;
+    const int64_t nmap = (int64_t)src.nb * src.nb;
+    for (int64_t t = gt; t < nmap; t += gs) dst.map[t] = src.map[t];
+    for (int64_t t = gt; t < ns; t += gs) {
+        dst.brow[t] = src.brow[t];
+        dst.bcol[t] = src.bcol[t];
+        dst.norm[t] = src.norm[t];
+        dst.sq[t] = src.sq[t];
+        dst.sqlo[t] = src.sqlo[t];
+    }
+    const int64_t nv = ns * src.b * src.b;
+    for (int64_t t = gt; t < nv; t += gs) dst.val[t] = src.val[t];
+}
+
+void launch_copy_live(const MatView& src, const MatView& dst, int64_t cap, hipStream_t s) {
+    const int64_t items = std::max<int64_t>(cap * src.b * src.b, (int64_t)src.nb * src.nb);
+    hipLaunchKernelGGL(k_copy_live, dim3(grid_for(items, 256, 4096)), dim3(256), 0, s, src, dst, cap);
 }
 
 }  // namespace spamm

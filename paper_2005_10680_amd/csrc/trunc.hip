@@ -74,6 +74,42 @@ static TruncTemp carve_trunc(void* temp, int64_t cap) {
     return t;
 }
 
+// One radix-select decision, taken by the first wave (all 64 lanes): the
+// first digit b (0..255) whose bucket still fits no more, cum(b) + hs[b] >= rem
+// with cum(b) = hs[0] + ... + hs[b-1], or -1 when every bucket fits.  Lane l
+// owns buckets 4l .. 4l+3; a wave scan of the lane sums gives each lane its
+// starting cum.  Integer sums, so the answer is the sequential scan's.
+SPAMM_DEV int radix_bucket(const unsigned long long* hs, uint64_t rem, uint64_t& cum_out) {
+    const int lane = threadIdx.x & 63;
+    uint64_t h[4];
+    uint64_t local = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        h[j] = hs[4 * lane + j];
+        local += h[j];
+    }
+    uint64_t incl = local;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t o = __shfl_up(incl, d);
+        if (lane >= d) incl += o;
+    }
+    uint64_t c = incl - local;
+    int found = -1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (found < 0) {
+            if (c + h[j] >= rem) found = 4 * lane + j;
+            else c += h[j];
+        }
+    }
+    const uint64_t bal = __ballot(found >= 0);
+    if (bal == 0ull) return -1;
+    const int src = __ffsll((long long)bal) - 1;
+    cum_out = __shfl(c, src);
+    return __shfl(found, src);
+}
+
 __global__ void k_trunc_keys(MatView X, const double* __restrict__ delta_dev, double delta_host, double scale,
                              TruncTemp t, int64_t cap, const int32_t* __restrict__ done) {
     if (done && *done) return;
@@ -134,21 +170,14 @@ __global__ __launch_bounds__(1024) void k_trunc_select(const double* __restrict_
                 atomicAdd(&hs[(key >> shift) & 255u], (unsigned long long)t.k[c]);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x < 64) {
             uint64_t cum = 0;
-            int found = -1;
-            for (int b = 0; b < 256; ++b) {
-                if (cum + hs[b] >= s_rem) {
-                    found = b;
-                    break;
-                }
-                cum += hs[b];
-            }
-            if (found < 0) {
+            const int found = radix_bucket(hs, s_rem, cum);
+            if (threadIdx.x == 0 && found < 0) {
                 // every remaining unit in this range fits: remove the whole range
                 s_thr = d == 0 ? ~0ull : ((pre | ((1ull << (shift + 8)) - 1ull)) + 1ull);
                 s_fin = 1;
-            } else {
+            } else if (threadIdx.x == 0) {
                 s_prefix = pre | ((uint64_t)found << shift);
                 s_rem = s_rem - cum;
                 if (d == 7) {
@@ -252,20 +281,13 @@ __global__ __launch_bounds__(1024) void k_trunc_small(MatView X, const double* _
             if ((key & mask_hi) == (pre & mask_hi)) atomicAdd(&hs[(key >> shift) & 255u], key >> 22);
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid < 64) {
             uint64_t cum = 0;
-            int found = -1;
-            for (int b = 0; b < 256; ++b) {
-                if (cum + hs[b] >= s_rem) {
-                    found = b;
-                    break;
-                }
-                cum += hs[b];
-            }
-            if (found < 0) {
+            const int found = radix_bucket(hs, s_rem, cum);
+            if (tid == 0 && found < 0) {
                 s_thr = d == 0 ? ~0ull : ((pre | ((1ull << (shift + 8)) - 1ull)) + 1ull);
                 s_fin = 1;
-            } else {
+            } else if (threadIdx.x == 0) {
                 s_prefix = pre | ((uint64_t)found << shift);
                 s_rem = s_rem - cum;
                 if (d == 7) {
