@@ -302,9 +302,10 @@ struct MulWs {
     int2* pairs;
     int64_t* sc;  // [8]: npairs, nout, nslot_total
     int32_t* counters;
+    int32_t* cuts;  // [9] per-XCD output ranges, written by the small-system pair pass
     int32_t* ovf;
     void* scan_tmp;
-    bool counters_clear = false;  // the last pair pass cleared the product's work counters
+    bool counters_clear = false;  // the last pair pass cleared the work counters and wrote cuts
 };
 
 void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
@@ -330,6 +331,7 @@ void carve_mul(Carver& c, int nb, int64_t max_pairs, MulWs& w) {
     w.pairs = c.take<int2>(w.cap_pairs > 0 ? w.cap_pairs : 1);
     w.sc = c.take<int64_t>(8);
     w.counters = c.take<int32_t>(16);
+    w.cuts = c.take<int32_t>(16);
     w.ovf = c.take<int32_t>(4);
     w.scan_tmp = c.take<char>(scan_temp_bytes(w.PP));
 }
@@ -353,8 +355,8 @@ void run_pairs(const MatView& A, const MatView& B, int btrans, int sym, const do
     if (nb <= kSmallNb && small_path_enabled()) {
         launch_pairs_small(nb, w.P, w.nw, bA, bB, A.map, A.norm, B.map, B.norm, btrans, sym, tau_dev, sigma_dev,
                            norm_min, w.cap_pairs, w.cap_out, w.oi, w.oj, w.optr, w.pairs, sigma_dev ? w.olow : nullptr,
-                           w.sc, C.cap, C.map, C.brow, C.bcol, C.nslot, fromc, mapX, branch_dev, w.counters, w.ovf,
-                           done, s);
+                           w.sc, C.cap, C.map, C.brow, C.bcol, C.nslot, fromc, mapX, branch_dev, w.counters, w.cuts,
+                           w.ovf, done, s);
         w.counters_clear = true;
         return;
     }
@@ -430,6 +432,7 @@ int run_gemm(const MatView& A, const MatView& B, int btrans, int sym, const MatV
         if (!btrans || !valA32) return -1;
         g.out32 = out32;
     }
+    if (w.counters_clear) g.cuts = w.cuts;
     launch_gemm_f64(g, num_cus(), s, ev_start, ev_end, w.counters_clear);
     w.counters_clear = false;
     if (mapX)
@@ -1034,24 +1037,51 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
 
     // X_0 and its first truncation: the spectral bounds and the slot count
     // of F in one read-back, then the capacity check before X_0 is written
+    // (the device-driven loop reads nothing back: the control block, with the
+    // mapped gap and delta_0, is set up by a kernel from the bounds on the
+    // device; the host loop reads the bounds and keeps the gap on the host)
+    const double tb_scale = p->variant == 0 ? 0.5 : 1.0;
+    const bool device_loop = p->graph_steps > 0;
     MatView Fv = view(F);
     MatView X0 = view(&w.X[0]);
     launch_gersch(Fv, w.rowtmp, w.lam, s);
-    double lam[2];
+    double lam[2] = {0.0, 0.0};
     int32_t nf = 0;
-    HIP_TRY(hipMemcpyAsync(lam, w.lam, sizeof(lam), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&nf, F->nslot, sizeof(nf), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if ((int64_t)nf + nb > cap && cap < (int64_t)nb * nb)
+    const bool check_cap = cap < (int64_t)nb * nb;  // nb^2 slots always hold X_0
+    if (!device_loop) HIP_TRY(hipMemcpyAsync(lam, w.lam, sizeof(lam), hipMemcpyDeviceToHost, s));
+    if (check_cap) HIP_TRY(hipMemcpyAsync(&nf, F->nslot, sizeof(nf), hipMemcpyDeviceToHost, s));
+    if (!device_loop || check_cap) HIP_TRY(hipStreamSynchronize(s));
+    if (check_cap && (int64_t)nf + nb > cap)
         return fail(SPAMM_ECAPACITY, "D->cap must be at least min(nslot(F) + nb, nb^2)");
+    double xh = NAN, xl = NAN;
+    if (device_loop) {
+        hc.eps = p->eps;
+        hc.homo = p->homo;
+        hc.lumo = p->lumo;
+        hc.delta_const = p->delta_const;
+        hc.e_tol = p->e_tol;
+        hc.n_occ = p->n_occ;
+        hc.n_max = p->n_max;
+        hc.variant = p->variant;
+        hc.N = p->N;
+        hc.n_e = 0;
+        hc.done = 0;
+        hc.nlog = 0;
+        hc.status = SPAMM_OK;
+        hc.tiered = tiered ? 1 : 0;
+        hc.have_gap = have_gap ? 1 : 0;
+        hc.tier_split = p->tier_split;
+        hc.trunc_scale = tb_scale;
+        launch_sp2_init(hc, w.lam, w.ctl, s);
+    } else {
+        const double W = lam[1] - lam[0];
+        xh = have_gap ? (lam[1] - p->homo) / W : NAN;
+        xl = have_gap ? (lam[1] - p->lumo) / W : NAN;
+        hc.delta = step_delta(p, xh - xl);
+        HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+    }
     launch_x0(Fv, w.lam, X0, w.dflag, w.dpos, w.mw.scan_tmp, w.dcount, s);
     launch_norms(b, X0.nslot, X0.cap, X0.brow, X0.val, X0.sq, X0.sqlo, X0.norm, s);
-    const double W = lam[1] - lam[0];
-    double xh = have_gap ? (lam[1] - p->homo) / W : NAN;
-    double xl = have_gap ? (lam[1] - p->lumo) / W : NAN;
-    const double delta0 = step_delta(p, xh - xl);
-    hc.delta = delta0;
-    HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
     if (p->variant != 1) launch_truncate(X0, &w.ctl->delta, 0.0, 1.0, w.trunc_tmp, cap, w.tstats, w.mw.ovf, nullptr, s);
     const bool full_tape = every == 1;
     if (every >= 1) {
@@ -1060,7 +1090,6 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
         if (rcc) return rcc;
     }
 
-    const double tb_scale = p->variant == 0 ? 0.5 : 1.0;
     // One purification step on the device, X~_{i-1} (xv) -> X~_i (nv), with
     // every decision read from the control block: the threshold sweep (and
     // the low-precision limit), kept pairs and output pattern, the leaf
@@ -1134,27 +1163,8 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     int status = SPAMM_OK;
     if (p->graph_steps > 0) {
         // ---- device-driven loop: two steps (X0 -> X1 -> X0) captured once,
-        // replayed until the control kernel sets done ----
-        hc.eps = p->eps;
-        hc.homo = p->homo;
-        hc.lumo = p->lumo;
-        hc.delta_const = p->delta_const;
-        hc.e_tol = p->e_tol;
-        hc.n_occ = p->n_occ;
-        hc.n_max = p->n_max;
-        hc.variant = p->variant;
-        hc.N = p->N;
-        hc.xh = xh;
-        hc.xl = xl;
-        hc.n_e = 0;
-        hc.done = 0;
-        hc.nlog = 0;
-        hc.status = SPAMM_OK;
-        hc.tiered = tiered ? 1 : 0;
-        hc.have_gap = have_gap ? 1 : 0;
-        hc.tier_split = p->tier_split;
-        hc.trunc_scale = tb_scale;
-        HIP_TRY(hipMemcpyAsync(w.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s));
+        // replayed until the control kernel sets done (the control block was
+        // set up with X_0) ----
         (void)num_cus();  // device properties are read once, outside the capture
         GraphGuard gg;
         HIP_TRY(capture_stream(&gg.cs));

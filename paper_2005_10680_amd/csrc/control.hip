@@ -7,6 +7,8 @@
 // host reads into host-mapped memory.  Both run in the traces launch itself,
 // in its last workgroup.  Same rules, same arithmetic as the host (the
 // shared sp2_* functions of common.hpp).
+#include <algorithm>
+
 #include "../../include/spamm.h"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -88,11 +90,11 @@ SPAMM_DEV void sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, co
 
 // ---------------------------------------------------------------------------
 // Traces: t1 = sum of the diagonal entries (rows below n), t2 = sum over the
-// live slots of (sq + sqlo) = ||X||_F^2, both in double-double.  Fixed
-// grid and fixed reduction order (slots strided over the grid, a wave tree,
-// the four waves in order, then the partials of the workgroups: lane l adds
-// partial l + 64 to partial l, then a wave tree), so the result depends only
-// on the slot contents and order.
+// live slots of (sq + sqlo) = ||X||_F^2, both in double-double.  A grid
+// fixed by the matrix size and a fixed reduction order (slots strided over
+// the grid, a wave tree, the four waves in order, then the partials of the
+// workgroups: lane l adds partial l + 64 to partial l, then a wave tree), so
+// the result depends only on the slot contents and order.
 // ---------------------------------------------------------------------------
 constexpr int kTrBlocks = 120;
 static_assert(kTrBlocks <= 128, "two partials per lane in the last workgroup");
@@ -203,8 +205,29 @@ void launch_traces_init(double* temp, hipStream_t s) {
 void launch_traces(const int32_t* nslot, int64_t cap, int b, int64_t n, const int32_t* brow, const int32_t* bcol,
                    const double* val, const double* sq, const double* sqlo, double* temp, double* out,
                    const int32_t* done, hipStream_t s, const TraceTail& tail) {
-    hipLaunchKernelGGL(k_traces, dim3(kTrBlocks), dim3(256), 0, s, nslot, cap, b, n, brow, bcol, val, sq, sqlo, temp,
-                       out, done, tail);
+    // one workgroup per 256 block positions of the nb x nb grid, at most
+    // kTrBlocks: a function of the matrix size only, so every run of one
+    // system (host or device loop, alone or batched) adds in the same order
+    const int64_t nb = (n + b - 1) / b;
+    const int grid = (int)std::min<int64_t>(kTrBlocks, std::max<int64_t>(1, (nb * nb + 255) / 256));
+    hipLaunchKernelGGL(k_traces, dim3(grid), dim3(256), 0, s, nslot, cap, b, n, brow, bcol, val, sq, sqlo, temp, out,
+                       done, tail);
+}
+
+// The control block of the device-driven loop: the host's settings, and from
+// the spectral bounds lam = (lambda_min, lambda_max) the gap edges mapped to
+// [0, 1] and delta_0 (the host loop's arithmetic, in the same order).
+__global__ void k_sp2_init(Sp2Ctl hc, const double* __restrict__ lam, Sp2Ctl* __restrict__ ctl) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double W = lam[1] - lam[0];
+    hc.xh = hc.have_gap ? (lam[1] - hc.homo) / W : NAN;
+    hc.xl = hc.have_gap ? (lam[1] - hc.lumo) / W : NAN;
+    hc.delta = sp2_step_delta(hc.eps, hc.n_max, hc.delta_const, hc.xh - hc.xl);
+    *ctl = hc;
+}
+
+void launch_sp2_init(const Sp2Ctl& hc, const double* lam, Sp2Ctl* ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_sp2_init, dim3(1), dim3(64), 0, s, hc, lam, ctl);
 }
 
 __global__ void k_ctl_upload(const Sp2Ctl* __restrict__ src, Sp2Ctl* __restrict__ ctl) {

@@ -262,15 +262,22 @@ void launch_level_build(const uint32_t* keys, const int64_t* n, int64_t cap, con
 // combination of Algorithm 3, a (row half of C) outer, c (column half)
 // inner, t = E(a, k=0, c) + E(a, k=1, c), acc += t^2, then the root.
 SPAMM_DEV double node_eval(const uint32_t* ckeys, const double* __restrict__ cvals, int c0, int c1, int m, int N) {
+    // a node has at most eight children: all their loads issued before any is used
+    uint32_t o[8];
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const bool live = c0 + u < c1;
+        o[u] = live ? (ckeys[c0 + u] & 7u) : 8u;
+        v[u] = live ? cvals[(size_t)(c0 + u) * N + m] : 0.0;
+    }
     double e[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) e[q] = 0.0;
-    for (int c = c0; c < c1; ++c) {
-        const uint32_t o = ckeys[c] & 7u;
-        const double v = cvals[(size_t)c * N + m];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) e[q] = (o == (uint32_t)q) ? v : e[q];
-    }
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = (o[u] == (uint32_t)q) ? v[u] : e[q];
     double acc = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)

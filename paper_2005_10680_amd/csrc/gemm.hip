@@ -943,9 +943,13 @@ __attribute__((amdgpu_waves_per_eu(RingCfg<B>::template waves<LOWT>(), 8))) void
     if ((int64_t)blockIdx.x >= nout && blockIdx.x >= 8) return;
     const int xcd = blockIdx.x % 8;
     if (tid < 9) {
-        const int64_t np = g.optr[nout];
-        auto pb = [&](int64_t o) -> int64_t { return g.optr[o]; };
-        s_cut[tid] = (int)xcd_cut(nout, np, tid, pb);
+        if (g.cuts) {
+            s_cut[tid] = g.cuts[tid];
+        } else {
+            const int64_t np = g.optr[nout];
+            auto pb = [&](int64_t o) -> int64_t { return g.optr[o]; };
+            s_cut[tid] = (int)xcd_cut(nout, np, tid, pb);
+        }
     }
     __syncthreads();
     const bool beta = g.mapX && g.branch && (*g.branch == 1);

@@ -113,14 +113,14 @@ void set_small_path(bool on);
 void launch_occ_small(const MatView& X, uint32_t* bits, int nw, uint8_t* tiles, int T, int l0, uint32_t* cube_keys,
                       int64_t* ncubes, const int32_t* done, hipStream_t s);
 // kept pairs, output list, output pattern of C and its slots, sc[0..3] as the
-// device-wide passes, and counters[0..15] = 0
+// device-wide passes, counters[0..15] = 0, and the ring kernel's 9 cuts
 void launch_pairs_small(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
                         const double* normA, const int32_t* mapB, const double* normB, int btrans, int sym,
                         const double* tau, const double* sigma, double norm_min, int64_t cap_pairs, int64_t cap_out,
                         int32_t* oi, int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int64_t* sc,
                         int64_t capC, int32_t* mapC, int32_t* browC, int32_t* bcolC, int32_t* nslotC,
-                        uint8_t* fromc, const int32_t* mapX, const int32_t* branch, int32_t* counters, int32_t* ovf,
-                        const int32_t* done, hipStream_t s);
+                        uint8_t* fromc, const int32_t* mapX, const int32_t* branch, int32_t* counters,
+                        int32_t* cuts, int32_t* ovf, const int32_t* done, hipStream_t s);
 
 // cse.hip
 size_t cse_cube_cap(int nb);
@@ -199,6 +199,10 @@ struct GemmArgs {
     // rotated by f32_rot; null when not wanted; the FP32-tier kernels only),
     // for the next step's low tier
     float* out32 = nullptr;
+    // the per-XCD output ranges of the ring kernel (9 cuts: the outputs whose
+    // first pair lies below npairs * x / 8), when the pair pass computed them;
+    // null: the kernel finds them itself
+    const int32_t* cuts = nullptr;
 };
 // ev_start/ev_end (optional) are recorded right around the product kernel.
 // counters_clear: the work counters g.counters[0..15] are already zero (the
@@ -258,6 +262,9 @@ struct Sp2HostStatus {
 };
 // *ctl = *src, src in host-mapped memory
 void launch_ctl_upload(const Sp2Ctl* src, Sp2Ctl* ctl, hipStream_t s);
+// *ctl = hc with xh, xl (gap edges mapped by the bounds lam[2] on the device)
+// and delta_0 filled in
+void launch_sp2_init(const Sp2Ctl& hc, const double* lam, Sp2Ctl* ctl, hipStream_t s);
 // What runs after the traces of the current iterate, in the traces launch
 // itself (by its last workgroup): the device control step (ctl set: graph
 // loop) or the host-status gather (hs set: host loop), reading the previous

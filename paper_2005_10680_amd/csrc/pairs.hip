@@ -361,7 +361,10 @@ void launch_occ_small(const MatView& X, uint32_t* bits, int nw, uint8_t* tiles, 
 // k_kept_count, the scans of the counts, the output flags and the low-tier
 // counts, k_kept_fill, k_hat_flags, the scan of the output pattern and
 // k_hat_assign for P * P <= kSmallPP outputs; also clears the product's 16
-// work counters (the product launch then skips its own reset).
+// work counters (the product launch then skips its own reset).  Output z is
+// taken by thread z mod kSmallThreads in round z / kSmallThreads, so small
+// grids keep every thread busy; the three counts of an output travel packed
+// in one 64-bit scan (21 bits each: at most 64 * 4096 pairs).
 __global__ __launch_bounds__(kSmallThreads) void k_pairs_small(
     int nb, int P, int nw, const uint32_t* __restrict__ bitsA, const uint32_t* __restrict__ bitsB,
     const int32_t* __restrict__ mapA, const double* __restrict__ normA, const int32_t* __restrict__ mapB,
@@ -371,23 +374,27 @@ __global__ __launch_bounds__(kSmallThreads) void k_pairs_small(
     int64_t* __restrict__ sc, int64_t capC, int32_t* __restrict__ mapC, int32_t* __restrict__ browC,
     int32_t* __restrict__ bcolC, int32_t* __restrict__ nslotC, uint8_t* __restrict__ fromc,
     const int32_t* __restrict__ mapX, const int32_t* __restrict__ branch_p, int32_t* __restrict__ counters,
-    int32_t* __restrict__ ovf, const int32_t* __restrict__ done) {
+    int32_t* __restrict__ cuts, int32_t* __restrict__ ovf, const int32_t* __restrict__ done) {
+    constexpr int kBits = 21;
+    constexpr int64_t kMask = ((int64_t)1 << kBits) - 1;
     __shared__ int32_t s_cnt[kSmallPP];
     __shared__ int64_t s_wave[kSmallThreads / 64];
+    __shared__ int32_t s_cut[8];
     if (done && *done) return;
     const int tid = threadIdx.x;
     if (tid < 16) counters[tid] = 0;
+    if (tid < 8) s_cut[tid] = 0;
     const double tau = *tau_p;
     const double sigma = sigma_p ? *sigma_p : 0.0;
     const int PP = P * P;
-    const int z0 = tid * kSmallPer;
-    int cl[kSmallPer];
-    int sum_c = 0, sum_f = 0, sum_l = 0;
+    const int R = (PP + kSmallThreads - 1) / kSmallThreads;
+    int64_t off[kSmallPer], oix[kSmallPer];
+    int64_t base = 0;
 #pragma unroll
     for (int u = 0; u < kSmallPer; ++u) {
-        const int z = z0 + u;
-        int c = 0;
-        cl[u] = 0;
+        if (u >= R) break;
+        const int z = u * kSmallThreads + tid;
+        int c = 0, cl = 0;
         if (z < PP) {
             uint32_t i, j;
             demorton2((uint32_t)z, i, j);
@@ -395,19 +402,19 @@ __global__ __launch_bounds__(kSmallThreads) void k_pairs_small(
                 for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
                               [&](int, int sa, int sb, double p) {
                                   ++c;
-                                  if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) ++cl[u];
+                                  if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) ++cl;
                               });
             }
             s_cnt[z] = c;
         }
-        sum_c += c;
-        sum_f += c > 0 ? 1 : 0;
-        sum_l += cl[u];
+        const int64_t v = (int64_t)c | ((int64_t)(c > 0 ? 1 : 0) << kBits) | ((int64_t)cl << (2 * kBits));
+        int64_t tot = 0;
+        const int64_t ex = base + block_inclusive_scan<kSmallThreads>(v, s_wave, tot) - v;
+        off[u] = ex & kMask;
+        oix[u] = (ex >> kBits) & kMask;
+        base += tot;
     }
-    int64_t npairs = 0, nout = 0, nlow = 0;
-    const int64_t off0 = block_inclusive_scan<kSmallThreads>(sum_c, s_wave, npairs) - sum_c;
-    const int64_t oidx0 = block_inclusive_scan<kSmallThreads>(sum_f, s_wave, nout) - sum_f;
-    if (sigma_p) block_inclusive_scan<kSmallThreads>(sum_l, s_wave, nlow);
+    const int64_t npairs = base & kMask, nout = (base >> kBits) & kMask, nlow = base >> (2 * kBits);
     if (tid == 0) {
         sc[0] = npairs;
         sc[1] = nout;
@@ -416,96 +423,91 @@ __global__ __launch_bounds__(kSmallThreads) void k_pairs_small(
         if (npairs > cap_pairs) atomicOr(ovf, kOvfPairs);
         if (nout > cap_out) atomicOr(ovf, kOvfOut);
     }
-    // kept pairs of each output: low tier first, then FP64, ascending k in each
+    // kept pairs of each output: low tier first, then FP64, ascending k in
+    // each; and the product's per-XCD output ranges (k_gemm_ring's cut x:
+    // the outputs whose first pair lies below npairs * x / 8)
     if (npairs <= cap_pairs) {
-        int64_t w = off0, o = oidx0;
 #pragma unroll
         for (int u = 0; u < kSmallPer; ++u) {
-            const int z = z0 + u;
+            if (u >= R) break;
+            const int z = u * kSmallThreads + tid;
             if (z >= PP || s_cnt[z] == 0) continue;
+            const int64_t o = oix[u];
+            if (o >= cap_out) continue;
             uint32_t i, j;
             demorton2((uint32_t)z, i, j);
-            if (o < cap_out) {
-                oi[o] = (int32_t)i;
-                oj[o] = (int32_t)j;
-                optr[o] = (int32_t)w;
-                const int64_t w0 = w;
-                if (sigma_p) {
-                    for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                                  [&](int, int sa, int sb, double p) {
-                                      if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) {
-                                          if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
-                                          ++w;
-                                      }
-                                  });
-                    if (olow) olow[o] = (int32_t)(w - w0);
-                    for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                                  [&](int, int sa, int sb, double p) {
-                                      if (!(p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min)) {
-                                          if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
-                                          ++w;
-                                      }
-                                  });
-                } else {
-                    for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                                  [&](int, int sa, int sb, double) {
+            oi[o] = (int32_t)i;
+            oj[o] = (int32_t)j;
+            optr[o] = (int32_t)off[u];
+            for (int x = 1; x < 8; ++x)
+                if (off[u] < npairs * x / 8) atomicAdd(&s_cut[x], 1);
+            int64_t w = off[u];
+            if (sigma_p) {
+                for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                              [&](int, int sa, int sb, double p) {
+                                  if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) {
                                       if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
                                       ++w;
-                                  });
-                }
-                w = w0 + s_cnt[z];
+                                  }
+                              });
+                if (olow) olow[o] = (int32_t)(w - off[u]);
+                for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                              [&](int, int sa, int sb, double p) {
+                                  if (!(p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min)) {
+                                      if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                                      ++w;
+                                  }
+                              });
             } else {
-                w += s_cnt[z];
+                for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                              [&](int, int sa, int sb, double) {
+                                  if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
+                                  ++w;
+                              });
             }
-            ++o;
         }
     }
     // output pattern (k_hat_flags) and its slots (k_hat_assign)
     const int br = branch_p ? *branch_p : 0;
-    int hf[kSmallPer];
-    int sum_h = 0;
+    int64_t hbase = 0;
 #pragma unroll
     for (int u = 0; u < kSmallPer; ++u) {
-        const int z = z0 + u;
-        hf[u] = 0;
+        if (u >= R) break;
+        const int z = u * kSmallThreads + tid;
+        uint32_t r = 0, c = 0;
+        int hf = 0;
+        bool in = false;
         if (z < PP) {
-            uint32_t r, c;
             demorton2((uint32_t)z, r, c);
-            if ((int)r < nb && (int)c < nb) {
+            in = (int)r < nb && (int)c < nb;
+            if (in) {
                 const uint32_t cz = sym ? morton2(min(r, c), max(r, c)) : (uint32_t)z;
-                hf[u] = s_cnt[cz] > 0;
-                if (!hf[u] && mapX && br == 1) hf[u] = mapX[(size_t)r * nb + c] >= 0;
+                hf = s_cnt[cz] > 0;
+                if (!hf && mapX && br == 1) hf = mapX[(size_t)r * nb + c] >= 0;
             }
         }
-        sum_h += hf[u];
-    }
-    int64_t total = 0;
-    int64_t sl = block_inclusive_scan<kSmallThreads>(sum_h, s_wave, total) - sum_h;
-    if (tid == 0) {
-        sc[2] = total;
-        *nslotC = (int32_t)(total <= capC ? total : capC);
-        if (total > capC) atomicOr(ovf, kOvfSlots);
-    }
-#pragma unroll
-    for (int u = 0; u < kSmallPer; ++u) {
-        const int z = z0 + u;
-        if (z >= PP) continue;
-        uint32_t r, c;
-        demorton2((uint32_t)z, r, c);
-        if ((int)r >= nb || (int)c >= nb) continue;
-        int32_t m = -1;
-        if (hf[u]) {
-            if (sl < capC) {
+        int64_t tot = 0;
+        const int64_t sl = hbase + block_inclusive_scan<kSmallThreads>(hf, s_wave, tot) - hf;
+        hbase += tot;
+        if (in) {
+            int32_t m = -1;
+            if (hf && sl < capC) {
                 m = (int32_t)sl;
                 browC[sl] = (int32_t)r;
                 bcolC[sl] = (int32_t)c;
                 const uint32_t cz = sym ? morton2(min(r, c), max(r, c)) : (uint32_t)z;
                 if (fromc) fromc[sl] = s_cnt[cz] > 0 ? 1 : 0;
             }
-            ++sl;
+            mapC[(size_t)r * nb + c] = m;
         }
-        mapC[(size_t)r * nb + c] = m;
     }
+    __syncthreads();
+    if (tid == 0) {
+        sc[2] = hbase;
+        *nslotC = (int32_t)(hbase <= capC ? hbase : capC);
+        if (hbase > capC) atomicOr(ovf, kOvfSlots);
+    }
+    if (cuts && tid < 9) cuts[tid] = tid == 8 ? (int32_t)nout : s_cut[tid];
 }
 
 void launch_pairs_small(int nb, int P, int nw, const uint32_t* bitsA, const uint32_t* bitsB, const int32_t* mapA,
@@ -513,11 +515,11 @@ void launch_pairs_small(int nb, int P, int nw, const uint32_t* bitsA, const uint
                         const double* tau, const double* sigma, double norm_min, int64_t cap_pairs, int64_t cap_out,
                         int32_t* oi, int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow, int64_t* sc,
                         int64_t capC, int32_t* mapC, int32_t* browC, int32_t* bcolC, int32_t* nslotC,
-                        uint8_t* fromc, const int32_t* mapX, const int32_t* branch, int32_t* counters, int32_t* ovf,
-                        const int32_t* done, hipStream_t s) {
+                        uint8_t* fromc, const int32_t* mapX, const int32_t* branch, int32_t* counters,
+                        int32_t* cuts, int32_t* ovf, const int32_t* done, hipStream_t s) {
     hipLaunchKernelGGL(k_pairs_small, dim3(1), dim3(kSmallThreads), 0, s, nb, P, nw, bitsA, bitsB, mapA, normA, mapB,
                        normB, btrans, sym, tau, sigma, norm_min, cap_pairs, cap_out, oi, oj, optr, pairs, olow, sc,
-                       capC, mapC, browC, bcolC, nslotC, fromc, mapX, branch, counters, ovf, done);
+                       capC, mapC, browC, bcolC, nslotC, fromc, mapX, branch, counters, cuts, ovf, done);
 }
 
 }  // namespace spamm
