@@ -18,74 +18,83 @@ namespace spamm {
 // One control step: record the results of the step that produced the current
 // iterate, then (unless the loop stops) the next step's branch, delta_i and
 // budgets.  tr: t1 hi, lo, t2 hi, lo of the current iterate.
-SPAMM_DEV void sp2_control(Sp2Ctl* ctl, const double* tr, const int64_t* msc, const int64_t* ts,
+SPAMM_DEV void sp2_control(Sp2Ctl* ctl_p, const double* tr, const int64_t* msc_p, const int64_t* ts_p,
                            const int32_t* ovf_mul, const int32_t* ovf_sweep, sp2_iter_log* logs,
                            int32_t max_records) {
-    if (ctl->done) return;
-    const int nlog = ctl->nlog;
+    // everything read up front (independent loads in flight together), the
+    // decisions in registers, the control block written back once
+    Sp2Ctl c = *ctl_p;
+    const int32_t ovf = *ovf_mul | *ovf_sweep;
+    int64_t msc[4], ts[3];
+    for (int q = 0; q < 4; ++q) msc[q] = msc_p[q];
+    for (int q = 0; q < 3; ++q) ts[q] = ts_p[q];
+    if (c.done) return;
+    const int nlog = c.nlog;
     const int it = nlog + 1;
-    if (*ovf_mul || *ovf_sweep) {
-        ctl->status = SPAMM_ECAPACITY;
-        ctl->done = 1;
+    if (ovf) {
+        ctl_p->status = SPAMM_ECAPACITY;
+        ctl_p->done = 1;
         return;
     }
     if (nlog > 0) {
         // results of the step that produced the current iterate
         sp2_iter_log& L = logs[nlog - 1];
-        L.idx = ctl->idx;
-        L.tau = ctl->tau;
+        L.idx = c.idx;
+        L.tau = c.tau;
         L.npairs = msc[0];
         L.nout = msc[1];
         L.nslot_hat = msc[2];
         L.removed_units = ts[0];
-        L.removed_fro2 = (double)ts[1] * sp2_trunc_quantum(L.delta * ctl->trunc_scale);
+        L.removed_fro2 = (double)ts[1] * sp2_trunc_quantum(L.delta * c.trunc_scale);
         L.nslot_kept = msc[2] - ts[2];  // blocks of X~: those of X^ minus the removed ones
-        L.npairs_low = ctl->tiered ? msc[3] : 0;
-        L.sigma = ctl->sigma;
-        L.sidx = ctl->sidx;
+        L.npairs_low = c.tiered ? msc[3] : 0;
+        L.sigma = c.sigma;
+        L.sidx = c.sidx;
     }
     const double t1 = tr[0], t2 = tr[2];
     const double e = dd_diff(tr[0], tr[1], tr[2], tr[3]);
-    ctl->e_hist[2] = ctl->e_hist[1];
-    ctl->e_hist[1] = ctl->e_hist[0];
-    ctl->e_hist[0] = e;
-    if (ctl->n_e < 3) ctl->n_e += 1;
+    c.e_hist[2] = c.e_hist[1];
+    c.e_hist[1] = c.e_hist[0];
+    c.e_hist[0] = e;
+    if (c.n_e < 3) c.n_e += 1;
     if (nlog >= max_records) {  // cannot happen with n_max + 2 records; stop safely
-        ctl->status = SPAMM_WNOCONV;
-        ctl->done = 1;
+        c.status = SPAMM_WNOCONV;
+        c.done = 1;
+        *ctl_p = c;
         return;
     }
-    sp2_iter_log& L = logs[nlog];
-    L = sp2_iter_log{};
+    sp2_iter_log L = sp2_iter_log{};
     L.i = it;
     L.t1 = t1;
     L.t2 = t2;
     L.e = e;
     L.branch = -1;
-    ctl->nlog = nlog + 1;
-    const bool stop = sp2_should_stop(ctl->e_hist, ctl->n_e, ctl->e_tol);
-    if (stop || it > ctl->n_max) {
+    c.nlog = nlog + 1;
+    const bool stop = sp2_should_stop(c.e_hist, c.n_e, c.e_tol);
+    if (stop || it > c.n_max) {
         L.stop = stop ? 1 : 2;
-        ctl->status = stop ? SPAMM_OK : SPAMM_WNOCONV;
-        ctl->done = 1;
-        return;
+        c.status = stop ? SPAMM_OK : SPAMM_WNOCONV;
+        c.done = 1;
+    } else {
+        const int br = sp2_choose_branch(t1, t2, c.n_occ);
+        if (c.have_gap) {
+            c.xh = sp2_map_gap(c.xh, br);
+            c.xl = sp2_map_gap(c.xl, br);
+        }
+        const double delta = sp2_step_delta(c.eps, c.n_max, c.delta_const, c.xh - c.xl);
+        L.branch = br;
+        L.delta = delta;
+        c.branch = br;
+        c.delta = delta;
+        c.budget = c.variant == 0 ? delta / 2.0 : delta;
+        c.budget_skip = c.tiered ? c.tier_split * c.budget : c.budget;
+        c.tau = 0.0;
+        c.idx = c.N;
+        c.sigma = 0.0;
+        c.sidx = c.N;
     }
-    const int br = sp2_choose_branch(t1, t2, ctl->n_occ);
-    if (ctl->have_gap) {
-        ctl->xh = sp2_map_gap(ctl->xh, br);
-        ctl->xl = sp2_map_gap(ctl->xl, br);
-    }
-    const double delta = sp2_step_delta(ctl->eps, ctl->n_max, ctl->delta_const, ctl->xh - ctl->xl);
-    L.branch = br;
-    L.delta = delta;
-    ctl->branch = br;
-    ctl->delta = delta;
-    ctl->budget = ctl->variant == 0 ? delta / 2.0 : delta;
-    ctl->budget_skip = ctl->tiered ? ctl->tier_split * ctl->budget : ctl->budget;
-    ctl->tau = 0.0;
-    ctl->idx = ctl->N;
-    ctl->sigma = 0.0;
-    ctl->sidx = ctl->N;
+    logs[nlog] = L;
+    *ctl_p = c;
 }
 
 // ---------------------------------------------------------------------------
