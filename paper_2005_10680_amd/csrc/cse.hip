@@ -5,10 +5,12 @@
 // triples.  Nodes are identified by 3D Morton keys, whose low three bits are
 // the octant (a, kappa, c) inside the parent.  The bottom l0 levels are
 // evaluated per "cube" (2^l0 x 2^l0 x 2^l0 triples): the cube's A and B
-// leaf norms are staged in LDS and eight threads per candidate walk the
-// cube's eight subtrees in the canonical order of Algorithm 3 (a = row half
-// outer, c = column half inner, t = E1 + E2, acc += t^2, sqrt at the end),
-// one of them then combining the eight in the same order.  The levels above run as segmented reductions over the
+// leaf norms are staged in LDS and each candidate's subtree is walked in the
+// canonical order of Algorithm 3 (a = row half outer, c = column half inner,
+// t = E1 + E2, acc += t^2, sqrt at the end) -- by one thread when there are
+// few candidates (several cubes per workgroup), else by eight threads, one
+// per child subtree, one of them then combining the eight in the same
+// order.  The levels above run as segmented reductions over the
 // sorted node lists, one launch per level.  All arithmetic is in the
 // paper's order with one rounding per operation, so every candidate's bound
 // is bit-identical to the recursive definition.
@@ -105,7 +107,73 @@ SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double 
     }
 }
 
-// Each workgroup of 256 threads takes one cube and kCandPerWg candidates:
+// LDS for the leaf products of the cubes of one workgroup (doubles)
+constexpr int kCubeLds = 4096;
+
+// Few candidates (N <= 64): workgroups of 256 threads take `cpw` cubes at a
+// time, `lpc` threads per cube (candidates m = lane, lane + lpc, ...): the
+// leaf norms of the cubes go to LDS, then their S^3 leaf products (computed
+// once, shared by every candidate), then each thread evaluates Algorithm 3
+// over its cube for its candidates.
+template <int L0, int MODE>
+__global__ __launch_bounds__(256) void k_cube_eval_whole(int nb, const uint32_t* __restrict__ keys,
+                                                  const int64_t* __restrict__ ncubes_p, int64_t cap,
+                                                  const int32_t* __restrict__ mapA, const double* __restrict__ normA,
+                                                  const int32_t* __restrict__ mapB, const double* __restrict__ normB,
+                                                  int btrans, const double* __restrict__ tau, int N,
+                                                  const double* __restrict__ tau0_p, double c_low, int cpw, int lpc,
+                                                  double* __restrict__ vals, const int32_t* __restrict__ done) {
+    constexpr int S = 1 << L0;
+    constexpr int S2 = S * S, S3 = S * S * S;
+    __shared__ double nA[kCubeLds / 4];
+    __shared__ double nB[kCubeLds / 4];
+    __shared__ double P[kCubeLds];
+    if (done && *done) return;
+    int64_t ncubes = *ncubes_p;
+    if (ncubes > cap) ncubes = cap;
+    const double t0 = (MODE == 1 && tau0_p) ? *tau0_p : 0.0;
+    const int tid = threadIdx.x;
+    for (int64_t g = blockIdx.x; g * cpw < ncubes; g += gridDim.x) {
+        const int64_t c0 = g * cpw;
+        __syncthreads();
+        for (int t = tid; t < cpw * S2; t += 256) {
+            const int c = t / S2, r = t % S2;
+            const int a = r / S, q = r % S;
+            double va = 0.0, vb = 0.0;
+            if (c0 + c < ncubes) {
+                uint32_t I, K, J;
+                demorton3(keys[c0 + c], I, K, J);
+                const int i = (int)I * S + a, k = (int)K * S + q;  // A_ik
+                if (i < nb && k < nb) {
+                    const int sa = mapA[(size_t)i * nb + k];
+                    if (sa >= 0) va = normA[sa];
+                }
+                const int kk = (int)K * S + a, j = (int)J * S + q;  // B_kj
+                if (kk < nb && j < nb) {
+                    const int sb = btrans ? mapB[(size_t)j * nb + kk] : mapB[(size_t)kk * nb + j];
+                    if (sb >= 0) vb = normB[sb];
+                }
+            }
+            nA[t] = va;
+            nB[t] = vb;
+        }
+        __syncthreads();
+        for (int t = tid; t < cpw * S3; t += 256) {
+            const int c = t / S3, r = t % S3;
+            const int i = r / S2, k = (r / S) % S, j = r % S;
+            P[t] = nA[c * S2 + i * S + k] * nB[c * S2 + k * S + j];
+        }
+        __syncthreads();
+        const int c = tid / lpc;
+        if (c < cpw && c0 + c < ncubes) {
+            for (int m = tid % lpc; m < N; m += lpc)
+                vals[(size_t)(c0 + c) * N + m] = cube_node<L0, S, MODE>(0, 0, 0, tau[m], t0, c_low, P + c * S3);
+        }
+    }
+}
+
+// More candidates: each workgroup of 256 threads takes one cube and
+// kCandPerWg candidates:
 // the cube's A and B leaf norms go to LDS, then its S^3 leaf products
 // (computed once per workgroup, shared by its candidates); eight threads per
 // candidate evaluate the cube's eight level-(L0 - 1) subtrees (octant
@@ -117,7 +185,7 @@ SPAMM_DEV double cube_node(int i0, int k0, int j0, double tm, double t0, double 
 constexpr int kCandPerWg = 256 / 8;
 
 template <int L0, int MODE>
-__global__ __launch_bounds__(256) void k_cube_eval(int nb, const uint32_t* __restrict__ keys,
+__global__ __launch_bounds__(256) void k_cube_eval_split(int nb, const uint32_t* __restrict__ keys,
                                                   const int64_t* __restrict__ ncubes_p, int64_t cap,
                                                   const int32_t* __restrict__ mapA, const double* __restrict__ normA,
                                                   const int32_t* __restrict__ mapB, const double* __restrict__ normB,
@@ -191,15 +259,10 @@ __global__ __launch_bounds__(256) void k_cube_eval(int nb, const uint32_t* __res
     }
 }
 
-void launch_cube_eval(int mode, int l0, int nb, const uint32_t* keys, const int64_t* ncubes, int64_t cap,
-                      const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB, int btrans,
-                      const double* tau, int N, const double* tau0, double c_low, double* vals, const int32_t* done,
-                      hipStream_t s) {
-    const int slices = (N + kCandPerWg - 1) / kCandPerWg;
-    const int grid = grid_for(cap * slices, 1, 8192);
-#define SPAMM_CUBE(L0_, M_)                                                                                      \
-    hipLaunchKernelGGL((k_cube_eval<L0_, M_>), dim3(grid), dim3(256), 0, s, nb, keys, ncubes, cap, mapA, normA, \
-                       mapB, normB, btrans, tau, N, tau0, c_low, slices, vals, done)
+// kernel<L0, MODE> for the runtime l0 (0..4) and mode (0, 1)
+template <template <int, int> class K, typename... Args>
+void launch_cube_kernel(int mode, int l0, dim3 grid, hipStream_t s, Args... args) {
+#define SPAMM_CUBE(L0_, M_) hipLaunchKernelGGL((K<L0_, M_>::fn), grid, dim3(256), 0, s, args...)
     if (mode == 0) {
         switch (l0) {
             case 0: SPAMM_CUBE(0, 0); break;
@@ -218,6 +281,37 @@ void launch_cube_eval(int mode, int l0, int nb, const uint32_t* keys, const int6
         }
     }
 #undef SPAMM_CUBE
+}
+template <int L0, int MODE>
+struct CubeWhole {
+    static constexpr auto fn = k_cube_eval_whole<L0, MODE>;
+};
+template <int L0, int MODE>
+struct CubeSplit {
+    static constexpr auto fn = k_cube_eval_split<L0, MODE>;
+};
+
+void launch_cube_eval(int mode, int l0, int nb, const uint32_t* keys, const int64_t* ncubes, int64_t cap,
+                      const int32_t* mapA, const double* normA, const int32_t* mapB, const double* normB, int btrans,
+                      const double* tau, int N, const double* tau0, double c_low, double* vals, const int32_t* done,
+                      hipStream_t s) {
+    if (N <= 64) {
+        // threads per cube: the candidate count rounded up to a power of two,
+        // cubes per workgroup: what 256 threads and the LDS hold
+        int lpc = 1;
+        while (lpc < N) lpc <<= 1;
+        const int s3 = 1 << (3 * l0);
+        int cpw = 256 / lpc;
+        while (cpw > 1 && cpw * s3 > kCubeLds) cpw >>= 1;
+        const int grid = grid_for((cap + cpw - 1) / cpw, 1, 4096);
+        launch_cube_kernel<CubeWhole>(mode, l0, dim3(grid), s, nb, keys, ncubes, cap, mapA, normA, mapB, normB,
+                                      btrans, tau, N, tau0, c_low, cpw, lpc, vals, done);
+        return;
+    }
+    const int slices = (N + kCandPerWg - 1) / kCandPerWg;
+    const int grid = grid_for(cap * slices, 1, 8192);
+    launch_cube_kernel<CubeSplit>(mode, l0, dim3(grid), s, nb, keys, ncubes, cap, mapA, normA, mapB, normB, btrans,
+                                  tau, N, tau0, c_low, slices, vals, done);
 }
 
 __global__ void k_level_flags(const uint32_t* __restrict__ keys, const int64_t* __restrict__ n_p, int64_t cap,
