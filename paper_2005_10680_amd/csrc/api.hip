@@ -1163,7 +1163,7 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     int status = SPAMM_OK;
     if (p->graph_steps > 0) {
         // ---- device-driven loop: two steps (X0 -> X1 -> X0) captured once,
-        // replayed until the control kernel sets done (the control block was
+        // replayed until the control step sets done (the control block was
         // set up with X_0) ----
         (void)num_cus();  // device properties are read once, outside the capture
         GraphGuard gg;
