@@ -332,6 +332,11 @@ def main():
         out["cpu_baseline_chain1024"] = cpu_chain_baseline(out.get("chain1024"))
 
     print(json.dumps(out), flush=True)
+    # the batch generator's worker pool is shut down by its with-block; make
+    # sure no child process outlives the run
+    import multiprocessing
+    for ch in multiprocessing.active_children():
+        ch.join(timeout=10)
 
 
 GEMM_SOURCES = ("paper_2005_10680_amd/csrc/gemm.hip", "paper_2005_10680_amd/csrc/kernels.hpp",
