@@ -12,7 +12,10 @@ and uses only what the oracle computes quickly at any size:
   step polynomial within a rounding bound; blocks the truncation removed
   are below its budget; a mid-run iterate truncated by the library and by
   the oracle loses exactly the same blocks; the result has trace n_occ, is
-  idempotent and commutes with F.
+  idempotent and commutes with F.  The accuracy half of the workload's
+  metric: ||D~ - D||_F < eps for FP64, both tiers and B_flat, against the
+  exact projector from a dense eigensolver (a library routine, run on the
+  GPU: the dense matrix is 2 GB).
 * 3D system n = 65536, leaf 64, seed 3, FP64 and both precision tiers:
   the first step, with the same checks; in the tiers the sampled
   blocks are within the per-block tier bound (c times the sum of the norm
@@ -174,6 +177,54 @@ def test_sys3d_16384_fp64_full_run():
     fdd = fd.to_dense()
     assert np.linalg.norm(fdd - fdd.T) < 1e-5
     del res, plain, D2, FD
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def sys3d_16384_projector():
+    """F (device block-sparse) and the exact projector onto its n/2 lowest
+    eigenvectors, dense on the GPU."""
+    n, b, seed = 16384, 64, 2
+    with open(os.path.join(HERE, "golden", "spectra.json")) as f:
+        spec = json.load(f)[f"sys3d_n{n}_s{seed}_b{b}"]
+    Fm = synth.sys3d(n, seed, b)
+    G = P.BlockSparse.from_host(Fm)
+    Fd = torch.from_numpy(oracle.BSM.of(Fm).to_dense()).cuda()
+    w, U = torch.linalg.eigh(Fd)
+    del Fd
+    # the dense eigenvalues bracket the same gap as the stored spectrum
+    assert abs(float(w[n // 2 - 1]) - spec["homo"]) < 1e-9 and abs(float(w[n // 2]) - spec["lumo"]) < 1e-9
+    Uo = U[:, : n // 2].contiguous()
+    del U, w
+    Dref = Uo @ Uo.T
+    del Uo
+    yield n, b, G, spec, Dref
+    del G, Dref
+    torch.cuda.empty_cache()
+
+
+def dense_on_gpu(M, n):
+    """Dense copy of a block-sparse result (n a multiple of the leaf)."""
+    brow, bcol, vals, _, _, _ = M.live()
+    b, nb = M.b, n // M.b
+    D = torch.zeros((nb, nb, b, b), dtype=torch.float64, device="cuda")
+    v = torch.from_numpy(np.ascontiguousarray(vals.transpose(0, 2, 1))).cuda()   # [k, row, col]
+    D[torch.from_numpy(brow.astype(np.int64)).cuda(), torch.from_numpy(bcol.astype(np.int64)).cuda()] = v
+    return D.permute(0, 2, 1, 3).reshape(n, n)
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", "tree"), ("fp32", "tree"), ("bf16x3", "tree"),
+                                             ("fp64", "flat"), ("bf16x3", "flat")])
+def test_sys3d_16384_accuracy(sys3d_16384_projector, precision, bound):
+    n, b, G, spec, Dref = sys3d_16384_projector
+    res = P.purify(G, n // 2, 1e-6, synth.tau_log(32), homo=spec["homo"], lumo=spec["lumo"], precision=precision,
+                   bound=bound)
+    assert res.status == P.SPAMM_OK
+    err = float(torch.linalg.norm(dense_on_gpu(res.D, n) - Dref).item())
+    assert err < 1e-6, err
+    if precision != "fp64":
+        assert sum(lg["npairs_low"] for lg in res.logs) > 0
+    del res
     torch.cuda.empty_cache()
 
 
