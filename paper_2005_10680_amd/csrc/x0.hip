@@ -35,18 +35,27 @@ __global__ __launch_bounds__(256) void k_gersch_rows(MatView F, double* __restri
             const int s = F.map[(size_t)I * nb + J];
             if (s < 0) continue;
             const double* v = F.val + (size_t)s * b * b;
-            for (int c = 0; c < b; ++c) {
-                const int64_t gj = (int64_t)J * b + c;
-                if (gj >= n) break;
-                const double x = v[(size_t)c * b + r];
-                if (gj == g) {
-                    cen = x;
-                    has_cen = true;
-                } else {
-                    const double ax = fabs(x);
-                    if (!(ax < 0x1p1000)) special = true;           // huge, inf or NaN
-                    else if (ax != 0.0 && ax < 0x1p-900) tiny = true;  // error terms may underflow
-                    rad = dd_add(rad, dd{ax, 0.0});
+            // columns below n, in ascending order; sixteen loads in flight
+            // before their additions
+            const int64_t rem = n - (int64_t)J * b;
+            const int cnt = rem < (int64_t)b ? (int)rem : b;
+            for (int c0 = 0; c0 < cnt; c0 += 16) {
+                double xs[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) xs[u] = c0 + u < cnt ? v[(size_t)(c0 + u) * b + r] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    if (c0 + u >= cnt) break;
+                    const double x = xs[u];
+                    if ((int64_t)J * b + c0 + u == g) {
+                        cen = x;
+                        has_cen = true;
+                    } else {
+                        const double ax = fabs(x);
+                        if (!(ax < 0x1p1000)) special = true;           // huge, inf or NaN
+                        else if (ax != 0.0 && ax < 0x1p-900) tiny = true;  // error terms may underflow
+                        rad = dd_add(rad, dd{ax, 0.0});
+                    }
                 }
             }
         }
