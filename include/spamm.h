@@ -264,11 +264,15 @@ typedef struct sp2_iter_log {
  *   log   : host [n_max + 2] records; nlog_out: records written.
  * Workspace: purify_sp2_workspace_bytes(nb, b, N, cap_blocks, max_pairs, tape_steps, precision) with
  * tape_steps = n_max (keep_tape = 1), n_max / keep_tape (keep_tape > 1) or 0.
- * Host-driven loop: reads scalars back every iteration (synchronises the
- * stream; the read-back goes through a small pinned host buffer allocated
- * for the call).  Graph mode (graph_steps > 0): same decisions, same kernels and
- * bit-identical results; the stream is synchronised once per graph_steps
- * iterations.
+ * Host-driven loop: reads the spectral bounds back once, then scalars every
+ * iteration (synchronises the stream; the read-back goes through a small
+ * pinned host buffer allocated for the call).  Graph mode (graph_steps > 0):
+ * same decisions, same kernels and bit-identical results; nothing is read
+ * back before the loop (a kernel sets the control block up from the bounds
+ * on the device; only a D->cap below nb^2 makes the call read F's slot count
+ * first), the graph is captured on a stream kept per host thread and device
+ * (created on first use, never destroyed), and the stream is synchronised
+ * once per graph_steps iterations.
  */
 size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
                                   int32_t tape_steps, int32_t precision);
