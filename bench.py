@@ -206,6 +206,8 @@ def main():
                      "traffic": measured_traffic(n, b, args.seed),
                      "avg_launch_ms": round(avg_gemm_ms, 4),
                      "flops_per_launch": gemm_flops / ngemm},
+        "product_kernel": product_kernel_stats("fp64", b, int(sum(l["npairs"] for l in steps)), 0,
+                                               sum(l["ms_gemm"] for l in steps), len(steps)),
     }
 
     # the same purification as a replayed graph with decisions on the device
@@ -276,6 +278,8 @@ def main():
                         "speedup_vs_fp64": round(float(np.median(times)) / float(np.median(mtimes)), 4),
                         "phase_ms_per_run": {k: round(sum(l[k] for l in msteps), 3)
                                              for k in ("ms_sweep", "ms_pairs", "ms_gemm", "ms_norms", "ms_trunc")},
+                        "product_kernel": product_kernel_stats(tier, b, mpairs, mlow,
+                                                               sum(l["ms_gemm"] for l in msteps), len(msteps)),
                         "verify_fro_err": verify_err(rm)}
             del rm
 
@@ -350,6 +354,29 @@ def gemm_source_hash():
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def product_kernel_stats(precision, b, pairs, low, gemm_ms, launches):
+    """The leaf-product kernel of one purification, from its stream-event
+    times: the operands its kept pairs stream through the CUs (2 b^2 values
+    per pair: 8 B each for an FP64 pair, 4 B for an FP32 one, 2 x 2 B for a
+    split-BF16 one), and the fraction of the MFMA peaks its flops would need
+    (FP64 pairs 2b^3 at 78.6 TFLOP/s; FP32 pairs 2b^3 at 157.3; split-BF16
+    pairs 3 x 2b^3 at 2.5 PFLOP/s)."""
+    s = gemm_ms / 1e3
+    f64 = pairs - low
+    low_bytes = {"fp64": 8, "fp32": 4, "bf16x3": 4}[precision]
+    stream = (f64 * 8 + low * low_bytes) * 2.0 * b * b
+    t_peak = f64 * 2.0 * b ** 3 / 78.6e12
+    if precision == "fp32":
+        t_peak += low * 2.0 * b ** 3 / 157.3e12
+    elif precision == "bf16x3":
+        t_peak += low * 3 * 2.0 * b ** 3 / 2.5e15
+    kern = {"fp64": f"k_gemm_ring<{b},0>", "fp32": f"k_gemm_ring<{b},1>", "bf16x3": f"k_gemm_ring<{b},2>"}[precision]
+    return {"kernel": kern, "ms_per_launch": round(gemm_ms / max(launches, 1), 4),
+            "operand_stream_GB_per_s": round(stream / s / 1e9, 1),
+            "operand_stream_frac_of_hbm_peak": round(stream / s / 8e12, 4),
+            "mfma_frac_at_the_peaks": round(t_peak / s, 4)}
 
 
 def measured_traffic(n, b, seed):
