@@ -249,7 +249,7 @@ void launch_norms_listed(int b, const int32_t* list, const int32_t* nlist, int64
 
 // dst <- src: the slot count, the whole block map and the live slots
 // (s < min(*src.nslot, cap)) with their values and norms, in one launch.
-__global__ void k_copy_live(MatView src, MatView dst, int64_t cap, int wide) {
+__global__ void k_copy_live(MatView src, MatView dst, int64_t cap) {
     int64_t ns = *src.nslot;
     if (ns > cap) ns = cap;
     if (ns < 0) ns = 0;
@@ -265,33 +265,13 @@ __global__ void k_copy_live(MatView src, MatView dst, int64_t cap, int wide) {
         dst.sq[t] = src.sq[t];
         dst.sqlo[t] = src.sqlo[t];
     }
-    // values in 16-byte pieces when both buffers are 16-byte aligned (a slot
-    // holds b^2 doubles, b even)
-    if (wide) {
-        // four pieces per thread in flight before their stores
-        const int64_t nv2 = ns * src.b * src.b / 2;
-        const double2* sv = reinterpret_cast<const double2*>(src.val);
-        double2* dv = reinterpret_cast<double2*>(dst.val);
-        for (int64_t t0 = gt; t0 < nv2; t0 += 4 * gs) {
-            double2 x[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (t0 + u * gs < nv2) x[u] = sv[t0 + u * gs];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (t0 + u * gs < nv2) dv[t0 + u * gs] = x[u];
-        }
-    } else {
-        const int64_t nv = ns * src.b * src.b;
-        for (int64_t t = gt; t < nv; t += gs) dst.val[t] = src.val[t];
-    }
+    const int64_t nv = ns * src.b * src.b;
+    for (int64_t t = gt; t < nv; t += gs) dst.val[t] = src.val[t];
 }
 
 void launch_copy_live(const MatView& src, const MatView& dst, int64_t cap, hipStream_t s) {
     const int64_t items = std::max<int64_t>(cap * src.b * src.b, (int64_t)src.nb * src.nb);
-    const int wide = ((reinterpret_cast<uintptr_t>(src.val) | reinterpret_cast<uintptr_t>(dst.val)) & 15) == 0 &&
-                     (src.b % 2) == 0;
-    hipLaunchKernelGGL(k_copy_live, dim3(grid_for(items, 256, 4096)), dim3(256), 0, s, src, dst, cap, wide);
+    hipLaunchKernelGGL(k_copy_live, dim3(grid_for(items, 256, 4096)), dim3(256), 0, s, src, dst, cap);
 }
 
 }  // namespace spamm
