@@ -235,7 +235,7 @@ typedef struct sp2_iter_log {
                                                                    blocks of X^_i, blocks of X~_i (X^_i's minus
                                                                    the truncated ones), truncated units */
     double removed_fro2;
-    /* stream-event times in ms: threshold sweep (and FP32 copies), kept pairs
+    /* stream-event times in ms: threshold sweep (and the precision tier's copies), kept pairs
        and output pattern, the leaf-product kernel alone (which also forms
        the block norms of its outputs), pass-through blocks and the norms the
        product could not certify, truncation, whole iteration */
@@ -272,7 +272,11 @@ typedef struct sp2_iter_log {
  * on the device; only a D->cap below nb^2 makes the call read F's slot count
  * first), the graph is captured on a stream kept per host thread and device
  * (created on first use, never destroyed), and the stream is synchronised
- * once per graph_steps iterations.
+ * once per graph_steps iterations.  With the split-BF16 tier (precision 2)
+ * each iteration forks the BF16 copies of X~_i onto a second kept stream
+ * (same lifetime, default priority) beside the threshold sweeps and joins
+ * it back before the leaf products, in both loops; the call's work is
+ * complete when `stream` is.
  */
 size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
                                   int32_t tape_steps, int32_t precision);

@@ -59,25 +59,28 @@ int num_cus() {
     return cached;
 }
 
-// The stream a purification captures its graph on: one per host thread and
-// device, created on first use and kept until the process ends (creating
-// and destroying one per call costs about as much as a small system's
-// whole loop).  Calls on one thread run one after another, so they never
-// share it at the same time.
-hipError_t capture_stream(hipStream_t* out) {
+// Streams kept for the purifications: one per host thread, device and use
+// (0: the stream a graph is captured on, 1: the side stream of the
+// split-BF16 copies), created on first use and kept until the process ends
+// (creating and destroying one per call costs about as much as a small
+// system's whole loop).  Calls on one thread run one after another, so they
+// never share one at the same time.  Default priority.
+static hipError_t kept_stream(int use, hipStream_t* out) {
     constexpr int kMaxDev = 64;
-    thread_local hipStream_t streams[kMaxDev] = {};
+    thread_local hipStream_t streams[2][kMaxDev] = {};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
-    if (!streams[dev]) {
-        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+    if (!streams[use][dev]) {
+        e = hipStreamCreateWithFlags(&streams[use][dev], hipStreamNonBlocking);
         if (e != hipSuccess) return e;
     }
-    *out = streams[dev];
+    *out = streams[use][dev];
     return hipSuccess;
 }
+
+hipError_t capture_stream(hipStream_t* out) { return kept_stream(0, out); }
 
 // Graph, executable graph and event of one device-driven loop; a capture
 // left open by an early return is ended first, so the kept stream stays
@@ -1019,14 +1022,24 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     Sp2Ws w;
     carve_sp2(c, nb, b, p->N, cap, max_pairs, tape_steps, w, p->precision);
     if (c.off > ws_bytes) return fail(SPAMM_EWORKSPACE, "workspace too small");
-    hipEvent_t ev[8];
-    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    // ev[0..5]: phase times (host loop), ev[6]: start of the device loop,
+    // ev[8]/ev[9]: fork and join of the split-BF16 copy's side stream
+    hipEvent_t ev[10] = {};
     struct EvGuard {
         hipEvent_t* e;
         ~EvGuard() {
-            for (int q = 0; q < 8; ++q) (void)hipEventDestroy(e[q]);
+            for (int q = 0; q < 10; ++q)
+                if (e[q]) (void)hipEventDestroy(e[q]);
         }
     } guard{ev};
+    for (int q = 0; q < 8; ++q) HIP_TRY(hipEventCreate(&ev[q]));
+    for (int q = 8; q < 10; ++q) HIP_TRY(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
+    hipStream_t side = nullptr;
+    if (p->precision == 2) HIP_TRY(kept_stream(1, &side));
+    // the side copy runs with one workgroup per CU, leaving the rest of each
+    // CU to the sweeps' kernels beside it (more workgroups made the step
+    // slower at n = 16384 and 65536)
+    const int side_wg = num_cus();
 
     Sp2Ctl hc;
     memset(&hc, 0, sizeof(hc));
@@ -1105,6 +1118,16 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     auto enqueue_step = [&](const MatView& xv, const MatView& nv, int par, const int32_t* done, hipEvent_t* evs,
                             hipStream_t st) -> int {
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
+        // split-BF16 tier: the copies of X~_i (an HBM-bound pass) run on the
+        // side stream beside the occupancy pass and the two sweeps, which
+        // read only the block pattern and norms; joined before the products
+        if (side) {
+            HIP_TRY(hipEventRecord(ev[8], st));
+            HIP_TRY(hipStreamWaitEvent(side, ev[8], 0));
+            launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp, done,
+                             side, side_wg);
+            HIP_TRY(hipEventRecord(ev[9], side));
+        }
         // the iterate's occupancy, shared by the sweeps and the kept pairs
         const SymOcc occ = build_sym_occ(xv, w.mw.bitsA, w.mw.nw, w.sw.tA, w.sw.T, w.sw.l0, done, st, &w.sw);
         if (p->variant != 2 && p->bound_kind != 0)
@@ -1123,12 +1146,9 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             else
                 run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2,
                           &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st, &occ);
-            if (p->precision == 2)
-                launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp,
-                                 done, st);
-            else if (!f32_fused)
-                launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, st);
+            if (!side && !f32_fused) launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, st);
         }
+        if (side) HIP_TRY(hipStreamWaitEvent(st, ev[9], 0));
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));
         // kept pairs, output pattern and the leaf products (combined with X),
         // with the block norms of the new iterate

@@ -1190,59 +1190,73 @@ SPAMM_DEV uint16_t bf16_bits(double v) { return (uint16_t)(__float_as_uint((floa
 // Split-BF16 copies of the live blocks: the block is scaled by 2^-e so that
 // its largest |x| lies in [1, 2) (exact), then hi = RN_bf16(x'), lo =
 // RN_bf16(x' - hi); both parts row-major, hi then lo per slot; expo = e.
-// One wave per block: lane l holds the CPL entries of row l % B in columns
-// CPL (l / B) onwards in registers (each column read is one coalesced load),
-// the wave takes the block's largest |x|, and each lane writes its row
-// segment of both parts with 16-byte stores.
+// One workgroup per block: the threads read the column-major block with
+// 16-byte loads (consecutive lanes, consecutive bytes) into an LDS copy with
+// rows of B + 1 doubles, take the block's largest |x|, and then write both
+// parts in 16-byte pieces of eight entries of a row, consecutive lanes
+// writing consecutive pieces, so both the reads and the writes move whole
+// lines.  The odd row stride keeps the column-order LDS writes and the
+// row-order reads within two passes of the 64 banks at leaf 64.
 template <int B>
 __global__ __launch_bounds__(256) void k_to_bf16x2(const int32_t* __restrict__ nslot_p, int64_t cap,
                                                   const int32_t* __restrict__ brow, const double* __restrict__ val,
                                                   uint16_t* __restrict__ out, int32_t* __restrict__ expo,
                                                   const int32_t* __restrict__ done) {
-    constexpr int CPL = B * B / 64;  // entries per lane: 16 at leaf 32, 64 at leaf 64
-    static_assert(CPL % 8 == 0, "16-byte row segments");
+    constexpr int LD = B + 1;          // LDS row stride in doubles
+    constexpr int NV = B * B / 512;    // 16-byte loads per thread: 8 at leaf 64, 2 at leaf 32
+    constexpr int NCH = B * B / 8;     // 16-byte pieces per part
+    static_assert(NV >= 1 && B % 8 == 0, "leaf 32 or 64");
+    __shared__ double tile[B * LD];
+    __shared__ double s_m[4];
     if (done && *done) return;
     int64_t nslot = *nslot_p;
     if (nslot > cap) nslot = cap;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int row = lane % B, c0 = CPL * (lane / B);
-    for (int64_t s = (int64_t)blockIdx.x * 4 + wv; s < nslot; s += (int64_t)gridDim.x * 4) {
-        if (brow[s] < 0) continue;  // hole (wave-uniform)
-        const double* v = val + (size_t)s * B * B;
-        double x[CPL];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int64_t s = blockIdx.x; s < nslot; s += gridDim.x) {
+        if (brow[s] < 0) continue;  // hole (workgroup-uniform)
+        const double2* src = reinterpret_cast<const double2*>(val + (size_t)s * B * B);
+        double2 v[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = src[q * 256 + t];
         double m = 0.0;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            x[c] = v[(size_t)(c0 + c) * B + row];  // column-major source
-            m = fmax(m, fabs(x[c]));
+        for (int q = 0; q < NV; ++q) {
+            const int e = 2 * (q * 256 + t), c = e / B, r = e % B;  // column-major: entries (r, c), (r + 1, c)
+            tile[r * LD + c] = v[q].x;
+            tile[(r + 1) * LD + c] = v[q].y;
+            m = fmax(m, fmax(fabs(v[q].x), fabs(v[q].y)));
         }
 #pragma unroll
         for (int k = 32; k >= 1; k >>= 1) m = fmax(m, __shfl_xor(m, k));
+        if (lane == 0) s_m[wv] = m;
+        __syncthreads();
+        m = fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3]));
         int ex = 0;
         if (m > 0.0) frexp(m, &ex);
         const int sc = 1 - ex;  // x' = x 2^sc has its largest |x'| in [1, 2)
-        uint16_t* hi = out + (size_t)s * 2 * B * B + (size_t)row * B + c0;  // row-major destination
-        uint16_t* lo = hi + B * B;
-#pragma unroll
-        for (int g = 0; g < CPL / 8; ++g) {
+        uint4* hi = reinterpret_cast<uint4*>(out + (size_t)s * 2 * B * B);  // row-major destination
+        uint4* lo = reinterpret_cast<uint4*>(out + (size_t)s * 2 * B * B + B * B);
+        for (int j = t; j < NCH; j += 256) {
+            const double* row = tile + (j / (B / 8)) * LD + 8 * (j % (B / 8));  // piece j: 8 entries of one row
             uint32_t hw[4], lw[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double x0 = ldexp(x[8 * g + 2 * q], sc), x1 = ldexp(x[8 * g + 2 * q + 1], sc);
+                const double x0 = ldexp(row[2 * q], sc), x1 = ldexp(row[2 * q + 1], sc);
                 const double h0 = rn_bf16(x0), h1 = rn_bf16(x1);
                 hw[q] = (uint32_t)bf16_bits(h0) | ((uint32_t)bf16_bits(h1) << 16);
                 lw[q] = (uint32_t)bf16_bits(rn_bf16(x0 - h0)) | ((uint32_t)bf16_bits(rn_bf16(x1 - h1)) << 16);
             }
-            reinterpret_cast<uint4*>(hi)[g] = uint4{hw[0], hw[1], hw[2], hw[3]};
-            reinterpret_cast<uint4*>(lo)[g] = uint4{lw[0], lw[1], lw[2], lw[3]};
+            hi[j] = uint4{hw[0], hw[1], hw[2], hw[3]};
+            lo[j] = uint4{lw[0], lw[1], lw[2], lw[3]};
         }
-        if (lane == 0) expo[s] = -sc;
+        if (t == 0) expo[s] = -sc;
+        __syncthreads();  // the next block rewrites the tile and s_m
     }
 }
 
 void launch_to_bf16x2(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, uint16_t* out,
-                      int32_t* expo, const int32_t* done, hipStream_t s) {
-    const int grid = grid_for(cap, 4, 8192);
+                      int32_t* expo, const int32_t* done, hipStream_t s, int max_wg) {
+    const int grid = grid_for(cap, 1, max_wg);
     switch (b) {
         case 32: hipLaunchKernelGGL((k_to_bf16x2<32>), dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, expo, done); break;
         case 64: hipLaunchKernelGGL((k_to_bf16x2<64>), dim3(grid), dim3(256), 0, s, nslot, cap, brow, val, out, expo, done); break;

@@ -217,9 +217,10 @@ void set_ring_per_cu(int b, int per_cu);
 void launch_gemm_batch(int b, int low, const GemmArgs* descs_dev, int nsys, int64_t* out_off, int64_t* pair_off,
                        int32_t* counters, int num_cu, hipStream_t s);
 // split-BF16 copies of the live blocks: x = 2^e (hi + lo + err), max |x| 2^-e
-// in [1, 2), hi = RN_bf16, lo = RN_bf16(x 2^-e - hi); row-major per slot
+// in [1, 2), hi = RN_bf16, lo = RN_bf16(x 2^-e - hi); row-major per slot;
+// one workgroup per block, at most max_wg workgroups
 void launch_to_bf16x2(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, uint16_t* out,
-                      int32_t* expo, const int32_t* done, hipStream_t s);
+                      int32_t* expo, const int32_t* done, hipStream_t s, int max_wg = 8192);
 // FP32 copies; swz = 1: rows rotated for the ring kernel (leaf 32 and 64), 0: the block's own layout
 void launch_to_f32(int b, const int32_t* nslot, int64_t cap, const int32_t* brow, const double* val, float* out,
                    int swz, const int32_t* done, hipStream_t s);

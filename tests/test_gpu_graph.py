@@ -2,8 +2,9 @@
 replayed as one HIP graph) against the oracle and against the host-driven
 loop: an FP64 graph run takes the oracle's decisions at every step and
 ends within 1e-12 of its result (each of Algorithms 5, 4 and 1); with the
-FP32 tier each step is checked against the oracle from the GPU's own
-iterate.  Same kernels and decisions as the host loop, so results and every
+FP32 and split-BF16 tiers each step is checked against the oracle from the
+GPU's own iterate (the split-BF16 copies are made on a side stream, forked
+and joined inside the captured step).  Same kernels and decisions as the host loop, so results and every
 per-iteration record are identical bit for bit.  The graph is replayed many
 times within one run and the run is repeated with eager host-loop work in
 between."""
@@ -50,7 +51,7 @@ def same(r1, r2):
 
 @pytest.mark.parametrize("case,variant,precision", [
     ("chain", "hybrid", "fp64"), ("chain", "spamm", "fp64"), ("chain", "truncmul", "fp64"),
-    ("sys3d", "hybrid", "fp64"), ("sys3d", "hybrid", "fp32")])
+    ("sys3d", "hybrid", "fp64"), ("sys3d", "hybrid", "fp32"), ("sys3d", "hybrid", "bf16x3")])
 def test_graph_loop_matches_host_loop(case, variant, precision):
     Fm, n_occ, taus, homo, lumo = system(case)
     F = P.BlockSparse.from_host(Fm)
