@@ -273,10 +273,10 @@ typedef struct sp2_iter_log {
  * first), the graph is captured on a stream kept per host thread and device
  * (created on first use, never destroyed), and the stream is synchronised
  * once per graph_steps iterations.  With the split-BF16 tier (precision 2)
- * each iteration forks the BF16 copies of X~_i onto a second kept stream
- * (same lifetime, default priority) beside the threshold sweeps and joins
- * it back before the leaf products, in both loops; the call's work is
- * complete when `stream` is.
+ * the host-driven loop forks the BF16 copies of X~_i onto a second kept
+ * stream (same lifetime, default priority) beside the threshold sweeps and
+ * joins it back before the leaf products; the graph keeps them on its one
+ * stream.  Either way the call's work is complete when `stream` is.
  */
 size_t purify_sp2_workspace_bytes(int32_t nb, int32_t b, int32_t N, int64_t cap_blocks, int64_t max_pairs,
                                   int32_t tape_steps, int32_t precision);

@@ -1034,8 +1034,12 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     } guard{ev};
     for (int q = 0; q < 8; ++q) HIP_TRY(hipEventCreate(&ev[q]));
     for (int q = 8; q < 10; ++q) HIP_TRY(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
+    // (host-driven loop only: on this ROCm a graph captured with a fork and
+    // a join was seen to keep the device memory of the buffers it had used
+    // unavailable after they were freed, so a captured step stays on one
+    // stream)
     hipStream_t side = nullptr;
-    if (p->precision == 2) HIP_TRY(kept_stream(1, &side));
+    if (p->precision == 2 && p->graph_steps <= 0) HIP_TRY(kept_stream(1, &side));
     // the side copy runs with one workgroup per CU, leaving the rest of each
     // CU to the sweeps' kernels beside it (more workgroups made the step
     // slower at n = 16384 and 65536)
@@ -1118,9 +1122,10 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
     auto enqueue_step = [&](const MatView& xv, const MatView& nv, int par, const int32_t* done, hipEvent_t* evs,
                             hipStream_t st) -> int {
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
-        // split-BF16 tier: the copies of X~_i (an HBM-bound pass) run on the
-        // side stream beside the occupancy pass and the two sweeps, which
-        // read only the block pattern and norms; joined before the products
+        // split-BF16 tier, host-driven loop: the copies of X~_i (an HBM-bound
+        // pass) run on the side stream beside the occupancy pass and the two
+        // sweeps, which read only the block pattern and norms; joined before
+        // the products
         if (side) {
             HIP_TRY(hipEventRecord(ev[8], st));
             HIP_TRY(hipStreamWaitEvent(side, ev[8], 0));
@@ -1146,7 +1151,11 @@ static int purify_run(const spamm_bsm* F, const sp2_params* p, spamm_bsm* D, sp2
             else
                 run_sweep(xv, xv, 1, p->tau, p->N, &w.ctl->budget, 0.0, 1, &w.ctl->tau, c_low, w.bound2,
                           &w.ctl->sidx, &w.ctl->sigma, w.sw, done, st, &occ);
-            if (!side && !f32_fused) launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, st);
+            if (p->precision == 2 && !side)
+                launch_to_bf16x2(b, xv.nslot, xv.cap, xv.brow, xv.val, reinterpret_cast<uint16_t*>(w.x32), w.xexp,
+                                 done, st);
+            else if (p->precision == 1 && !f32_fused)
+                launch_to_f32(b, xv.nslot, xv.cap, xv.brow, xv.val, w.x32, 1, done, st);
         }
         if (side) HIP_TRY(hipStreamWaitEvent(st, ev[9], 0));
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));

@@ -3,8 +3,8 @@ replayed as one HIP graph) against the oracle and against the host-driven
 loop: an FP64 graph run takes the oracle's decisions at every step and
 ends within 1e-12 of its result (each of Algorithms 5, 4 and 1); with the
 FP32 and split-BF16 tiers each step is checked against the oracle from the
-GPU's own iterate (the split-BF16 copies are made on a side stream, forked
-and joined inside the captured step).  Same kernels and decisions as the host loop, so results and every
+GPU's own iterate (the host loop makes the split-BF16 copies on a side
+stream beside the sweeps, the graph on its one stream).  Same kernels and decisions as the host loop, so results and every
 per-iteration record are identical bit for bit.  The graph is replayed many
 times within one run and the run is repeated with eager host-loop work in
 between."""

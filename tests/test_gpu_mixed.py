@@ -145,3 +145,30 @@ def test_purify_tier_teacher_forced(tier):
     assert low_total > 0
     Dg = to_oracle(res.D).to_dense()
     assert np.linalg.norm(Dg - Dref) < 1e-6
+
+
+def test_bf16_side_stream_releases_memory():
+    """The host-driven split-BF16 loop copies X~_i on a second stream beside
+    the sweeps: repeated calls give identical results, and the device memory
+    of their freed workspaces and outputs comes back (free memory after the
+    fourth call equals that after the first, allocator cache emptied)."""
+    n, b = 4096, 64
+    Fm = synth.sys3d(n, 13, b)
+    w = np.linalg.eigvalsh(oracle.BSM.of(Fm).to_dense())
+    taus = synth.tau_log(32)
+    G = P.BlockSparse.from_host(Fm)
+
+    def run():
+        res = P.purify(G, n // 2, 1e-6, taus, homo=w[n // 2 - 1], lumo=w[n // 2], precision="bf16x3")
+        out = res.D.live()[2].copy(), [lg["npairs_low"] for lg in res.logs]
+        del res
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return out, torch.cuda.mem_get_info()[0]
+
+    (v1, l1), free1 = run()
+    for _ in range(3):
+        (v, lo), free = run()
+        assert np.array_equal(v.view(np.uint64), v1.view(np.uint64)) and lo == l1
+    assert sum(l1) > 0
+    assert abs(free - free1) <= 8 << 20, (free1, free)
