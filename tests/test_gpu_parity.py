@@ -120,6 +120,29 @@ def test_norms_nan_block():
 # K2 sweep (Algorithm 3) and selection
 # ---------------------------------------------------------------------------
 
+@pytest.mark.parametrize("N", [1, 64, 65, 1024])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sweep_bitwise_candidate_counts(N, mode):
+    """The shortest and the longest candidate list (1 and 1024), and both
+    sides of the cube pass's switch from one thread per candidate (N <= 64)
+    to eight per candidate in slices of 32 (N = 65: a ragged last slice);
+    Algorithm 3 alone (mode 0) and with the precision tier's leaf values
+    (mode 1: p below tau0, c_low p from tau0 up to the candidate): the
+    whole bound vector bitwise and the selection."""
+    X = sym_x(1500, 32, 2)                         # nb = 47
+    tl = np.array([1e-6]) if N == 1 else synth.tau_log(N, -20.0)
+    M = P.BlockSparse.from_host(X)
+    P.build_norms(M)
+    kw = dict(mode=1, tau0=1e-9, c_low=0.25) if mode else {}
+    obound = oracle.cse_tree(X, X, tl, **kw)
+    for budget in [obound[N // 3] * 1.0000001, 1e-12, 1e-30]:
+        bound, idx, tau = P.sweep_tau(M, M, tl, budget, b_transposed=True, **kw)
+        gb = bound.cpu().numpy()
+        assert np.array_equal(gb.view(np.uint64), obound.view(np.uint64))
+        oi, ot = oracle.select(obound, tl, budget)
+        assert int(idx.item()) == oi and float(tau.item()) == ot
+
+
 @pytest.mark.parametrize("n,b,seed,taus", [
     (1024, 32, 1, "paper"),     # chain-sized, 350 candidates
     (1500, 32, 2, "log"),       # nb = 47, ragged tail
