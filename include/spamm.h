@@ -425,7 +425,7 @@ int spamm_get_small_path(void);
 
 /*
  * Leaf-size and schedule autotuner (not in the paper).  For each leaf size
- * (32, 64, 128; 32 and 64 with the FP32 tier) F is re-blocked and the first
+ * (32, 64, 128; 32 and 64 with a precision tier) F is re-blocked and the first
  * trial_steps steps of its purification with parameters p are timed (the
  * delta schedule is the one of the full run); the mean time of the steps
  * after the first decides the leaf size.  Then every workgroups-per-CU

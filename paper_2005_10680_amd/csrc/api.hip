@@ -1993,7 +1993,7 @@ size_t purify_sp2_autotune_workspace_bytes(int64_t n, int32_t N, int32_t precisi
     if (n < 1 || N < 1) return 0;
     size_t m = 0;
     for (int b : {32, 64, 128}) {
-        if (precision == 1 && b > 64) continue;
+        if (precision != 0 && b > 64) continue;  // the precision tiers run at leaf 32 and 64
         m = std::max(m, trial_size(n, b, N, precision).bytes);
     }
     return m;
@@ -2046,7 +2046,7 @@ int purify_sp2_autotune(const spamm_bsm* F, const sp2_params* p, int32_t trial_s
     const int leaves[3] = {32, 64, 128};
     for (int q = 0; q < 3; ++q) {
         ms_per_step[q] = -1.0f;
-        if (p->precision == 1 && leaves[q] > 64) continue;
+        if (p->precision != 0 && leaves[q] > 64) continue;  // tiers: leaf 32 and 64 only
         float st = 0.0f, gm = 0.0f;
         rc = trial(leaves[q], &st, &gm);
         if (rc) return rc;

@@ -89,3 +89,26 @@ def test_autotune_picks_a_working_leaf():
     finally:
         for bb, v in saved.items():
             P.set_gemm_schedule(bb, v)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_autotune_precision_tiers_skip_leaf_128(precision):
+    """The precision tiers run at leaf 32 and 64 only: their trials leave
+    leaf 128 out (no time reported for it) and the chosen leaf purifies in
+    that tier."""
+    n = 2048
+    Fm = synth.sys3d(n, 9, 32)
+    w = np.linalg.eigvalsh(oracle.BSM.of(Fm).to_dense())
+    F = P.BlockSparse.from_host(Fm)
+    taus = synth.tau_log(32)
+    saved = {b: P.get_gemm_schedule(b) for b in (32, 64, 128)}
+    try:
+        b, pc, ms = P.autotune(F, n // 2, 1e-6, taus, homo=w[n // 2 - 1], lumo=w[n // 2], precision=precision,
+                               trial_steps=4)
+        assert set(ms) == {32, 64} and all(v > 0 for v in ms.values())
+        assert b == min(ms, key=ms.get) and 1 <= pc <= saved[b]
+        r = P.purify(P.reblock(F, b), n // 2, 1e-6, taus, homo=w[n // 2 - 1], lumo=w[n // 2], precision=precision)
+        assert r.status >= 0 and sum(lg["npairs_low"] for lg in r.logs) > 0
+    finally:
+        for bb, v in saved.items():
+            P.set_gemm_schedule(bb, v)
