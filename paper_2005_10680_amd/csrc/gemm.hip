@@ -440,8 +440,12 @@ SPAMM_DEV void dma_bf16_chunk(const char* __restrict__ blk, int chunk, char* lds
         const int part = piece / PPP, pp = piece % PPP;
         const int pos = pp * 64 + lane;
         const int row = pos >> 2, kg = ((pos & 3) - bf16_rot(row)) & 3;
-        const char* src = blk + (size_t)part * B * B * 2 + (size_t)row * B * 2 + chunk * 64 + kg * 16;
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+        // wave-uniform base plus the lane's 32-bit offset inside the part:
+        // one VGPR per lane instead of a 64-bit address per piece, which
+        // keeps the split-BF16 kernels within their registers (no spills)
+        const char* base = blk + (size_t)part * B * B * 2 + chunk * 64;
+        const uint32_t lofs = (uint32_t)(row * B * 2 + kg * 16);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(base + lofs),
                                          (__attribute__((address_space(3))) void*)(lds_dst + piece * 1024), 16, 0,
                                          0);
     }
@@ -848,7 +852,13 @@ SPAMM_DEV void ring_epilogue(RingCtx<B, LOWT>& cx, const GemmArgs& d, int i, int
     constexpr int PC = 16;  // epilogue columns per pass
     static_assert(PC * R::LDT * 8 <= R::STAGE && B % PC == 0, "epilogue tile fits one ring slot");
     double* ldsd = reinterpret_cast<double*>(RingSlot<B, R::NS - 1>::get());
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the thread index passes through an empty asm so that the epilogue's
+    // per-lane addresses are formed here, per output, rather than hoisted
+    // out of the persistent loop: the tier kernels then need no scratch
+    // (a spilled address's reload waits for every copy in flight)
+    int tid = threadIdx.x;
+    if constexpr (LOWT != 0) asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int sh = d.map_out[(size_t)i * d.nb + j];
     const int sht = (d.sym && i != j) ? d.map_out[(size_t)j * d.nb + i] : -1;
