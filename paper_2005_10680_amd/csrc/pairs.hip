@@ -40,6 +40,36 @@ void launch_occupancy(const MatView& M, int mode, uint32_t* bits, int nw, uint8_
 }
 
 
+// Eight lanes per output (i, j): lane g of the group walks the contiguous
+// bitmap words [g nw / 8, (g + 1) nw / 8) of the candidate inner indices, so
+// an output's map and norm loads run on eight lanes at once rather than one
+// after another; the lanes hold ascending k ranges in lane order.
+constexpr int kKeptG = 8;
+
+// kept pairs (and low-tier pairs) of output (i, j) in this lane's words
+SPAMM_DEV void kept_lane_count(int i, int j, int w0, int w1, int nb, int nw, const uint32_t* __restrict__ bitsA,
+                               const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
+                               const double* __restrict__ normA, const int32_t* __restrict__ mapB,
+                               const double* __restrict__ normB, int btrans, double tau, double sigma,
+                               double norm_min, int& c, int& cl) {
+    c = 0;
+    cl = 0;
+    for (int w = w0; w < w1; ++w) {
+        uint32_t m = bitsA[(size_t)i * nw + w] & bitsB[(size_t)j * nw + w];
+        while (m) {
+            const int k = w * 32 + __ffs(m) - 1;
+            m &= m - 1;
+            const int sa = mapA[(size_t)i * nb + k];
+            const int sb = btrans ? mapB[(size_t)j * nb + k] : mapB[(size_t)k * nb + j];
+            if (sa < 0 || sb < 0) continue;
+            const double p = normA[sa] * normB[sb];
+            if (!(p >= tau)) continue;
+            ++c;
+            if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) ++cl;
+        }
+    }
+}
+
 __global__ void k_kept_count(int nb, int P, int nw, const uint32_t* __restrict__ bitsA,
                              const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
                              const double* __restrict__ normA, const int32_t* __restrict__ mapB,
@@ -51,20 +81,27 @@ __global__ void k_kept_count(int nb, int P, int nw, const uint32_t* __restrict__
     const double tau = *tau_p;
     const double sigma = sigma_p ? *sigma_p : 0.0;
     const int64_t PP = (int64_t)P * P;
-    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < PP; z += (int64_t)gridDim.x * blockDim.x) {
+    const int g = threadIdx.x % kKeptG;
+    const int w0 = g * nw / kKeptG, w1 = (g + 1) * nw / kKeptG;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kKeptG);
+    // z is uniform over the eight lanes of a group (blockDim.x is a multiple of 8)
+    for (int64_t z = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kKeptG; z < PP; z += groups) {
         uint32_t i, j;
         demorton2((uint32_t)z, i, j);
         int c = 0, cl = 0;
-        if ((int)i < nb && (int)j < nb && !(sym && i > j)) {
-            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                          [&](int, int sa, int sb, double p) {
-                              ++c;
-                              if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) ++cl;
-                          });
+        if ((int)i < nb && (int)j < nb && !(sym && i > j))
+            kept_lane_count((int)i, (int)j, w0, w1, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
+                            sigma, norm_min, c, cl);
+#pragma unroll
+        for (int d = 1; d < kKeptG; d <<= 1) {
+            c += __shfl_xor(c, d, kKeptG);
+            cl += __shfl_xor(cl, d, kKeptG);
         }
-        cnt[z] = c;
-        cnt_flag[z] = c > 0 ? 1 : 0;
-        if (cnt_low) cnt_low[z] = cl;
+        if (g == 0) {
+            cnt[z] = c;
+            cnt_flag[z] = c > 0 ? 1 : 0;
+            if (cnt_low) cnt_low[z] = cl;
+        }
     }
 }
 
@@ -73,13 +110,16 @@ void launch_kept_count(int nb, int P, int nw, const uint32_t* bitsA, const uint3
                        const double* tau, const double* sigma, double norm_min, int32_t* cnt, int32_t* cnt_flag,
                        int32_t* cnt_low, const int32_t* done, hipStream_t s) {
     int64_t PP = (int64_t)P * P;
-    hipLaunchKernelGGL(k_kept_count, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB, mapA,
-                       normA, mapB, normB, btrans, sym, tau, sigma, norm_min, cnt, cnt_flag, cnt_low, done);
+    hipLaunchKernelGGL(k_kept_count, dim3(grid_for(PP * kKeptG, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB,
+                       mapA, normA, mapB, normB, btrans, sym, tau, sigma, norm_min, cnt, cnt_flag, cnt_low, done);
 }
 
 // Pairs of one output: low-precision pairs (tau <= p < sigma, both block
 // norms >= norm_min) first, then the FP64 ones, each group in ascending k.
-// Without tiers (sigma null) every pair is FP64.
+// Without tiers (sigma null) every pair is FP64.  Each lane of the output's
+// group counts its words' pairs of both kinds, the group's exclusive scans
+// (in lane order, i.e. ascending k) give the lane's first position in each
+// part, and a second walk writes them.
 __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ bitsA,
                             const uint32_t* __restrict__ bitsB, const int32_t* __restrict__ mapA,
                             const double* __restrict__ normA, const int32_t* __restrict__ mapB,
@@ -92,6 +132,7 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
                             int32_t* __restrict__ ovf, const int32_t* __restrict__ done) {
     if (done && *done) return;
     const double tau = *tau_p;
+    // without tiers no pair is low (sigma 0: p < 0 never holds for a kept p >= tau >= 0)
     const double sigma = sigma_p ? *sigma_p : 0.0;
     const int64_t PP = (int64_t)P * P;
     const int64_t npairs = *npairs_p, nout = *nout_p;
@@ -102,38 +143,56 @@ __global__ void k_kept_fill(int nb, int P, int nw, const uint32_t* __restrict__ 
     }
     // an overflowing list is reported, not filled (its 32-bit offsets may have wrapped)
     if (npairs > cap_pairs) return;
-    for (int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; z < PP; z += (int64_t)gridDim.x * blockDim.x) {
-        if (cnt[z] == 0) continue;
+    const int g = threadIdx.x % kKeptG;
+    const int w0 = g * nw / kKeptG, w1 = (g + 1) * nw / kKeptG;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kKeptG);
+    for (int64_t z = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kKeptG; z < PP; z += groups) {
+        if (cnt[z] == 0) continue;  // group-uniform
         uint32_t i, j;
         demorton2((uint32_t)z, i, j);
-        int64_t o = oidx[z];
+        const int64_t o = oidx[z];
         if (o >= cap_out) continue;
-        oi[o] = (int32_t)i;
-        oj[o] = (int32_t)j;
-        optr[o] = off[z];
-        int64_t w = off[z];
-        if (sigma_p) {
-            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                          [&](int, int sa, int sb, double p) {
-                              if (p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min) {
-                                  if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
-                                  ++w;
-                              }
-                          });
-            if (olow) olow[o] = (int32_t)(w - off[z]);
-            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                          [&](int, int sa, int sb, double p) {
-                              if (!(p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min)) {
-                                  if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
-                                  ++w;
-                              }
-                          });
-        } else {
-            for_each_kept((int)i, (int)j, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau,
-                          [&](int, int sa, int sb, double) {
-                              if (w < cap_pairs) pairs[w] = make_int2(sa, sb);
-                              ++w;
-                          });
+        int c = 0, cl = 0;
+        kept_lane_count((int)i, (int)j, w0, w1, nb, nw, bitsA, bitsB, mapA, normA, mapB, normB, btrans, tau, sigma,
+                        norm_min, c, cl);
+        const int ch = c - cl;
+        // inclusive scans over the group's lanes, then exclusive
+        int sl = cl, sh = ch;
+#pragma unroll
+        for (int d = 1; d < kKeptG; d <<= 1) {
+            const int ul = __shfl_up(sl, d, kKeptG), uh = __shfl_up(sh, d, kKeptG);
+            if (g >= d) {
+                sl += ul;
+                sh += uh;
+            }
+        }
+        const int low_tot = __shfl(sl, kKeptG - 1, kKeptG);
+        const int64_t base = off[z];
+        int64_t wl = base + (sl - cl);             // this lane's first low-tier pair
+        int64_t wh = base + low_tot + (sh - ch);   // this lane's first FP64 pair
+        if (g == 0) {
+            oi[o] = (int32_t)i;
+            oj[o] = (int32_t)j;
+            optr[o] = (int32_t)base;
+            if (sigma_p && olow) olow[o] = low_tot;
+        }
+        if (c == 0) continue;
+        for (int w = w0; w < w1; ++w) {
+            uint32_t m = bitsA[(size_t)i * nw + w] & bitsB[(size_t)j * nw + w];
+            while (m) {
+                const int k = w * 32 + __ffs(m) - 1;
+                m &= m - 1;
+                const int sa = mapA[(size_t)i * nb + k];
+                const int sb = btrans ? mapB[(size_t)j * nb + k] : mapB[(size_t)k * nb + j];
+                if (sa < 0 || sb < 0) continue;
+                const double p = normA[sa] * normB[sb];
+                if (!(p >= tau)) continue;
+                const bool low = p < sigma && normA[sa] >= norm_min && normB[sb] >= norm_min;
+                const int64_t wp = low ? wl : wh;
+                if (wp < cap_pairs) pairs[wp] = make_int2(sa, sb);
+                if (low) ++wl;
+                else ++wh;
+            }
         }
     }
 }
@@ -145,9 +204,9 @@ void launch_kept_fill(int nb, int P, int nw, const uint32_t* bitsA, const uint32
                       int64_t cap_out, int32_t* oi, int32_t* oj, int32_t* optr, int2* pairs, int32_t* olow,
                       int32_t* ovf, const int32_t* done, hipStream_t s) {
     int64_t PP = (int64_t)P * P;
-    hipLaunchKernelGGL(k_kept_fill, dim3(grid_for(PP, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB, mapA,
-                       normA, mapB, normB, btrans, tau, sigma, norm_min, cnt, off, oidx, npairs, nout, cap_pairs, cap_out, oi,
-                       oj, optr, pairs, olow, ovf, done);
+    hipLaunchKernelGGL(k_kept_fill, dim3(grid_for(PP * kKeptG, 256, 8192)), dim3(256), 0, s, nb, P, nw, bitsA, bitsB,
+                       mapA, normA, mapB, normB, btrans, tau, sigma, norm_min, cnt, off, oidx, npairs, nout, cap_pairs,
+                       cap_out, oi, oj, optr, pairs, olow, ovf, done);
 }
 
 // Output pattern: block (r, c) of the result exists when the product has a
