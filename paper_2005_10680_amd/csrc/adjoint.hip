@@ -84,32 +84,37 @@ __global__ void k_adj_place(MatView X, const int32_t* __restrict__ flag, const i
     }
 }
 
-// Visit the pairs of output (i, k): first kind, then second kind, each in
-// ascending j.  f(kind, slot_first_operand, slot_second_operand).
+// Eight lanes per output, as the forward kept-pair passes: lane g walks the
+// contiguous bitmap words [g nw / 8, (g + 1) nw / 8) of both kinds, so the
+// lanes hold ascending j ranges in lane order.
+constexpr int kAdjG = 8;
+
+// The pairs of output (i, k) in this lane's words: first kind, then second
+// kind, each in ascending j; f(kind, slot of the first operand, slot of the
+// second operand).
 template <typename Fn>
-SPAMM_DEV void adj_pairs(int i, int k, int nb, int nw, const uint32_t* bitsX, const uint32_t* bitsG,
-                         const int32_t* mapX, const double* normX, const int32_t* mapG, double tau, Fn&& f) {
+SPAMM_DEV void adj_lane_pairs(int i, int k, int w0, int w1, int nb, int nw, const uint32_t* bitsX,
+                              const uint32_t* bitsG, const int32_t* mapX, const double* normX, const int32_t* mapG,
+                              double tau, Fn&& f) {
     const int sik = mapX[(size_t)i * nb + k];
     if (sik < 0) return;
     const double nik = normX[sik];
-    for (int w = 0; w < nw; ++w) {
+    for (int w = w0; w < w1; ++w) {
         uint32_t m = bitsX[(size_t)k * nw + w] & bitsG[(size_t)i * nw + w];
         while (m) {
-            const int t = __ffs(m) - 1;
+            const int j = w * 32 + __ffs(m) - 1;
             m &= m - 1;
-            const int j = w * 32 + t;
             const int skj = mapX[(size_t)k * nb + j];
             const int sij = mapG[(size_t)i * nb + j];
             if (skj < 0 || sij < 0) continue;
             if (nik * normX[skj] >= tau) f(0, sij, skj);
         }
     }
-    for (int w = 0; w < nw; ++w) {
+    for (int w = w0; w < w1; ++w) {
         uint32_t m = bitsX[(size_t)i * nw + w] & bitsG[(size_t)k * nw + w];
         while (m) {
-            const int t = __ffs(m) - 1;
+            const int j = w * 32 + __ffs(m) - 1;
             m &= m - 1;
-            const int j = w * 32 + t;
             const int sij = mapX[(size_t)i * nb + j];
             const int skj = mapG[(size_t)k * nb + j];
             if (sij < 0 || skj < 0) continue;
@@ -124,10 +129,16 @@ __global__ void k_adj_count(const int64_t* __restrict__ nout_p, const int32_t* _
                             const double* __restrict__ normX, const int32_t* __restrict__ mapG, double tau,
                             int32_t* __restrict__ cnt) {
     const int64_t nout = *nout_p;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nout; o += (int64_t)gridDim.x * blockDim.x) {
+    const int g = threadIdx.x % kAdjG;
+    const int w0 = g * nw / kAdjG, w1 = (g + 1) * nw / kAdjG;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kAdjG);
+    for (int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAdjG; o < nout; o += groups) {
         int c = 0;
-        adj_pairs(oi[o], oj[o], nb, nw, bitsX, bitsG, mapX, normX, mapG, tau, [&](int, int, int) { ++c; });
-        cnt[o] = c;
+        adj_lane_pairs(oi[o], oj[o], w0, w1, nb, nw, bitsX, bitsG, mapX, normX, mapG, tau,
+                       [&](int, int, int) { ++c; });
+#pragma unroll
+        for (int d = 1; d < kAdjG; d <<= 1) c += __shfl_xor(c, d, kAdjG);
+        if (g == 0) cnt[o] = c;
     }
 }
 
@@ -141,6 +152,9 @@ __global__ void k_adj_fin(const int64_t* __restrict__ nout_p, const int64_t* __r
     }
 }
 
+// the pairs of output o: first kind (ascending j), then second kind
+// (ascending j, first slot stored as its one's complement); each lane's
+// first position in each part from scans over the group's lanes
 __global__ void k_adj_fill(const int64_t* __restrict__ nout_p, const int32_t* __restrict__ oi,
                            const int32_t* __restrict__ oj, int nb, int nw, const uint32_t* __restrict__ bitsX,
                            const uint32_t* __restrict__ bitsG, const int32_t* __restrict__ mapX,
@@ -149,11 +163,34 @@ __global__ void k_adj_fill(const int64_t* __restrict__ nout_p, const int32_t* __
                            const int32_t* __restrict__ ovf) {
     if (*ovf) return;
     const int64_t nout = *nout_p;
-    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nout; o += (int64_t)gridDim.x * blockDim.x) {
-        int64_t p = optr[o];
-        adj_pairs(oi[o], oj[o], nb, nw, bitsX, bitsG, mapX, normX, mapG, tau, [&](int kind, int s1, int s2) {
-            if (p < cap_pairs) pairs[p] = kind == 0 ? make_int2(s1, s2) : make_int2(~s1, s2);
-            ++p;
+    const int g = threadIdx.x % kAdjG;
+    const int w0 = g * nw / kAdjG, w1 = (g + 1) * nw / kAdjG;
+    const int64_t groups = (int64_t)gridDim.x * (blockDim.x / kAdjG);
+    for (int64_t o = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kAdjG; o < nout; o += groups) {
+        const int i = oi[o], k = oj[o];
+        int c0 = 0, c1 = 0;
+        adj_lane_pairs(i, k, w0, w1, nb, nw, bitsX, bitsG, mapX, normX, mapG, tau, [&](int kind, int, int) {
+            if (kind == 0) ++c0;
+            else ++c1;
+        });
+        int s0 = c0, s1 = c1;
+#pragma unroll
+        for (int d = 1; d < kAdjG; d <<= 1) {
+            const int u0 = __shfl_up(s0, d, kAdjG), u1 = __shfl_up(s1, d, kAdjG);
+            if (g >= d) {
+                s0 += u0;
+                s1 += u1;
+            }
+        }
+        const int tot0 = __shfl(s0, kAdjG - 1, kAdjG);
+        const int64_t base = optr[o];
+        int64_t p0 = base + (s0 - c0), p1 = base + tot0 + (s1 - c1);
+        if (c0 + c1 == 0) continue;
+        adj_lane_pairs(i, k, w0, w1, nb, nw, bitsX, bitsG, mapX, normX, mapG, tau, [&](int kind, int a, int b) {
+            const int64_t p = kind == 0 ? p0 : p1;
+            if (p < cap_pairs) pairs[p] = kind == 0 ? make_int2(a, b) : make_int2(~a, b);
+            if (kind == 0) ++p0;
+            else ++p1;
         });
     }
 }
@@ -170,7 +207,7 @@ void launch_adj_pairs(int nb, int nw, int64_t cap_out, const int64_t* nout, cons
                       const uint32_t* bitsX, const uint32_t* bitsG, const int32_t* mapX, const double* normX,
                       const int32_t* mapG, double tau, int32_t* cnt, int32_t* optr, int64_t* npairs,
                       int64_t cap_pairs, int2* pairs, int32_t* ovf, void* scan_tmp, hipStream_t s) {
-    const int grid = grid_for(cap_out, 256, 4096);
+    const int grid = grid_for(cap_out * kAdjG, 256, 8192);
     hipLaunchKernelGGL(k_adj_count, dim3(grid), dim3(256), 0, s, nout, oi, oj, nb, nw, bitsX, bitsG, mapX, normX,
                        mapG, tau, cnt);
     scan_i32(cnt, optr, cap_out, nout, npairs, scan_tmp, s);
