@@ -449,9 +449,26 @@ __global__ __launch_bounds__(kTopThreads) void k_levels_top(const uint32_t* __re
         }
         if (tid == 0) pstart[np] = n;
         __syncthreads();
-        for (int idx = tid; idx < np * N; idx += kTopThreads) {
-            const int p = idx / N, m = idx - p * N;
-            pv[(size_t)p * N + m] = node_eval(keys[cur], cv, pstart[p], pstart[p + 1], m, N);
+        // four nodes per thread and round, their child loads all issued
+        // before the first result is stored (the stores may alias the
+        // children's values as far as the compiler knows)
+        constexpr int U = 4;
+        const int tot = np * N;
+        for (int idx0 = tid; idx0 < tot; idx0 += U * kTopThreads) {
+            double r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = idx0 + u * kTopThreads;
+                if (idx < tot) {
+                    const int p = idx / N, m = idx - p * N;
+                    r[u] = node_eval(keys[cur], cv, pstart[p], pstart[p + 1], m, N);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = idx0 + u * kTopThreads;
+                if (idx < tot) pv[idx] = r[u];  // idx = p N + m
+            }
         }
         __syncthreads();
         cur = 1 - cur;
